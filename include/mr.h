@@ -1,0 +1,137 @@
+/*
+ * mr.h -- C ABI of libmrecon: grayscale morphological reconstruction by
+ * dilation and fill-holes on one AMD Instinct MI355X (gfx950), run as an
+ * irregular wavefront propagation (IWPP).
+ *
+ * The operations (Table II of the paper):
+ *   Morphological Reconstruction -- flood-fill of a marker image limited by a
+ *     mask image, with 4- or 8-connectivity. Here: R = the least image J with
+ *     J >= min(marker, mask) that is stable under
+ *     J(p) <- min(mask(p), max of J over p and its G-neighbours).
+ *   FillHoles -- flood-fill of the background from selected points. Here: the
+ *     flood starts from every image-border pixel and runs on the bitwise
+ *     complement: out = NOT R(Jb, NOT img), Jb = NOT img on the border and the
+ *     type's minimum elsewhere; `conn` is the connectivity of the background
+ *     flood. Images of height or width <= 2 are all border: out = img.
+ * How (Algorithm 1, Sec. III-B on the GPU queue and atomics, Sec. V-C.2 on the
+ * regular-then-irregular hybrid): tile rounds propagate inside 64 x 64
+ * register tiles until a local fixed point; tiles whose halo changed are
+ * revisited; after `sweep_rounds` rounds the pixels that can still raise a
+ * neighbour are compacted into a device frontier queue and finished by
+ * persistent workgroups with atomic max updates.
+ *
+ * Conventions for every entry point:
+ *  - Images are row-major, element (y, x) at index y * pitch + x; pitch is in
+ *    elements, pitch >= W, and 0 means W; H * pitch must be below 2^32.
+ *    Pixel types: MR_U8 (uint8) and MR_I32 (int32, full signed range).
+ *    Image pointers are aligned to the pixel size. For MR_U8 the working
+ *    image is updated with 32-bit compare-and-swap on the aligned words that
+ *    hold its pixels, so the allocation must cover those whole words and no
+ *    other agent may write bytes that share a word with the image while a
+ *    call runs.
+ *  - Image, mask and workspace pointers are DEVICE pointers owned by the
+ *    caller. The library never allocates device memory: all scratch space is
+ *    the caller's workspace, whose size the *_workspace_bytes functions give.
+ *    The workspace must be 256-byte aligned.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream). Calls
+ *    enqueue work and return without waiting for the device, unless stated.
+ *    Faults inside kernels surface at the caller's next synchronization.
+ *  - Arguments are checked on the host before anything is enqueued. Errors
+ *    are negative return codes; mr_last_error() gives a message for the
+ *    calling thread. Nothing is thrown across the ABI.
+ *  - Marker pixels above the mask are clipped to the mask (no error).
+ *  - Two calls that share a workspace must be ordered on one stream.
+ */
+#ifndef MR_H
+#define MR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MR_ABI_VERSION 1
+
+typedef enum { MR_U8 = 1, MR_I32 = 4 } mr_dtype; /* value = bytes per pixel */
+
+enum {
+    MR_OK = 0,
+    MR_EINVAL = -1, /* bad argument */
+    MR_ENOMEM = -2, /* workspace or arena too small */
+    MR_EHIP = -3,   /* HIP runtime error, or a device-side iteration cap hit */
+    MR_EAGAIN = -4  /* serving: the job cannot be admitted now; retry later */
+};
+
+enum { MR_OP_RECON = 0, MR_OP_FILL = 1 };
+
+/* Tuning knobs. A NULL mr_tune* means "use the defaults" (mr_default_tune).
+ * No knob changes the result, only the time it takes. */
+typedef struct {
+    int32_t sweep_rounds;      /* tile rounds before the queue phase (>= 1);
+                                  a negative value runs tile rounds until no
+                                  tile is dirty and skips the queue phase (the
+                                  call then waits for the device between
+                                  rounds) */
+    int32_t max_sweeps;        /* cap on sweep iterations per tile visit
+                                  (1..1024); a capped tile is revisited */
+    int32_t persistent_blocks; /* queue-phase workgroups; 0 = as many as can
+                                  be co-resident on the GPU */
+    int32_t reserved;          /* must be 0 */
+} mr_tune;
+
+/* Work counters of the last call that used a workspace. */
+typedef struct {
+    uint64_t rounds;      /* tile rounds launched */
+    uint64_t tiles;       /* tile visits (64 x 64 register tiles) */
+    uint64_t seeds;       /* frontier entries made by the seed pass */
+    uint64_t pops;        /* frontier entries processed by the queue phase */
+    uint64_t pushes;      /* frontier entries produced by the queue phase */
+    uint64_t cas_retries; /* failed compare-and-swap attempts (u8 updates) */
+    uint64_t overflows;   /* entries that did not fit the device ring and were
+                             handed back to tile rounds (never an error) */
+} mr_counters;
+
+/* Fills *out with the default knobs. */
+void mr_default_tune(mr_tune *out);
+
+/* Workspace bytes needed by one mr_recon_dilate (op = MR_OP_RECON) or
+ * mr_fill_holes (op = MR_OP_FILL) call on an H x W image. Returns 0 for
+ * invalid arguments (see mr_last_error). */
+size_t mr_workspace_bytes(int op, int64_t H, int64_t W, mr_dtype t, int conn,
+                          const mr_tune *tune);
+
+/* Reconstruction by dilation (Table II, Morphological Reconstruction).
+ * marker_inout: device, H x W of type t with the given pitch; on return (in
+ *   stream order) it holds R.
+ * mask: device, same geometry and pitch, read only.
+ * ws / ws_bytes: device workspace of at least mr_workspace_bytes(MR_OP_RECON,
+ *   ...) bytes; its contents on entry do not matter.
+ * Errors: MR_EINVAL (null pointer, H or W < 1, pitch < W, conn not 4 or 8,
+ *   unknown type, misaligned workspace), MR_ENOMEM (ws_bytes too small),
+ *   MR_EHIP (launch failure). */
+int mr_recon_dilate(void *marker_inout, const void *mask, int64_t H, int64_t W, int64_t pitch,
+                    mr_dtype t, int conn, void *ws, size_t ws_bytes, const mr_tune *tune,
+                    void *stream);
+
+/* Fill-holes (Table II, FillHoles): img_inout is replaced by its filled
+ * version. Arguments and errors as for mr_recon_dilate with op MR_OP_FILL. */
+int mr_fill_holes(void *img_inout, int64_t H, int64_t W, int64_t pitch, mr_dtype t, int conn,
+                  void *ws, size_t ws_bytes, const mr_tune *tune, void *stream);
+
+/* Copies the work counters held in a workspace to *out. Waits for `stream`.
+ * Errors: MR_EINVAL (null pointer), MR_EHIP. */
+int mr_read_counters(const void *ws, mr_counters *out, void *stream);
+
+/* Message for the last error returned to the calling thread ("" if none). */
+const char *mr_last_error(void);
+
+/* ABI version of the loaded library (MR_ABI_VERSION it was built with). */
+int mr_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MR_H */

@@ -1,0 +1,304 @@
+// mr_api.hip -- host side of libmrecon: argument checks, workspace layout and
+// the launch sequence behind the C ABI declared in include/mr.h.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "mr_internal.h"
+
+using namespace mr;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(MR_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+uint64_t next_pow2(uint64_t v) {
+    uint64_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// Spin budget of an idle queue wave before it gives up (a watchdog: the
+// queue always drains long before this on a working device).
+constexpr unsigned long long SPIN_CAP = 1ull << 24;
+
+// Where everything lives inside a workspace.
+struct Layout {
+    int64_t n_tiles = 0;
+    uint64_t ring_cap = 0;
+    size_t off_desc = 0, off_flags = 0, off_qflag = 0, off_bitmap = 0, off_ring = 0, off_plane = 0, total = 0;
+    int64_t plane_pitch = 0;
+};
+
+Layout layout_for(int64_t n_tiles, int64_t fill_plane_bytes, int64_t plane_pitch) {
+    Layout L;
+    L.n_tiles = n_tiles;
+    L.ring_cap = next_pow2((uint64_t)n_tiles + 8192);
+    size_t o = align_up(sizeof(Ctrl), 256);
+    L.off_desc = o;
+    o = align_up(o + sizeof(ImgDesc), 256);
+    L.off_flags = o;
+    o = align_up(o + (size_t)n_tiles * 4, 256);
+    L.off_qflag = o;
+    o = align_up(o + (size_t)n_tiles * 4, 256);
+    L.off_bitmap = o;
+    o = align_up(o + (size_t)n_tiles * TS * 8, 256);
+    L.off_ring = o;
+    o = align_up(o + (size_t)L.ring_cap * 4, 256);
+    L.off_plane = o;
+    o = align_up(o + (size_t)fill_plane_bytes, 256);
+    L.total = o;
+    L.plane_pitch = plane_pitch;
+    return L;
+}
+
+int64_t tiles_across(int64_t n) { return (n + TI - 1) / TI; }
+
+bool valid_dtype(int t) { return t == MR_U8 || t == MR_I32; }
+
+int check_tune(const mr_tune *tn) {
+    if (!tn) return MR_OK;
+    if (tn->sweep_rounds == 0) return fail(MR_EINVAL, "tune.sweep_rounds must be >= 1 or negative");
+    if (tn->max_sweeps < 1 || tn->max_sweeps > 1024)
+        return fail(MR_EINVAL, "tune.max_sweeps must be in 1..1024 (got %d)", tn->max_sweeps);
+    if (tn->persistent_blocks < 0)
+        return fail(MR_EINVAL, "tune.persistent_blocks must be >= 0");
+    if (tn->reserved != 0) return fail(MR_EINVAL, "tune.reserved must be 0");
+    return MR_OK;
+}
+
+int check_image(int op, int64_t H, int64_t W, int64_t pitch, int t, int conn) {
+    if (op != MR_OP_RECON && op != MR_OP_FILL) return fail(MR_EINVAL, "unknown op %d", op);
+    if (H < 1 || W < 1) return fail(MR_EINVAL, "H and W must be >= 1 (got %lld x %lld)",
+                                    (long long)H, (long long)W);
+    if (pitch != 0 && pitch < W)
+        return fail(MR_EINVAL, "pitch %lld is smaller than W %lld", (long long)pitch,
+                    (long long)W);
+    if (!valid_dtype(t)) return fail(MR_EINVAL, "unknown pixel type %d", t);
+    if (conn != 4 && conn != 8) return fail(MR_EINVAL, "conn must be 4 or 8 (got %d)", conn);
+    const int64_t nt = tiles_across(H) * tiles_across(W);
+    if (nt >= (1ll << 31) - 1) return fail(MR_EINVAL, "image too large (%lld tiles)", (long long)nt);
+    // kernels address a plane with 32-bit element offsets
+    const int64_t p = pitch ? pitch : W;
+    const int64_t pp = (W + 63) / 64 * 64;
+    if (H * std::max(p, pp) >= (1ll << 32))
+        return fail(MR_EINVAL, "image plane too large: H * pitch must stay below 2^32 elements");
+    return MR_OK;
+}
+
+Layout single_layout(int op, int64_t H, int64_t W, int t) {
+    const int64_t nt = tiles_across(H) * tiles_across(W);
+    int64_t plane = 0, pp = 0;
+    if (op == MR_OP_FILL) {
+        pp = (int64_t)align_up((size_t)W, 64);
+        plane = H * pp * t;
+    }
+    return layout_for(nt, plane, pp);
+}
+
+mr_tune effective_tune(const mr_tune *tn) {
+    mr_tune d;
+    mr_default_tune(&d);
+    return tn ? *tn : d;
+}
+
+// Pinned word the converge mode polls through.
+unsigned long long *host_word() {
+    static thread_local unsigned long long *w = nullptr;
+    if (!w && hipHostMalloc((void **)&w, sizeof *w, hipHostMallocDefault) != hipSuccess)
+        w = nullptr;
+    return w;
+}
+
+// The whole propagation over the images of one launch.
+int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *ws,
+                 const mr_tune &tn, hipStream_t s, bool any_fill) {
+    char *base = (char *)ws;
+    Ctrl *ctrl = (Ctrl *)base;
+    uint32_t *flags = (uint32_t *)(base + L.off_flags);
+    uint32_t *qflag = (uint32_t *)(base + L.off_qflag);
+    uint64_t *bitmap = (uint64_t *)(base + L.off_bitmap);
+    uint32_t *ring = (uint32_t *)(base + L.off_ring);
+    hipError_t e;
+
+    if ((e = launch_clear_ctrl(ctrl, s)) != hipSuccess) return hip_fail(e, "clear");
+    if ((e = launch_clear_u32(flags, L.n_tiles, 0u, s)) != hipSuccess) return hip_fail(e, "clear");
+    if ((e = launch_clear_u32(ring, (int64_t)L.ring_cap, Q_EMPTY, s)) != hipSuccess)
+        return hip_fail(e, "clear");
+
+    uint32_t round = 1;
+    if ((e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, ctrl, round, 1,
+                               tn.max_sweeps, s)) != hipSuccess)
+        return hip_fail(e, "tile round");
+    if (tn.sweep_rounds > 0) {
+        for (round = 2; round <= (uint32_t)tn.sweep_rounds; ++round)
+            if ((e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, ctrl, round, 0,
+                                       tn.max_sweeps, s)) != hipSuccess)
+                return hip_fail(e, "tile round");
+        const uint32_t seed_round = (uint32_t)tn.sweep_rounds + 1;
+        if ((e = launch_store_u64(&ctrl->rounds, (unsigned long long)tn.sweep_rounds, s)) !=
+            hipSuccess)
+            return hip_fail(e, "store");
+        if ((e = launch_seed(tbytes, conn, imgs, L.n_tiles, flags, seed_round, ctrl, bitmap,
+                             qflag, ring, L.ring_cap, s)) != hipSuccess)
+            return hip_fail(e, "seed");
+        int blocks = tn.persistent_blocks;
+        const int maxb = queue_max_blocks(tbytes, conn);
+        if (maxb <= 0) return fail(MR_EHIP, "cannot size the queue launch");
+        if (blocks == 0 || blocks > maxb) blocks = maxb;
+        if ((e = launch_queue(tbytes, conn, imgs, ctrl, bitmap, qflag, ring, L.ring_cap, blocks,
+                              SPIN_CAP, s)) != hipSuccess)
+            return hip_fail(e, "queue");
+    } else {
+        // converge mode: rounds until no tile is dirty, polling every few rounds
+        unsigned long long *hw = host_word();
+        if (!hw) return fail(MR_EHIP, "cannot allocate a pinned host word");
+        const uint32_t max_rounds = 1u << 20;
+        const uint32_t poll = 4;
+        while (true) {
+            for (uint32_t k = 0; k < poll; ++k) {
+                ++round;
+                if ((e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, ctrl, round, 0,
+                                           tn.max_sweeps, s)) != hipSuccess)
+                    return hip_fail(e, "tile round");
+            }
+            if ((e = hipMemcpyAsync(hw, &ctrl->mark.v, sizeof *hw, hipMemcpyDeviceToHost, s)) !=
+                hipSuccess)
+                return hip_fail(e, "poll copy");
+            if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "poll sync");
+            if (*hw <= round) break; // nothing marked for a round not yet run
+            if (round > max_rounds) return fail(MR_EHIP, "tile rounds did not converge");
+        }
+        if ((e = launch_store_u64(&ctrl->rounds, (unsigned long long)round, s)) != hipSuccess)
+            return hip_fail(e, "store");
+    }
+    if (any_fill && (e = launch_fill_output(tbytes, imgs, L.n_tiles, s)) != hipSuccess)
+        return hip_fail(e, "fill output");
+    return MR_OK;
+}
+
+int run_single(int op, void *J_io, const void *I, int64_t H, int64_t W, int64_t pitch, int t,
+               int conn, void *ws, size_t ws_bytes, const mr_tune *tune, void *stream) {
+    g_err.clear();
+    int rc;
+    if ((rc = check_image(op, H, W, pitch, t, conn)) != MR_OK) return rc;
+    if ((rc = check_tune(tune)) != MR_OK) return rc;
+    if (!J_io || (op == MR_OP_RECON && !I) || !ws)
+        return fail(MR_EINVAL, "null image or workspace pointer");
+    if ((uintptr_t)ws % 256) return fail(MR_EINVAL, "workspace must be 256-byte aligned");
+    if ((uintptr_t)J_io % t || (I && (uintptr_t)I % t))
+        return fail(MR_EINVAL, "image pointers must be aligned to the pixel size");
+    const Layout L = single_layout(op, H, W, t);
+    if (ws_bytes < L.total)
+        return fail(MR_ENOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes,
+                    L.total);
+    if (pitch == 0) pitch = W;
+    ImgDesc d{};
+    d.H = H;
+    d.W = W;
+    d.op = op;
+    d.ntx = (int32_t)tiles_across(W);
+    d.nty = (int32_t)tiles_across(H);
+    d.tile_base = 0;
+    d.px_base = 0;
+    d.done = 0;
+    if (op == MR_OP_RECON) {
+        d.J = J_io;
+        d.I = I;
+        d.out = nullptr;
+        d.pJ = pitch;
+        d.pI = pitch;
+    } else {
+        d.J = (char *)ws + L.off_plane;
+        d.I = J_io;
+        d.out = J_io;
+        d.pJ = L.plane_pitch;
+        d.pI = pitch;
+    }
+    const mr_tune tn = effective_tune(tune);
+    Imgs imgs{};
+    imgs.n = 1;
+    imgs.d = (const ImgDesc *)((char *)ws + L.off_desc);
+    hipError_t e = launch_put_desc((ImgDesc *)imgs.d, d, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "descriptor");
+    return run_sequence(t, conn, imgs, L, ws, tn, (hipStream_t)stream, op == MR_OP_FILL);
+}
+
+} // namespace
+
+extern "C" {
+
+void mr_default_tune(mr_tune *out) {
+    if (!out) return;
+    out->sweep_rounds = 4;
+    out->max_sweeps = 16;
+    out->persistent_blocks = 0;
+    out->reserved = 0;
+}
+
+size_t mr_workspace_bytes(int op, int64_t H, int64_t W, mr_dtype t, int conn, const mr_tune *tune) {
+    g_err.clear();
+    if (check_image(op, H, W, 0, (int)t, conn) != MR_OK) return 0;
+    if (check_tune(tune) != MR_OK) return 0;
+    return single_layout(op, H, W, (int)t).total;
+}
+
+int mr_recon_dilate(void *marker_inout, const void *mask, int64_t H, int64_t W, int64_t pitch,
+                    mr_dtype t, int conn, void *ws, size_t ws_bytes, const mr_tune *tune,
+                    void *stream) {
+    return run_single(MR_OP_RECON, marker_inout, mask, H, W, pitch, (int)t, conn, ws, ws_bytes,
+                      tune, stream);
+}
+
+int mr_fill_holes(void *img_inout, int64_t H, int64_t W, int64_t pitch, mr_dtype t, int conn,
+                  void *ws, size_t ws_bytes, const mr_tune *tune, void *stream) {
+    return run_single(MR_OP_FILL, img_inout, nullptr, H, W, pitch, (int)t, conn, ws, ws_bytes,
+                      tune, stream);
+}
+
+int mr_read_counters(const void *ws, mr_counters *out, void *stream) {
+    g_err.clear();
+    if (!ws || !out) return fail(MR_EINVAL, "null pointer");
+    Ctrl h;
+    hipError_t e = hipMemcpyAsync(&h, ws, sizeof h, hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "counter copy");
+    if ((e = hipStreamSynchronize((hipStream_t)stream)) != hipSuccess)
+        return hip_fail(e, "counter sync");
+    mr_counters c{};
+    c.rounds = h.rounds;
+    c.seeds = h.seeds_total.v;
+    for (int i = 0; i < NCNT; ++i) {
+        c.tiles += h.tiles[i];
+        c.pops += h.pops[i];
+        c.pushes += h.pushes[i];
+        c.cas_retries += h.cas[i];
+        c.overflows += h.ovf[i];
+    }
+    *out = c;
+    if (h.watchdog) return fail(MR_EHIP, "a queue workgroup hit its spin cap");
+    return MR_OK;
+}
+
+const char *mr_last_error(void) { return g_err.c_str(); }
+
+int mr_abi_version(void) { return MR_ABI_VERSION; }
+
+} // extern "C"

@@ -1,0 +1,86 @@
+// mr_internal.h -- layouts shared by the device kernels and the host engine of
+// libmrecon. Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/mr.h"
+
+namespace mr {
+
+// Register tile: 64 lanes x 64 rows of 32-bit keys, whose outer ring is a
+// frozen halo, so each tile owns a 62 x 62 interior. Tile (ty, tx) covers
+// image rows ty*62-1 .. ty*62+62 and columns tx*62-1 .. tx*62+62.
+constexpr int TS = 64;
+constexpr int TI = TS - 2;
+
+// One image of a launch. A single-image call builds one; a batch builds one
+// per tile of the batch. The working image J is updated in place: for
+// reconstruction it is the caller's marker, for fill-holes a workspace plane.
+struct ImgDesc {
+    void *J;           // working image, pitch pJ elements
+    const void *I;     // reconstruction: the mask; fill-holes: the input image
+    void *out;         // fill-holes: where NOT J goes at the end; else null
+    int64_t H, W;
+    int64_t pJ, pI;    // pitches in elements (out uses pI)
+    int64_t tile_base; // first tile of this image in the launch's tile list
+    int64_t px_base;   // frontier id of pixel (0, 0); ids are px_base + y*W + x
+    int32_t ntx, nty;  // tiles across and down
+    int32_t op;        // MR_OP_RECON or MR_OP_FILL
+    int32_t done;      // serving: 1 once the image needs no more device work
+};
+
+// Device control block at the start of every workspace. Contended words sit
+// on their own 128-byte lines.
+struct alignas(128) Line {
+    unsigned long long v;
+    unsigned long long pad[15];
+};
+
+constexpr int NCNT = 64; // spread counters, summed on the host
+
+struct Ctrl {
+    Line q_head;     // frontier ring: next entry to claim
+    Line q_tail;     // frontier ring: next free entry
+    Line pending;    // entries pushed and not yet fully processed
+    Line mark;       // highest round any tile was marked dirty for
+    Line overflowed; // non-zero when a push was handed back to the tiles
+    Line seeds_total;
+    unsigned long long tiles[NCNT];  // tile visits (spread)
+    unsigned long long pops[NCNT];   // queue-phase pops (spread)
+    unsigned long long pushes[NCNT]; // queue-phase pushes (spread)
+    unsigned long long cas[NCNT];    // failed CAS attempts (spread)
+    unsigned long long ovf[NCNT];    // overflowed pushes (spread)
+    unsigned long long rounds;       // written by the host sequence
+    unsigned long long watchdog;     // non-zero if a queue block hit its spin cap
+};
+
+// Launch-wide view of the images: a device array of descriptors sorted by
+// tile_base (single-image calls keep theirs in the workspace).
+struct Imgs {
+    const ImgDesc *d;
+    int32_t n;
+};
+
+constexpr uint32_t Q_EMPTY = 0xFFFFFFFFu;
+
+// Host-side launchers (defined in mr_kernels.hip).
+hipError_t launch_clear_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_clear_ctrl(Ctrl *c, hipStream_t s);
+hipError_t launch_tile_round(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
+                             uint32_t *flags, Ctrl *ctrl, uint32_t round, int first,
+                             int max_iters, hipStream_t s);
+hipError_t launch_seed(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
+                       const uint32_t *flags, uint32_t round, Ctrl *ctrl, uint64_t *bitmap,
+                       uint32_t *qflag, uint32_t *ring, uint64_t cap, hipStream_t s);
+hipError_t launch_queue(int tbytes, int conn, const Imgs &imgs, Ctrl *ctrl, uint64_t *bitmap,
+                        uint32_t *qflag, uint32_t *ring, uint64_t cap, int blocks,
+                        unsigned long long spin_cap, hipStream_t s);
+hipError_t launch_fill_output(int tbytes, const Imgs &imgs, int64_t n_tiles, hipStream_t s);
+hipError_t launch_store_u64(unsigned long long *p, unsigned long long v, hipStream_t s);
+hipError_t launch_put_desc(ImgDesc *dst, const ImgDesc &v, hipStream_t s);
+int queue_max_blocks(int tbytes, int conn);
+
+} // namespace mr

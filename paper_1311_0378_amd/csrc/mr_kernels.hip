@@ -1,0 +1,757 @@
+// mr_kernels.hip -- gfx950 kernels of libmrecon.
+//
+// Pixels are handled as 32-bit unsigned keys whose order is the pixel order:
+// uint8 v -> v, int32 v -> v ^ 0x80000000. Key 0 is the type's minimum, so it
+// is the identity of max and stands for "no pixel" outside the image. The
+// bitwise complement used by fill-holes is KMAX - key in key space.
+//
+// Three kernels carry the propagation (Algorithm 1 split into the regular and
+// irregular phases of Sec. V-C.2):
+//  * k_tile_round -- the regular phase. One wave owns a 64 x 64 tile of keys
+//    held in registers (lane = column, register = row); the outer ring is a
+//    frozen halo. Down and up sweeps run along the registers with the
+//    diagonal neighbours taken from the adjacent lanes by DPP; the tile is
+//    transposed through LDS for the right and left sweeps. Sweeps repeat until
+//    the tile is stable, then the interior is stored and the tiles whose halo
+//    changed are marked dirty for the next round.
+//  * k_seed -- one relaxation step over each tile still dirty after the last
+//    round; every raised pixel is compacted by wave ballot into the tile's row
+//    of the frontier bitmap, and the tile into the device frontier ring.
+//  * k_queue -- persistent waves pop tiles from the ring, claim the set bits of
+//    the tile's bitmap and propagate each claimed pixel to its neighbours with
+//    atomic max updates; every raised neighbour is pushed back (bit set, its
+//    tile enqueued once). The waves leave when nothing is pending.
+#include <algorithm>
+
+#include "mr_internal.h"
+
+namespace mr {
+
+template <typename T> struct Pix;
+template <> struct Pix<uint8_t> {
+    static constexpr uint32_t KMAX = 0xFFu;
+    __device__ static __forceinline__ uint32_t key(uint8_t v) { return v; }
+    __device__ static __forceinline__ uint8_t val(uint32_t k) { return (uint8_t)k; }
+};
+template <> struct Pix<int32_t> {
+    static constexpr uint32_t KMAX = 0xFFFFFFFFu;
+    __device__ static __forceinline__ uint32_t key(int32_t v) { return (uint32_t)v ^ 0x80000000u; }
+    __device__ static __forceinline__ int32_t val(uint32_t k) { return (int32_t)(k ^ 0x80000000u); }
+};
+
+template <typename T> using gptr = __attribute__((address_space(1))) T *;
+template <typename T> using cgptr = const __attribute__((address_space(1))) T *;
+
+// Lane i receives lane i-1's value (lane 0 receives 0).
+__device__ __forceinline__ uint32_t from_lower_lane(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138 /* wave_shr:1 */, 0xF, 0xF, true);
+}
+// Lane i receives lane i+1's value (lane 63 receives 0).
+__device__ __forceinline__ uint32_t from_upper_lane(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130 /* wave_shl:1 */, 0xF, 0xF, true);
+}
+
+// Descriptor of the image that owns `tile` (binary search on tile_base).
+__device__ __forceinline__ ImgDesc load_desc(Imgs imgs, int64_t tile) {
+    int lo = 0, hi = imgs.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (imgs.d[mid].tile_base <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    return imgs.d[lo];
+}
+
+// Coherent (device-scope) access to the working image, used while other
+// waves update it with atomics.
+template <typename T> struct Atom;
+template <> struct Atom<int32_t> {
+    __device__ static __forceinline__ uint32_t load_key(const int32_t *base, int64_t off) {
+        const int32_t v = __hip_atomic_load(base + off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return Pix<int32_t>::key(v);
+    }
+    // Raise the pixel to key k if it is lower; true if this call raised it.
+    __device__ static __forceinline__ bool raise(int32_t *base, int64_t off, uint32_t k,
+                                                 unsigned long long &retries) {
+        (void)retries;
+        const int32_t v = Pix<int32_t>::val(k);
+        const int32_t old = __hip_atomic_fetch_max(base + off, v, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        return old < v;
+    }
+};
+template <> struct Atom<uint8_t> {
+    __device__ static __forceinline__ uint32_t load_key(const uint8_t *base, int64_t off) {
+        const uintptr_t a = (uintptr_t)(base + off);
+        const uint32_t *w = (const uint32_t *)(a & ~(uintptr_t)3);
+        const uint32_t sh = (uint32_t)(a & 3) * 8u;
+        const uint32_t word = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return (word >> sh) & 0xFFu;
+    }
+    __device__ static __forceinline__ bool raise(uint8_t *base, int64_t off, uint32_t k,
+                                                 unsigned long long &retries) {
+        const uintptr_t a = (uintptr_t)(base + off);
+        uint32_t *w = (uint32_t *)(a & ~(uintptr_t)3);
+        const uint32_t sh = (uint32_t)(a & 3) * 8u;
+        uint32_t old = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        while (true) {
+            if (((old >> sh) & 0xFFu) >= k) return false;
+            const uint32_t nw = (old & ~(0xFFu << sh)) | (k << sh);
+            uint32_t expect = old;
+            if (__hip_atomic_compare_exchange_strong(w, &expect, nw, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                return true;
+            old = expect;
+            ++retries;
+        }
+    }
+};
+
+// ------------------------------------------------------------------ tiles
+
+
+// Load one 64 x 64 register tile. INITIAL builds the starting working image
+// (reconstruction: min(marker, mask); fill-holes: the complement on the image
+// border and the minimum inside) instead of reading it; FILL reads the input
+// image and complements it into the mask. Every load is issued unconditionally
+// from a clamped, in-bounds address and outside pixels are replaced by key 0
+// afterwards, so all loads of the tile can be in flight together. The halo
+// ring gets I = J, which freezes it: min(max(J, n), J) = J.
+template <typename T, bool FILL, bool INITIAL>
+__device__ __forceinline__ void load_tile(const ImgDesc &d, int64_t gy0, int64_t gx, int lane,
+                                          uint32_t (&J)[TS], uint32_t (&I)[TS]) {
+    using P = Pix<T>;
+    cgptr<T> Jp = (cgptr<T>)d.J;
+    cgptr<T> Ip = (cgptr<T>)d.I;
+    const int64_t H = d.H, W = d.W;
+    const bool xin = gx >= 0 && gx < W;
+    const uint32_t xc = (uint32_t)min(max(gx, (int64_t)0), W - 1);
+    const bool halo_lane = lane == 0 || lane == TS - 1;
+    const bool xedge = xc == 0 || xc == (uint32_t)(W - 1);
+#pragma unroll
+    for (int r = 0; r < TS; ++r) {
+        const int64_t gy = gy0 + r;
+        const bool ok = xin && gy >= 0 && gy < H;
+        const uint32_t yc = (uint32_t)min(max(gy, (int64_t)0), H - 1);
+        uint32_t iv = P::key(Ip[yc * (uint32_t)d.pI + xc]);
+        if (FILL) iv = P::KMAX - iv;
+        uint32_t jv;
+        if (INITIAL) {
+            if (FILL)
+                jv = (xedge || yc == 0 || yc == (uint32_t)(H - 1)) ? iv : 0u;
+            else
+                jv = min(P::key(Jp[yc * (uint32_t)d.pJ + xc]), iv);
+        } else {
+            jv = P::key(Jp[yc * (uint32_t)d.pJ + xc]);
+        }
+        jv = ok ? jv : 0u;
+        iv = ok ? iv : 0u;
+        J[r] = jv;
+        I[r] = (halo_lane || r == 0 || r == TS - 1) ? jv : iv;
+    }
+}
+
+// Transpose a 64 x 64 register tile through LDS: afterwards lane l holds row
+// l and register c holds column c.
+__device__ __forceinline__ void transpose(uint32_t (&A)[TS], uint32_t (*tb)[TS + 1], int lane) {
+#pragma unroll
+    for (int r = 0; r < TS; ++r) tb[r][lane] = A[r];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < TS; ++c) A[c] = tb[lane][c];
+    __syncthreads();
+}
+
+// Forward sweep along the registers: A[r] takes max over the previous
+// register's three lanes (one for 4-connectivity), limited by B[r]. Values
+// only rise, so callers detect change by comparing column sums.
+template <int CONN>
+__device__ __forceinline__ void sweep_fwd(uint32_t (&A)[TS], const uint32_t (&B)[TS]) {
+#pragma unroll
+    for (int r = 1; r < TS - 1; ++r) {
+        const uint32_t u = A[r - 1];
+        uint32_t n = u;
+        if (CONN == 8) n = max(n, max(from_lower_lane(u), from_upper_lane(u)));
+        const uint32_t v = min(max(A[r], n), B[r]);
+        A[r] = v;
+    }
+}
+
+template <int CONN>
+__device__ __forceinline__ void sweep_bwd(uint32_t (&A)[TS], const uint32_t (&B)[TS]) {
+#pragma unroll
+    for (int r = TS - 2; r >= 1; --r) {
+        const uint32_t u = A[r + 1];
+        uint32_t n = u;
+        if (CONN == 8) n = max(n, max(from_lower_lane(u), from_upper_lane(u)));
+        const uint32_t v = min(max(A[r], n), B[r]);
+        A[r] = v;
+    }
+}
+
+// Sum of the interior rows of a column. Keys only rise, so the sum rises iff
+// some key changed; 62 keys below 2^32 cannot overflow 64 bits, and 62 u8 keys
+// cannot overflow 32.
+template <typename T>
+__device__ __forceinline__ uint64_t col_sum(const uint32_t (&A)[TS]) {
+    if (sizeof(T) == 1) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int r = 1; r < TS - 1; ++r) s += A[r];
+        return s;
+    }
+    uint64_t s = 0;
+#pragma unroll
+    for (int r = 1; r < TS - 1; ++r) s += A[r];
+    return s;
+}
+
+__device__ __forceinline__ void mark(uint32_t *flags, const ImgDesc &d, int ty, int tx,
+                                     uint32_t val) {
+    if (ty < 0 || ty >= d.nty || tx < 0 || tx >= d.ntx) return;
+    flags[d.tile_base + (int64_t)ty * d.ntx + tx] = val;
+}
+
+// One visit of one tile: load, sweep to a local fixed point (or the cap),
+// store, and mark the neighbours whose halo changed.
+template <typename T, int CONN, bool FILL, bool INITIAL>
+__device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane,
+                                           uint32_t *__restrict__ flags, Ctrl *__restrict__ ctrl,
+                                           uint32_t round, int max_iters,
+                                           uint32_t (*tb)[TS + 1]) {
+    using P = Pix<T>;
+    constexpr bool first = INITIAL;
+    const int64_t lt = t - d.tile_base;
+    const int ty = (int)(lt / d.ntx), tx = (int)(lt - (int64_t)ty * d.ntx);
+    const int64_t gy0 = (int64_t)ty * TI - 1, gx = (int64_t)tx * TI - 1 + lane;
+
+    uint32_t J[TS], I[TS], IT[TS];
+    load_tile<T, FILL, INITIAL>(d, gy0, gx, lane, J, I);
+#pragma unroll
+    for (int r = 0; r < TS; ++r) IT[r] = I[r];
+    transpose(IT, tb, lane);
+
+    const uint32_t top_in = J[1], bot_in = J[TS - 2];
+    const uint64_t col_in = col_sum<T>(J);
+    uint64_t col_prev = col_in;
+
+    bool stable = false, changed = false;
+    for (int it = 0; it < max_iters; ++it) {
+        sweep_fwd<CONN>(J, I);
+        sweep_bwd<CONN>(J, I);
+        transpose(J, tb, lane);
+        sweep_fwd<CONN>(J, IT);
+        sweep_bwd<CONN>(J, IT);
+        transpose(J, tb, lane);
+        const uint64_t col_now = col_sum<T>(J);
+        const bool ch = col_now != col_prev;
+        col_prev = col_now;
+        if (__ballot(ch) == 0) {
+            stable = true;
+            break;
+        }
+        changed = true;
+    }
+
+    const bool in_lane = lane >= 1 && lane <= TS - 2;
+    if (changed || first) {
+        gptr<T> Jw = (gptr<T>)d.J;
+        if (in_lane && gx < d.W) {
+            // rows gy0+1 .. gy0+62 are all >= 0; only the last tile row may
+            // run past the image
+            const int rows = (int)min<int64_t>(TS - 2, d.H - gy0 - 1);
+            uint32_t off = (uint32_t)(gy0 + 1) * (uint32_t)d.pJ + (uint32_t)gx;
+#pragma unroll
+            for (int r = 1; r < TS - 1; ++r) {
+                asm volatile("" : "+v"(off));
+                if (r <= rows) Jw[off] = P::val(J[r]);
+                off += (uint32_t)d.pJ;
+            }
+        }
+    }
+    if (lane == 0) atomicAdd(&ctrl->tiles[t & (NCNT - 1)], 1ull);
+    if (!changed && stable) return;
+
+    const uint64_t col_out = col_prev;
+    const uint64_t bt = __ballot(in_lane && J[1] != top_in);
+    const uint64_t bb = __ballot(in_lane && J[TS - 2] != bot_in);
+    const uint64_t bc = __ballot(col_out != col_in);
+    if (lane == 0) {
+        const uint32_t nxt = round + 1;
+        const bool left = (bc >> 1) & 1, right = (bc >> (TS - 2)) & 1;
+        bool any = !stable;
+        if (!stable) mark(flags, d, ty, tx, nxt);
+        if (bt) { mark(flags, d, ty - 1, tx, nxt); any = true; }
+        if (bb) { mark(flags, d, ty + 1, tx, nxt); any = true; }
+        if (left) { mark(flags, d, ty, tx - 1, nxt); any = true; }
+        if (right) { mark(flags, d, ty, tx + 1, nxt); any = true; }
+        if (CONN == 8) {
+            if ((bt >> 1) & 1) mark(flags, d, ty - 1, tx - 1, nxt);
+            if ((bt >> (TS - 2)) & 1) mark(flags, d, ty - 1, tx + 1, nxt);
+            if ((bb >> 1) & 1) mark(flags, d, ty + 1, tx - 1, nxt);
+            if ((bb >> (TS - 2)) & 1) mark(flags, d, ty + 1, tx + 1, nxt);
+        }
+        if (any) {
+            unsigned long long *m = &ctrl->mark.v;
+            if (__hip_atomic_load(m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < nxt)
+                __hip_atomic_fetch_max(m, (unsigned long long)nxt, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// One tile round. Grid: one 64-thread block per tile of the launch.
+template <typename T, int CONN>
+__global__ __launch_bounds__(64) void k_tile_round(Imgs imgs, uint32_t *__restrict__ flags,
+                                                   Ctrl *__restrict__ ctrl, uint32_t round,
+                                                   int first, int max_iters) {
+    __shared__ uint32_t tb[TS][TS + 1]; // transpose buffer
+    const int64_t t = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (!first && flags[t] < round) return;
+    const ImgDesc d = load_desc(imgs, t);
+    if (d.done) return;
+    if (d.op == MR_OP_FILL) {
+        if (first) visit_tile<T, CONN, true, true>(d, t, lane, flags, ctrl, round, max_iters, tb);
+        else visit_tile<T, CONN, true, false>(d, t, lane, flags, ctrl, round, max_iters, tb);
+    } else {
+        if (first) visit_tile<T, CONN, false, true>(d, t, lane, flags, ctrl, round, max_iters, tb);
+        else visit_tile<T, CONN, false, false>(d, t, lane, flags, ctrl, round, max_iters, tb);
+    }
+}
+
+// ------------------------------------------------------------ frontier ring
+
+// The ring holds tile ids; a tile is in it at most once (its qflag is 1 from
+// enqueue until a wave finishes with it), so it never holds more than the
+// launch's tile count, and the capacity exceeds that plus the waves in flight.
+__device__ __forceinline__ void ring_push(Ctrl *ctrl, uint32_t *ring, uint64_t cap, uint32_t t) {
+    __hip_atomic_fetch_add(&ctrl->pending.v, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long pos =
+        __hip_atomic_fetch_add(&ctrl->q_tail.v, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t *slot = ring + (pos & (cap - 1));
+    // The capacity bound means the slot is already free; the wait is a guard,
+    // capped so that a broken bound cannot hang the device.
+    for (uint32_t spin = 0;
+         __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != Q_EMPTY; ++spin) {
+        if (spin > (1u << 22)) {
+            atomicAdd(&ctrl->watchdog, 1ull);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    __hip_atomic_store(slot, t, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Claim the oldest ring entry; Q_EMPTY if the ring looks empty.
+__device__ __forceinline__ uint32_t ring_pop(Ctrl *ctrl, uint32_t *ring, uint64_t cap) {
+    unsigned long long h =
+        __hip_atomic_load(&ctrl->q_head.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (true) {
+        const unsigned long long tl =
+            __hip_atomic_load(&ctrl->q_tail.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (h >= tl) return Q_EMPTY;
+        if (__hip_atomic_compare_exchange_weak(&ctrl->q_head.v, &h, h + 1, __ATOMIC_RELAXED,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            break;
+    }
+    uint32_t *slot = ring + (h & (cap - 1));
+    uint32_t v;
+    // the producer that reserved this entry writes it right after reserving
+    for (uint32_t spin = 0;
+         (v = __hip_atomic_load(slot, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) == Q_EMPTY;
+         ++spin) {
+        if (spin > (1u << 22)) {
+            atomicAdd(&ctrl->watchdog, 1ull);
+            return Q_EMPTY;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    __hip_atomic_store(slot, Q_EMPTY, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return v;
+}
+
+// ------------------------------------------------------------------- seeds
+
+// One relaxation step over each tile still dirty for `round`: every interior
+// pixel takes min(I, max of J over itself and its neighbours). Raised pixels
+// are stored, their bits form the tile's frontier bitmap rows, and the tile
+// enters the ring. Tiles that are not dirty only clear their bitmap and flag.
+template <typename T>
+__device__ __forceinline__ void load_row(const ImgDesc &d, int64_t gy, int64_t gx, bool frozen,
+                                         uint32_t &j, uint32_t &i) {
+    using P = Pix<T>;
+    j = 0;
+    i = 0;
+    if (gx >= 0 && gx < d.W && gy >= 0 && gy < d.H) {
+        j = P::key(((cgptr<T>)d.J)[gy * d.pJ + gx]);
+        i = P::key(((cgptr<T>)d.I)[gy * d.pI + gx]);
+        if (d.op == MR_OP_FILL) i = P::KMAX - i;
+    }
+    if (frozen) i = j;
+}
+
+template <typename T, int CONN>
+__global__ __launch_bounds__(64) void k_seed(Imgs imgs, const uint32_t *__restrict__ flags,
+                                             uint32_t round, Ctrl *__restrict__ ctrl,
+                                             uint64_t *__restrict__ bitmap,
+                                             uint32_t *__restrict__ qflag,
+                                             uint32_t *__restrict__ ring, uint64_t cap) {
+    using P = Pix<T>;
+    const int64_t t = blockIdx.x;
+    const int lane = threadIdx.x;
+    const ImgDesc d = load_desc(imgs, t);
+    if (d.done || flags[t] < round) {
+        bitmap[t * TS + lane] = 0;
+        if (lane == 0) qflag[t] = 0;
+        return;
+    }
+    const int64_t lt = t - d.tile_base;
+    const int ty = (int)(lt / d.ntx), tx = (int)(lt - (int64_t)ty * d.ntx);
+    const int64_t gy0 = (int64_t)ty * TI - 1, gx = (int64_t)tx * TI - 1 + lane;
+    const bool halo_lane = lane == 0 || lane == TS - 1;
+
+    uint32_t jp, ip, jc, ic, jn, in_;
+    load_row<T>(d, gy0, gx, true, jp, ip);
+    load_row<T>(d, gy0 + 1, gx, halo_lane, jc, ic);
+    uint64_t myrow = 0; // lane r ends up holding row r's bits
+    uint32_t nseed = 0;
+    gptr<T> Jw = (gptr<T>)d.J;
+    for (int r = 1; r < TS - 1; ++r) {
+        load_row<T>(d, gy0 + r + 1, gx, halo_lane || r + 1 == TS - 1, jn, in_);
+        uint32_t n = max(jp, jn);
+        n = max(n, max(from_lower_lane(jc), from_upper_lane(jc)));
+        if (CONN == 8) {
+            n = max(n, max(from_lower_lane(jp), from_upper_lane(jp)));
+            n = max(n, max(from_lower_lane(jn), from_upper_lane(jn)));
+        }
+        const uint32_t v = min(max(jc, n), ic);
+        const bool raised = v > jc; // frozen lanes and outside pixels have I == J
+        const uint64_t bits = __ballot(raised);
+        if (raised) Jw[(gy0 + r) * d.pJ + gx] = P::val(v);
+        if (lane == r) myrow = bits;
+        nseed += (uint32_t)__popcll(bits);
+        jp = jc;
+        jc = jn;
+        ic = in_;
+    }
+    bitmap[t * TS + lane] = myrow;
+    if (lane == 0) {
+        if (nseed) {
+            qflag[t] = 1;
+            __hip_atomic_fetch_add(&ctrl->seeds_total.v, (unsigned long long)nseed,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            qflag[t] = 0;
+        }
+    }
+    // the bitmap rows must be visible before the tile can be popped
+    __threadfence();
+    if (lane == 0 && nseed) ring_push(ctrl, ring, cap, (uint32_t)t);
+}
+
+// ------------------------------------------------------------------- queue
+
+constexpr int QWAVES = 4;                  // waves per queue workgroup
+constexpr int LIST_CAP = TI * TI;          // claimed pixels of one tile
+
+// Process one claimed pixel: propagate its value to every neighbour that it
+// can raise (Algorithm 1's PropagationCondition / Update), pushing each
+// neighbour actually raised.
+template <typename T, int CONN>
+__device__ __forceinline__ void relax_pixel(const ImgDesc &d, int64_t y, int64_t x, Ctrl *ctrl,
+                                            uint64_t *bitmap, uint32_t *qflag, uint32_t *ring,
+                                            uint64_t cap, uint32_t &npush,
+                                            unsigned long long &retries) {
+    using P = Pix<T>;
+    T *Jw = (T *)d.J;
+    cgptr<T> Ip = (cgptr<T>)d.I;
+    const bool fill = d.op == MR_OP_FILL;
+    const uint32_t jp = Atom<T>::load_key(Jw, y * d.pJ + x);
+#pragma unroll
+    for (int k = 0; k < CONN; ++k) {
+        // edge neighbours first, then diagonals
+        const int dy = (k == 0) ? -1 : (k == 1) ? 1 : (k < 4) ? 0 : (k < 6 ? -1 : 1);
+        const int dx = (k < 2) ? 0 : (k == 2) ? -1 : (k == 3) ? 1 : ((k & 1) ? 1 : -1);
+        const int64_t yy = y + dy, xx = x + dx;
+        if (yy < 0 || yy >= d.H || xx < 0 || xx >= d.W) continue;
+        const uint32_t jq = Atom<T>::load_key(Jw, yy * d.pJ + xx);
+        if (jq >= jp) continue;
+        uint32_t iq = P::key(Ip[yy * d.pI + xx]);
+        if (fill) iq = P::KMAX - iq;
+        if (jq >= iq) continue;
+        const uint32_t v = min(jp, iq);
+        if (!Atom<T>::raise(Jw, yy * d.pJ + xx, v, retries)) continue;
+        // push: set the pixel's frontier bit, enqueue its tile once
+        const int tyq = (int)(yy / TI), txq = (int)(xx / TI);
+        const int rq = (int)(yy - (int64_t)tyq * TI) + 1, lq = (int)(xx - (int64_t)txq * TI) + 1;
+        const int64_t tq = d.tile_base + (int64_t)tyq * d.ntx + txq;
+        const uint64_t bit = 1ull << lq;
+        const uint64_t old = __hip_atomic_fetch_or(bitmap + tq * TS + rq, bit, __ATOMIC_RELEASE,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        ++npush;
+        if (old & bit) continue;
+        if (__hip_atomic_exchange(qflag + tq, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 0)
+            ring_push(ctrl, ring, cap, (uint32_t)tq);
+    }
+}
+
+template <typename T, int CONN>
+__global__ __launch_bounds__(64 * QWAVES) void k_queue(Imgs imgs, Ctrl *__restrict__ ctrl,
+                                                       uint64_t *__restrict__ bitmap,
+                                                       uint32_t *__restrict__ qflag,
+                                                       uint32_t *__restrict__ ring, uint64_t cap,
+                                                       unsigned long long spin_cap) {
+    __shared__ uint16_t list[QWAVES][LIST_CAP];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint16_t *mylist = list[w];
+    uint32_t npush = 0, npop = 0;
+    unsigned long long retries = 0, idle = 0;
+    const int cslot = (int)((blockIdx.x * QWAVES + w) & (NCNT - 1));
+
+    while (true) {
+        uint32_t t = Q_EMPTY;
+        if (lane == 0) t = ring_pop(ctrl, ring, cap);
+        t = __shfl(t, 0);
+        if (t == Q_EMPTY) {
+            unsigned long long pend = 0;
+            if (lane == 0)
+                pend = __hip_atomic_load(&ctrl->pending.v, __ATOMIC_ACQUIRE,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+            pend = __shfl(pend, 0);
+            if (pend == 0) break;
+            if (++idle > spin_cap) {
+                if (lane == 0) atomicAdd(&ctrl->watchdog, 1ull);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(8);
+            continue;
+        }
+        idle = 0;
+        const ImgDesc d = load_desc(imgs, t);
+        const int64_t lt = (int64_t)t - d.tile_base;
+        const int ty = (int)(lt / d.ntx), tx = (int)(lt - (int64_t)ty * d.ntx);
+        const int64_t gy0 = (int64_t)ty * TI - 1, gx0 = (int64_t)tx * TI - 1;
+        uint64_t *rows = bitmap + (int64_t)t * TS;
+        bool released = false;
+        while (true) {
+            uint64_t bits = __hip_atomic_exchange(rows + lane, 0ull, __ATOMIC_ACQUIRE,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+            if (__ballot(bits != 0) == 0) {
+                if (released) break;
+                // let pushes enqueue the tile again, then look once more
+                if (lane == 0)
+                    __hip_atomic_store(qflag + t, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                released = true;
+                continue;
+            }
+            // compact the claimed bits into a pixel list (row << 8 | lane)
+            const uint32_t c = (uint32_t)__popcll(bits);
+            uint32_t off = c; // inclusive scan over lanes
+#pragma unroll
+            for (int s = 1; s < 64; s <<= 1) {
+                const uint32_t o = __shfl_up(off, s);
+                if (lane >= s) off += o;
+            }
+            const uint32_t total = __shfl(off, 63);
+            off -= c;
+            while (bits) {
+                const int l = __ffsll((unsigned long long)bits) - 1;
+                bits &= bits - 1;
+                mylist[off++] = (uint16_t)((lane << 8) | l);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            for (uint32_t base = 0; base < total; base += 64) {
+                const uint32_t k = base + lane;
+                if (k < total) {
+                    const uint32_t e = mylist[k];
+                    const int64_t y = gy0 + (e >> 8), x = gx0 + (e & 0xFF);
+                    relax_pixel<T, CONN>(d, y, x, ctrl, bitmap, qflag, ring, cap, npush, retries);
+                }
+            }
+            npop += total;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            if (released) {
+                // bits arrived after the release; own the tile again if nobody
+                // re-enqueued it, else leave the rest to the new entry
+                uint32_t prev = 0;
+                if (lane == 0)
+                    prev = __hip_atomic_exchange(qflag + t, 1u, __ATOMIC_ACQ_REL,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+                prev = __shfl(prev, 0);
+                if (prev != 0) break;
+                released = false;
+            }
+        }
+        // everything this tile produced is counted; retire the ring entry
+        __threadfence();
+        if (lane == 0)
+            __hip_atomic_fetch_add(&ctrl->pending.v, (unsigned long long)-1ll, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // fold the per-lane counters
+    unsigned long long p = npush, r = retries;
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) {
+        p += __shfl_xor(p, s);
+        r += __shfl_xor(r, s);
+    }
+    if (lane == 0) {
+        atomicAdd(&ctrl->pushes[cslot], p);
+        atomicAdd(&ctrl->pops[cslot], (unsigned long long)npop);
+        atomicAdd(&ctrl->cas[cslot], r);
+    }
+}
+
+// ------------------------------------------------------------ small kernels
+
+__global__ void k_clear_u32(uint32_t *p, int64_t n, uint32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_clear_ctrl(Ctrl *c) {
+    unsigned long long *p = (unsigned long long *)c;
+    const int n = (int)(sizeof(Ctrl) / sizeof(unsigned long long));
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+// Fill-holes epilogue: out = NOT J over the interior of every tile of the
+// launch whose image is a fill-holes image.
+template <typename T>
+__global__ __launch_bounds__(64) void k_fill_output(Imgs imgs) {
+    using P = Pix<T>;
+    const int64_t t = blockIdx.x;
+    const int lane = threadIdx.x;
+    const ImgDesc d = load_desc(imgs, t);
+    if (d.op != MR_OP_FILL || d.done) return;
+    const int64_t lt = t - d.tile_base;
+    const int ty = (int)(lt / d.ntx), tx = (int)(lt - (int64_t)ty * d.ntx);
+    const int64_t gx = (int64_t)tx * TI - 1 + lane;
+    if (lane < 1 || lane > TS - 2 || gx >= d.W) return;
+    cgptr<T> Jp = (cgptr<T>)d.J;
+    gptr<T> O = (gptr<T>)d.out;
+    for (int r = 1; r < TS - 1; ++r) {
+        const int64_t gy = (int64_t)ty * TI - 1 + r;
+        if (gy >= d.H) break;
+        O[gy * d.pI + gx] = P::val(P::KMAX - P::key(Jp[gy * d.pJ + gx]));
+    }
+}
+
+__global__ void k_store_u64(unsigned long long *p, unsigned long long v) { *p = v; }
+
+__global__ void k_put_desc(ImgDesc *dst, ImgDesc v) { *dst = v; }
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t launch_clear_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_clear_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_ctrl(Ctrl *c, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_ctrl, dim3(1), dim3(256), 0, s, c);
+    return hipGetLastError();
+}
+
+template <typename T, int CONN>
+static hipError_t tile_round_t(const Imgs &imgs, int64_t n_tiles, uint32_t *flags, Ctrl *ctrl,
+                               uint32_t round, int first, int max_iters, hipStream_t s) {
+    hipLaunchKernelGGL((k_tile_round<T, CONN>), dim3((unsigned)n_tiles), dim3(64), 0, s, imgs,
+                       flags, ctrl, round, first, max_iters);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_round(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
+                             uint32_t *flags, Ctrl *ctrl, uint32_t round, int first,
+                             int max_iters, hipStream_t s) {
+    if (tbytes == 1)
+        return conn == 8 ? tile_round_t<uint8_t, 8>(imgs, n_tiles, flags, ctrl, round, first, max_iters, s)
+                         : tile_round_t<uint8_t, 4>(imgs, n_tiles, flags, ctrl, round, first, max_iters, s);
+    return conn == 8 ? tile_round_t<int32_t, 8>(imgs, n_tiles, flags, ctrl, round, first, max_iters, s)
+                     : tile_round_t<int32_t, 4>(imgs, n_tiles, flags, ctrl, round, first, max_iters, s);
+}
+
+template <typename T, int CONN>
+static hipError_t seed_t(const Imgs &imgs, int64_t n_tiles, const uint32_t *flags,
+                         uint32_t round, Ctrl *ctrl, uint64_t *bitmap, uint32_t *qflag,
+                         uint32_t *ring, uint64_t cap, hipStream_t s) {
+    hipLaunchKernelGGL((k_seed<T, CONN>), dim3((unsigned)n_tiles), dim3(64), 0, s, imgs, flags,
+                       round, ctrl, bitmap, qflag, ring, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
+                       const uint32_t *flags, uint32_t round, Ctrl *ctrl, uint64_t *bitmap,
+                       uint32_t *qflag, uint32_t *ring, uint64_t cap, hipStream_t s) {
+    if (tbytes == 1)
+        return conn == 8 ? seed_t<uint8_t, 8>(imgs, n_tiles, flags, round, ctrl, bitmap, qflag, ring, cap, s)
+                         : seed_t<uint8_t, 4>(imgs, n_tiles, flags, round, ctrl, bitmap, qflag, ring, cap, s);
+    return conn == 8 ? seed_t<int32_t, 8>(imgs, n_tiles, flags, round, ctrl, bitmap, qflag, ring, cap, s)
+                     : seed_t<int32_t, 4>(imgs, n_tiles, flags, round, ctrl, bitmap, qflag, ring, cap, s);
+}
+
+template <typename T, int CONN>
+static const void *queue_fn() {
+    return (const void *)&k_queue<T, CONN>;
+}
+
+static const void *queue_kernel(int tbytes, int conn) {
+    if (tbytes == 1) return conn == 8 ? queue_fn<uint8_t, 8>() : queue_fn<uint8_t, 4>();
+    return conn == 8 ? queue_fn<int32_t, 8>() : queue_fn<int32_t, 4>();
+}
+
+int queue_max_blocks(int tbytes, int conn) {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, queue_kernel(tbytes, conn),
+                                                     64 * QWAVES, 0) != hipSuccess)
+        return 0;
+    return per_cu * cus;
+}
+
+template <typename T, int CONN>
+static hipError_t queue_t(const Imgs &imgs, Ctrl *ctrl, uint64_t *bitmap, uint32_t *qflag,
+                          uint32_t *ring, uint64_t cap, int blocks, unsigned long long spin_cap,
+                          hipStream_t s) {
+    hipLaunchKernelGGL((k_queue<T, CONN>), dim3((unsigned)blocks), dim3(64 * QWAVES), 0, s, imgs,
+                       ctrl, bitmap, qflag, ring, cap, spin_cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_queue(int tbytes, int conn, const Imgs &imgs, Ctrl *ctrl, uint64_t *bitmap,
+                        uint32_t *qflag, uint32_t *ring, uint64_t cap, int blocks,
+                        unsigned long long spin_cap, hipStream_t s) {
+    if (tbytes == 1)
+        return conn == 8 ? queue_t<uint8_t, 8>(imgs, ctrl, bitmap, qflag, ring, cap, blocks, spin_cap, s)
+                         : queue_t<uint8_t, 4>(imgs, ctrl, bitmap, qflag, ring, cap, blocks, spin_cap, s);
+    return conn == 8 ? queue_t<int32_t, 8>(imgs, ctrl, bitmap, qflag, ring, cap, blocks, spin_cap, s)
+                     : queue_t<int32_t, 4>(imgs, ctrl, bitmap, qflag, ring, cap, blocks, spin_cap, s);
+}
+
+hipError_t launch_fill_output(int tbytes, const Imgs &imgs, int64_t n_tiles, hipStream_t s) {
+    if (tbytes == 1)
+        hipLaunchKernelGGL(k_fill_output<uint8_t>, dim3((unsigned)n_tiles), dim3(64), 0, s, imgs);
+    else
+        hipLaunchKernelGGL(k_fill_output<int32_t>, dim3((unsigned)n_tiles), dim3(64), 0, s, imgs);
+    return hipGetLastError();
+}
+
+hipError_t launch_put_desc(ImgDesc *dst, const ImgDesc &v, hipStream_t s) {
+    hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(1), 0, s, dst, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_store_u64(unsigned long long *p, unsigned long long v, hipStream_t s) {
+    hipLaunchKernelGGL(k_store_u64, dim3(1), dim3(1), 0, s, p, v);
+    return hipGetLastError();
+}
+
+} // namespace mr

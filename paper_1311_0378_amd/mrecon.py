@@ -1,0 +1,173 @@
+"""ctypes binding of libmrecon (include/mr.h). Argument marshalling only.
+
+Every function takes and returns torch CUDA tensors; PyTorch provides the
+device memory and the stream, and all of the computation runs in the HIP
+kernels of ``libmrecon.so``. There is no fallback: if the library is missing
+the first call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmrecon.so")
+HEADER = os.path.join(HERE, "..", "include", "mr.h")
+
+MR_U8, MR_I32 = 1, 4
+MR_OK, MR_EINVAL, MR_ENOMEM, MR_EHIP, MR_EAGAIN = 0, -1, -2, -3, -4
+MR_OP_RECON, MR_OP_FILL = 0, 1
+
+_DTYPES = {torch.uint8: MR_U8, torch.int32: MR_I32}
+
+
+class MrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libmrecon error {code}: {msg}")
+        self.code = code
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("sweep_rounds", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
+                ("persistent_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Counters(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in
+                ("rounds", "tiles", "seeds", "pops", "pushes", "cas_retries", "overflows")]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1311_0378_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        i32, i64, vp, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
+        c_int = ctypes.c_int
+        L.mr_default_tune.argtypes = [ctypes.POINTER(Tune)]
+        L.mr_default_tune.restype = None
+        L.mr_workspace_bytes.argtypes = [c_int, i64, i64, c_int, c_int, ctypes.POINTER(Tune)]
+        L.mr_workspace_bytes.restype = sz
+        L.mr_recon_dilate.argtypes = [vp, vp, i64, i64, i64, c_int, c_int, vp, sz,
+                                      ctypes.POINTER(Tune), vp]
+        L.mr_recon_dilate.restype = c_int
+        L.mr_fill_holes.argtypes = [vp, i64, i64, i64, c_int, c_int, vp, sz,
+                                    ctypes.POINTER(Tune), vp]
+        L.mr_fill_holes.restype = c_int
+        L.mr_read_counters.argtypes = [vp, ctypes.POINTER(Counters), vp]
+        L.mr_read_counters.restype = c_int
+        L.mr_last_error.argtypes = []
+        L.mr_last_error.restype = ctypes.c_char_p
+        L.mr_abi_version.argtypes = []
+        L.mr_abi_version.restype = c_int
+        _lib = L
+    return _lib
+
+
+def header_functions():
+    """Names of the functions declared in include/mr.h."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mr_[a-z_0-9]+)\s*\(", text)))
+
+
+def _check(rc: int):
+    if rc != MR_OK:
+        raise MrError(rc, lib().mr_last_error().decode())
+
+
+def default_tune() -> Tune:
+    t = Tune()
+    lib().mr_default_tune(ctypes.byref(t))
+    return t
+
+
+def make_tune(**kw) -> Tune:
+    t = default_tune()
+    for k, v in kw.items():
+        setattr(t, k, int(v))
+    return t
+
+
+def _tune_ptr(tune):
+    if tune is None:
+        return None
+    if isinstance(tune, dict):
+        tune = make_tune(**tune)
+    return ctypes.byref(tune)
+
+
+def _stream_ptr(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _image_args(t: torch.Tensor):
+    if t.dim() != 2:
+        raise ValueError("images must be 2-D")
+    if t.dtype not in _DTYPES:
+        raise TypeError(f"pixel type must be uint8 or int32, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError("images must be CUDA (HIP) tensors")
+    if t.stride(1) != 1:
+        raise ValueError("image rows must be contiguous (stride(1) == 1)")
+    H, W = t.shape
+    return int(H), int(W), int(t.stride(0)), _DTYPES[t.dtype]
+
+
+def workspace_bytes(op: int, H: int, W: int, dtype: torch.dtype, conn: int, tune=None) -> int:
+    n = lib().mr_workspace_bytes(op, H, W, _DTYPES[dtype], conn, _tune_ptr(tune))
+    if n == 0:
+        raise MrError(MR_EINVAL, lib().mr_last_error().decode())
+    return int(n)
+
+
+def alloc_workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def recon_dilate(marker: torch.Tensor, mask: torch.Tensor, conn: int = 8, tune=None,
+                 workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Reconstruction by dilation of ``marker`` under ``mask``, in place in
+    ``marker`` (returned). Enqueued on ``stream`` (default: current)."""
+    H, W, pitch, t = _image_args(marker)
+    if mask.shape != marker.shape or mask.dtype != marker.dtype or mask.stride() != marker.stride():
+        raise ValueError("mask must match the marker's shape, dtype and strides")
+    if workspace is None:
+        workspace = alloc_workspace(workspace_bytes(MR_OP_RECON, H, W, marker.dtype, conn, tune),
+                                    marker.device)
+    _check(lib().mr_recon_dilate(marker.data_ptr(), mask.data_ptr(), H, W, pitch, t, conn,
+                                 workspace.data_ptr(), workspace.numel(), _tune_ptr(tune),
+                                 _stream_ptr(stream)))
+    return marker
+
+
+def fill_holes(img: torch.Tensor, conn: int = 8, tune=None,
+               workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Fill-holes of ``img`` in place (returned)."""
+    H, W, pitch, t = _image_args(img)
+    if workspace is None:
+        workspace = alloc_workspace(workspace_bytes(MR_OP_FILL, H, W, img.dtype, conn, tune),
+                                    img.device)
+    _check(lib().mr_fill_holes(img.data_ptr(), H, W, pitch, t, conn, workspace.data_ptr(),
+                               workspace.numel(), _tune_ptr(tune), _stream_ptr(stream)))
+    return img
+
+
+def read_counters(workspace: torch.Tensor, stream=None) -> dict:
+    """Work counters of the last call that used ``workspace`` (waits for it)."""
+    c = Counters()
+    _check(lib().mr_read_counters(workspace.data_ptr(), ctypes.byref(c), _stream_ptr(stream)))
+    return c.as_dict()

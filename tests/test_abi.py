@@ -1,0 +1,97 @@
+"""The C ABI on the host: the library loads, exports what include/mr.h
+declares, and rejects bad arguments before touching the device."""
+import ctypes
+
+import pytest
+
+from paper_1311_0378_amd import mrecon
+
+
+@pytest.fixture(scope="module")
+def L():
+    return mrecon.lib()
+
+
+def test_exports_every_declared_function(L):
+    names = mrecon.header_functions()
+    assert "mr_recon_dilate" in names and "mr_fill_holes" in names
+    for n in names:
+        assert hasattr(L, n), f"{n} is declared in include/mr.h but not exported"
+
+
+def test_abi_version(L):
+    assert L.mr_abi_version() == 1
+
+
+def test_default_tune():
+    t = mrecon.default_tune()
+    assert t.sweep_rounds >= 1 and 1 <= t.max_sweeps <= 1024 and t.reserved == 0
+
+
+def test_workspace_bytes_grows_with_size():
+    import torch
+    a = mrecon.workspace_bytes(mrecon.MR_OP_RECON, 100, 100, torch.uint8, 8)
+    b = mrecon.workspace_bytes(mrecon.MR_OP_RECON, 1000, 1000, torch.uint8, 8)
+    f = mrecon.workspace_bytes(mrecon.MR_OP_FILL, 1000, 1000, torch.uint8, 8)
+    f32 = mrecon.workspace_bytes(mrecon.MR_OP_FILL, 1000, 1000, torch.int32, 8)
+    assert 0 < a < b < f < f32
+    assert f - b >= 1000 * 1000  # the fill-holes working plane
+
+
+@pytest.mark.parametrize("args", [
+    (0, 0, 10, 10, 8),      # op, dtype ok ... H/W ok: baseline valid (checked separately)
+])
+def test_workspace_bytes_valid(L, args):
+    op, _, H, W, conn = args
+    assert L.mr_workspace_bytes(op, H, W, 1, conn, None) > 0
+
+
+@pytest.mark.parametrize("op,H,W,t,conn", [
+    (2, 10, 10, 1, 8), (0, 0, 10, 1, 8), (0, 10, -1, 1, 8), (0, 10, 10, 2, 8),
+    (0, 10, 10, 1, 6), (0, 1 << 20, 1 << 14, 1, 8)])
+def test_workspace_bytes_invalid(L, op, H, W, t, conn):
+    assert L.mr_workspace_bytes(op, H, W, t, conn, None) == 0
+    assert L.mr_last_error()
+
+
+FAKE = 0x7F0000000000  # never dereferenced: every call below fails validation
+
+
+def _recon(L, marker=FAKE, mask=FAKE, H=8, W=8, pitch=0, t=1, conn=8, ws=FAKE,
+           ws_bytes=1 << 30, tune=None):
+    return L.mr_recon_dilate(ctypes.c_void_p(marker), ctypes.c_void_p(mask), H, W, pitch, t,
+                             conn, ctypes.c_void_p(ws), ws_bytes, tune, None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(marker=0), mrecon.MR_EINVAL), (dict(mask=0), mrecon.MR_EINVAL),
+    (dict(ws=0), mrecon.MR_EINVAL), (dict(H=0), mrecon.MR_EINVAL), (dict(W=-3), mrecon.MR_EINVAL),
+    (dict(pitch=4), mrecon.MR_EINVAL), (dict(conn=6), mrecon.MR_EINVAL),
+    (dict(t=2), mrecon.MR_EINVAL), (dict(ws=FAKE + 8), mrecon.MR_EINVAL),
+    (dict(t=4, marker=FAKE + 2), mrecon.MR_EINVAL), (dict(ws_bytes=100), mrecon.MR_ENOMEM),
+])
+def test_recon_rejects(L, kw, code):
+    assert _recon(L, **kw) == code
+    assert L.mr_last_error()
+
+
+@pytest.mark.parametrize("field,value", [("sweep_rounds", 0), ("max_sweeps", 0),
+                                         ("max_sweeps", 5000), ("persistent_blocks", -1),
+                                         ("reserved", 1)])
+def test_recon_rejects_bad_tune(L, field, value):
+    t = mrecon.default_tune()
+    setattr(t, field, value)
+    assert _recon(L, tune=ctypes.byref(t)) == mrecon.MR_EINVAL
+
+
+def test_fill_rejects(L):
+    rc = L.mr_fill_holes(ctypes.c_void_p(0), 8, 8, 0, 1, 8, ctypes.c_void_p(FAKE), 1 << 30, None,
+                         None)
+    assert rc == mrecon.MR_EINVAL
+    rc = L.mr_fill_holes(ctypes.c_void_p(FAKE), 8, 8, 0, 1, 8, ctypes.c_void_p(FAKE), 64, None,
+                         None)
+    assert rc == mrecon.MR_ENOMEM
+
+
+def test_read_counters_rejects_null(L):
+    assert L.mr_read_counters(None, None, None) == mrecon.MR_EINVAL

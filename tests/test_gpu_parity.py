@@ -1,0 +1,151 @@
+"""Parity of the HIP path with the CPU oracle, element by element (bit-exact).
+
+The result of reconstruction and of fill-holes is unique (the least fixed
+point of the geodesic dilation), and all arithmetic is integer, so every
+pixel must match exactly, for every tuning of the sweep/queue split.
+"""
+import glob
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import refs
+from paper_1311_0378_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # collected on CPU-only hosts too
+    pytest.skip("no GPU", allow_module_level=True)
+
+from gpu_util import first_mismatch, gpu_fill, gpu_recon  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+TUNES = [None, dict(sweep_rounds=1, max_sweeps=1), dict(sweep_rounds=2, max_sweeps=3),
+         dict(sweep_rounds=-1), dict(sweep_rounds=8, persistent_blocks=3)]
+
+
+def check(got, want):
+    assert np.array_equal(got, want), first_mismatch(got, want)
+
+
+@pytest.mark.parametrize("path", sorted(glob.glob(os.path.join(GOLDEN, "*.txt"))),
+                         ids=os.path.basename)
+def test_golden(path):
+    g = refs.load_golden(path)
+    if g["op"] == "recon":
+        got = gpu_recon(g["marker"], g["mask"], g["conn"])
+    else:
+        got = gpu_fill(g["input"], g["conn"])
+    check(got, g["expected"])
+
+
+SHAPES = [(1, 1), (1, 200), (200, 1), (2, 3), (61, 62), (62, 62), (63, 64), (64, 65),
+          (124, 125), (130, 70), (187, 251)]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"{s[0]}x{s[1]}")
+@pytest.mark.parametrize("conn", [4, 8])
+@pytest.mark.parametrize("dt", ["u8", "i32"])
+def test_recon_random_shapes(shape, conn, dt):
+    rng = np.random.default_rng(shape[0] * 1000 + shape[1] * 10 + conn + (dt == "i32"))
+    if dt == "u8":
+        mask = rng.integers(0, 6, shape).astype(np.uint8)
+        marker = rng.integers(0, 6, shape).astype(np.uint8)
+    else:
+        mask = rng.integers(-2**31, 2**31, shape, dtype=np.int64).astype(np.int32)
+        marker = rng.integers(-2**31, 2**31, shape, dtype=np.int64).astype(np.int32)
+    want, _ = oracle.recon_dilate(marker, mask, conn)
+    check(gpu_recon(marker, mask, conn), want)
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"{s[0]}x{s[1]}")
+@pytest.mark.parametrize("conn", [4, 8])
+def test_fill_random_shapes(shape, conn):
+    rng = np.random.default_rng(sum(shape) + conn)
+    img = rng.integers(0, 5, shape).astype(np.uint8)
+    want, _ = oracle.fill_holes(img, conn)
+    check(gpu_fill(img, conn), want)
+
+
+@pytest.mark.parametrize("tune", TUNES, ids=str)
+@pytest.mark.parametrize("conn", [4, 8])
+def test_recon_synthetic_tunes(tune, conn):
+    marker, mask = synth.make_tile(300, 517, 30, 3, "u8", 0.1)
+    want, _ = oracle.recon_dilate(marker, mask, conn)
+    check(gpu_recon(marker, mask, conn, tune=tune), want)
+
+
+@pytest.mark.parametrize("tune", TUNES, ids=str)
+@pytest.mark.parametrize("conn", [4, 8])
+def test_fill_synthetic_tunes(tune, conn):
+    img = synth.binary_from_mask(synth.quantize(synth.make_field(311, 400, 60, 5, 0.4), "u8"))
+    want, _ = oracle.fill_holes(img, conn)
+    check(gpu_fill(img, conn, tune=tune), want)
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_serpentine_queue_heavy(conn):
+    from test_oracle_pins import serpentine
+    marker, mask = serpentine(127, 129, 7)
+    want, _ = oracle.recon_dilate(marker, mask, conn)
+    for tune in (None, dict(sweep_rounds=1, max_sweeps=1)):
+        got, c = gpu_recon(marker, mask, conn, tune=tune, counters=True)
+        check(got, want)
+
+
+def test_pitched_rows():
+    marker, mask = synth.make_tile(200, 333, 20, 8, "u8", 0.0)
+    want, _ = oracle.recon_dilate(marker, mask, 8)
+    check(gpu_recon(marker, mask, 8, pad=37), want)
+    img = synth.binary_from_mask(mask)
+    wantf, _ = oracle.fill_holes(img, 8)
+    check(gpu_fill(img, 8, pad=13), wantf)
+
+
+def test_i32_full_range_fill():
+    rng = np.random.default_rng(5)
+    img = rng.integers(-2**31, 2**31, (150, 170), dtype=np.int64).astype(np.int32)
+    for conn in (4, 8):
+        want, _ = oracle.fill_holes(img, conn)
+        check(gpu_fill(img, conn), want)
+
+
+def test_counters_and_clip():
+    marker, mask = synth.make_tile(256, 256, 12, 1, "u8", 0.0)
+    marker = np.maximum(marker, 100).astype(np.uint8)  # many pixels above the mask
+    want, _ = oracle.recon_dilate(marker, mask, 8)
+    got, c = gpu_recon(marker, mask, 8, tune=dict(sweep_rounds=1, max_sweeps=1), counters=True)
+    check(got, want)
+    assert c["rounds"] == 1 and c["tiles"] >= 25
+    assert c["pops"] >= c["seeds"] > 0
+
+
+# ---------------------------------------------------------- workload sizes
+
+def test_workload_1024():
+    marker, mask = synth.single_1024()
+    want, _ = oracle.recon_dilate(marker, mask, 8)
+    check(gpu_recon(marker, mask, 8), want)
+
+
+@pytest.fixture(scope="module")
+def w4096():
+    return synth.single_4096()
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_workload_4096_recon(w4096, conn):
+    marker, mask, _ = w4096
+    want, _ = oracle.recon_dilate(marker, mask, conn)
+    check(gpu_recon(marker, mask, conn), want)
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_workload_4096_fill(w4096, conn):
+    img = w4096[2]
+    want, _ = oracle.fill_holes(img, conn)
+    check(gpu_fill(img, conn), want)
