@@ -69,7 +69,7 @@ enum { MR_OP_RECON = 0, MR_OP_FILL = 1 };
 /* Tuning knobs. A NULL mr_tune* means "use the defaults" (mr_default_tune).
  * No knob changes the result, only the time it takes. */
 typedef struct {
-    int32_t sweep_rounds;      /* tile rounds before the queue phase (>= 1);
+    int32_t sweep_rounds;      /* tile rounds before the queue phase (1..1000);
                                   a negative value runs tile rounds until no
                                   tile is dirty and skips the queue phase (the
                                   call then waits for the device between
@@ -123,6 +123,14 @@ int mr_fill_holes(void *img_inout, int64_t H, int64_t W, int64_t pitch, mr_dtype
 /* Copies the work counters held in a workspace to *out. Waits for `stream`.
  * Errors: MR_EINVAL (null pointer), MR_EHIP. */
 int mr_read_counters(const void *ws, mr_counters *out, void *stream);
+
+/* Tile visits per round of the last call that used a workspace: out[i] is
+ * the number of 64 x 64 tiles visited in round i + 1, and out[rounds] the
+ * number of tiles the seed pass started from (0 when the rounds converged).
+ * Writes min(cap, rounds + 1) entries, sets *n_rounds. Waits for `stream`.
+ * Errors: MR_EINVAL (null pointer, negative cap), MR_EHIP. */
+int mr_read_round_tiles(const void *ws, uint32_t *out, int32_t cap, int32_t *n_rounds,
+                        void *stream);
 
 /* Message for the last error returned to the calling thread ("" if none). */
 const char *mr_last_error(void);

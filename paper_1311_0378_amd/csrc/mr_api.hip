@@ -38,13 +38,29 @@ uint64_t next_pow2(uint64_t v) {
 
 // Spin budget of an idle queue wave before it gives up (a watchdog: the
 // queue always drains long before this on a working device).
-constexpr unsigned long long SPIN_CAP = 1ull << 24;
+constexpr unsigned long long SPIN_CAP = 1ull << 16;
+
+// Grid of the list-driven kernels (tile rounds after the first, seed): enough
+// 64-thread blocks to fill every SIMD twice over.
+int list_grid() {
+    static int g = 0;
+    if (!g) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            cus > 0)
+            g = cus * 8;
+        else
+            g = 2048;
+    }
+    return g;
+}
 
 // Where everything lives inside a workspace.
 struct Layout {
     int64_t n_tiles = 0;
     uint64_t ring_cap = 0;
-    size_t off_desc = 0, off_flags = 0, off_qflag = 0, off_bitmap = 0, off_ring = 0, off_plane = 0, total = 0;
+    size_t off_desc = 0, off_flags = 0, off_lists = 0, off_qflag = 0, off_bitmap = 0, off_ring = 0, off_plane = 0, total = 0;
     int64_t plane_pitch = 0;
 };
 
@@ -57,6 +73,8 @@ Layout layout_for(int64_t n_tiles, int64_t fill_plane_bytes, int64_t plane_pitch
     o = align_up(o + sizeof(ImgDesc), 256);
     L.off_flags = o;
     o = align_up(o + (size_t)n_tiles * 4, 256);
+    L.off_lists = o;
+    o = align_up(o + (size_t)n_tiles * 8, 256);
     L.off_qflag = o;
     o = align_up(o + (size_t)n_tiles * 4, 256);
     L.off_bitmap = o;
@@ -76,7 +94,8 @@ bool valid_dtype(int t) { return t == MR_U8 || t == MR_I32; }
 
 int check_tune(const mr_tune *tn) {
     if (!tn) return MR_OK;
-    if (tn->sweep_rounds == 0) return fail(MR_EINVAL, "tune.sweep_rounds must be >= 1 or negative");
+    if (tn->sweep_rounds == 0 || tn->sweep_rounds > MAX_ROUNDS)
+        return fail(MR_EINVAL, "tune.sweep_rounds must be in 1..%d, or negative", MAX_ROUNDS);
     if (tn->max_sweeps < 1 || tn->max_sweeps > 1024)
         return fail(MR_EINVAL, "tune.max_sweeps must be in 1..1024 (got %d)", tn->max_sweeps);
     if (tn->persistent_blocks < 0)
@@ -134,31 +153,35 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
     char *base = (char *)ws;
     Ctrl *ctrl = (Ctrl *)base;
     uint32_t *flags = (uint32_t *)(base + L.off_flags);
+    uint32_t *lists = (uint32_t *)(base + L.off_lists);
     uint32_t *qflag = (uint32_t *)(base + L.off_qflag);
     uint64_t *bitmap = (uint64_t *)(base + L.off_bitmap);
     uint32_t *ring = (uint32_t *)(base + L.off_ring);
+    const int grid = list_grid();
     hipError_t e;
 
-    if ((e = launch_clear_ctrl(ctrl, s)) != hipSuccess) return hip_fail(e, "clear");
-    if ((e = launch_clear_u32(flags, L.n_tiles, 0u, s)) != hipSuccess) return hip_fail(e, "clear");
-    if ((e = launch_clear_u32(ring, (int64_t)L.ring_cap, Q_EMPTY, s)) != hipSuccess)
+    if ((e = launch_clear_ctrl(ctrl, (uint32_t)L.n_tiles, s)) != hipSuccess)
         return hip_fail(e, "clear");
+    if ((e = launch_clear_u32(flags, L.n_tiles, 0u, s)) != hipSuccess) return hip_fail(e, "clear");
 
     uint32_t round = 1;
-    if ((e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, ctrl, round, 1,
-                               tn.max_sweeps, s)) != hipSuccess)
+    if ((e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl, round,
+                               tn.max_sweeps, grid, s)) != hipSuccess)
         return hip_fail(e, "tile round");
     if (tn.sweep_rounds > 0) {
         for (round = 2; round <= (uint32_t)tn.sweep_rounds; ++round)
-            if ((e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, ctrl, round, 0,
-                                       tn.max_sweeps, s)) != hipSuccess)
+            if ((e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl, round,
+                                       tn.max_sweeps, grid, s)) != hipSuccess)
                 return hip_fail(e, "tile round");
-        const uint32_t seed_round = (uint32_t)tn.sweep_rounds + 1;
         if ((e = launch_store_u64(&ctrl->rounds, (unsigned long long)tn.sweep_rounds, s)) !=
             hipSuccess)
             return hip_fail(e, "store");
-        if ((e = launch_seed(tbytes, conn, imgs, L.n_tiles, flags, seed_round, ctrl, bitmap,
-                             qflag, ring, L.ring_cap, s)) != hipSuccess)
+        if ((e = launch_clear_u32(qflag, L.n_tiles, 0u, s)) != hipSuccess ||
+            (e = launch_clear_u64(bitmap, L.n_tiles * TS, s)) != hipSuccess ||
+            (e = launch_clear_u32(ring, (int64_t)L.ring_cap, Q_EMPTY, s)) != hipSuccess)
+            return hip_fail(e, "clear");
+        if ((e = launch_seed(tbytes, conn, imgs, L.n_tiles, lists, round, ctrl, bitmap, qflag,
+                             ring, L.ring_cap, grid, s)) != hipSuccess)
             return hip_fail(e, "seed");
         int blocks = tn.persistent_blocks;
         const int maxb = queue_max_blocks(tbytes, conn);
@@ -168,24 +191,25 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
                               SPIN_CAP, s)) != hipSuccess)
             return hip_fail(e, "queue");
     } else {
-        // converge mode: rounds until no tile is dirty, polling every few rounds
+        // converge mode: rounds until a round leaves no dirty tile, polling
+        // the next round's list length every few rounds
         unsigned long long *hw = host_word();
         if (!hw) return fail(MR_EHIP, "cannot allocate a pinned host word");
-        const uint32_t max_rounds = 1u << 20;
-        const uint32_t poll = 4;
+        const uint32_t poll = 8;
         while (true) {
-            for (uint32_t k = 0; k < poll; ++k) {
+            for (uint32_t k = 0; k < poll && round < MAX_ROUNDS; ++k) {
                 ++round;
-                if ((e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, ctrl, round, 0,
-                                           tn.max_sweeps, s)) != hipSuccess)
+                if ((e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl,
+                                           round, tn.max_sweeps, grid, s)) != hipSuccess)
                     return hip_fail(e, "tile round");
             }
-            if ((e = hipMemcpyAsync(hw, &ctrl->mark.v, sizeof *hw, hipMemcpyDeviceToHost, s)) !=
-                hipSuccess)
+            *hw = 0;
+            if ((e = hipMemcpyAsync(hw, &ctrl->round_tiles[round + 1], sizeof(uint32_t),
+                                    hipMemcpyDeviceToHost, s)) != hipSuccess)
                 return hip_fail(e, "poll copy");
             if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "poll sync");
-            if (*hw <= round) break; // nothing marked for a round not yet run
-            if (round > max_rounds) return fail(MR_EHIP, "tile rounds did not converge");
+            if (*hw == 0) break;
+            if (round >= MAX_ROUNDS) return fail(MR_EHIP, "tile rounds did not converge");
         }
         if ((e = launch_store_u64(&ctrl->rounds, (unsigned long long)round, s)) != hipSuccess)
             return hip_fail(e, "store");
@@ -285,8 +309,9 @@ int mr_read_counters(const void *ws, mr_counters *out, void *stream) {
     mr_counters c{};
     c.rounds = h.rounds;
     c.seeds = h.seeds_total.v;
+    for (unsigned long long r = 1; r <= h.rounds && r <= (unsigned long long)MAX_ROUNDS; ++r)
+        c.tiles += h.round_tiles[r];
     for (int i = 0; i < NCNT; ++i) {
-        c.tiles += h.tiles[i];
         c.pops += h.pops[i];
         c.pushes += h.pushes[i];
         c.cas_retries += h.cas[i];
@@ -294,6 +319,20 @@ int mr_read_counters(const void *ws, mr_counters *out, void *stream) {
     }
     *out = c;
     if (h.watchdog) return fail(MR_EHIP, "a queue workgroup hit its spin cap");
+    return MR_OK;
+}
+
+int mr_read_round_tiles(const void *ws, uint32_t *out, int32_t cap, int32_t *n_rounds,
+                        void *stream) {
+    g_err.clear();
+    if (!ws || !n_rounds || (cap > 0 && !out) || cap < 0) return fail(MR_EINVAL, "bad pointer or cap");
+    Ctrl h;
+    hipError_t e = hipMemcpyAsync(&h, ws, sizeof h, hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "copy");
+    if ((e = hipStreamSynchronize((hipStream_t)stream)) != hipSuccess) return hip_fail(e, "sync");
+    const int n = (int)std::min<unsigned long long>(h.rounds + 1, MAX_ROUNDS);
+    *n_rounds = (int32_t)h.rounds;
+    for (int i = 0; i < cap && i < n; ++i) out[i] = h.round_tiles[i + 1];
     return MR_OK;
 }
 

@@ -39,7 +39,8 @@ struct alignas(128) Line {
     unsigned long long pad[15];
 };
 
-constexpr int NCNT = 64; // spread counters, summed on the host
+constexpr int NCNT = 64;      // spread counters, summed on the host
+constexpr int MAX_ROUNDS = 1000; // tile rounds per call (sweep_rounds bound)
 
 struct Ctrl {
     Line q_head;     // frontier ring: next entry to claim
@@ -55,6 +56,10 @@ struct Ctrl {
     unsigned long long ovf[NCNT];    // overflowed pushes (spread)
     unsigned long long rounds;       // written by the host sequence
     unsigned long long watchdog;     // non-zero if a queue block hit its spin cap
+    // round_tiles[r]: tiles in the dirty list of round r (round 1 = all tiles,
+    // written by the host sequence); round_tiles[k+1] is what the seed pass
+    // starts from after k rounds.
+    uint32_t round_tiles[MAX_ROUNDS + 2];
 };
 
 // Launch-wide view of the images: a device array of descriptors sorted by
@@ -68,13 +73,17 @@ constexpr uint32_t Q_EMPTY = 0xFFFFFFFFu;
 
 // Host-side launchers (defined in mr_kernels.hip).
 hipError_t launch_clear_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
-hipError_t launch_clear_ctrl(Ctrl *c, hipStream_t s);
+hipError_t launch_clear_ctrl(Ctrl *c, uint32_t first_round_tiles, hipStream_t s);
+// Round r reads the dirty list lists[(r & 1) * n_tiles ...] of length
+// ctrl->round_tiles[r] (round 1: every tile, no list) and appends the tiles it
+// dirties to the other half for round r + 1.
 hipError_t launch_tile_round(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
-                             uint32_t *flags, Ctrl *ctrl, uint32_t round, int first,
-                             int max_iters, hipStream_t s);
+                             uint32_t *flags, uint32_t *lists, Ctrl *ctrl, uint32_t round,
+                             int max_iters, int grid, hipStream_t s);
 hipError_t launch_seed(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
-                       const uint32_t *flags, uint32_t round, Ctrl *ctrl, uint64_t *bitmap,
-                       uint32_t *qflag, uint32_t *ring, uint64_t cap, hipStream_t s);
+                       const uint32_t *lists, uint32_t round, Ctrl *ctrl, uint64_t *bitmap,
+                       uint32_t *qflag, uint32_t *ring, uint64_t cap, int grid, hipStream_t s);
+hipError_t launch_clear_u64(uint64_t *p, int64_t n, hipStream_t s);
 hipError_t launch_queue(int tbytes, int conn, const Imgs &imgs, Ctrl *ctrl, uint64_t *bitmap,
                         uint32_t *qflag, uint32_t *ring, uint64_t cap, int blocks,
                         unsigned long long spin_cap, hipStream_t s);

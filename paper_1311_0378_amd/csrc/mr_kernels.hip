@@ -206,18 +206,25 @@ __device__ __forceinline__ uint64_t col_sum(const uint32_t (&A)[TS]) {
     return s;
 }
 
-__device__ __forceinline__ void mark(uint32_t *flags, const ImgDesc &d, int ty, int tx,
-                                     uint32_t val) {
+// Put tile (ty, tx) of image d on the dirty list of round `nxt`, once:
+// flags hold the latest round a tile is listed for.
+__device__ __forceinline__ void mark(uint32_t *flags, uint32_t *list_out, Ctrl *ctrl,
+                                     const ImgDesc &d, int ty, int tx, uint32_t nxt) {
     if (ty < 0 || ty >= d.nty || tx < 0 || tx >= d.ntx) return;
-    flags[d.tile_base + (int64_t)ty * d.ntx + tx] = val;
+    const int64_t nb = d.tile_base + (int64_t)ty * d.ntx + tx;
+    if (atomicMax(flags + nb, nxt) < nxt) {
+        const uint32_t i = atomicAdd(&ctrl->round_tiles[nxt], 1u);
+        list_out[i] = (uint32_t)nb;
+    }
 }
 
 // One visit of one tile: load, sweep to a local fixed point (or the cap),
 // store, and mark the neighbours whose halo changed.
 template <typename T, int CONN, bool FILL, bool INITIAL>
 __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane,
-                                           uint32_t *__restrict__ flags, Ctrl *__restrict__ ctrl,
-                                           uint32_t round, int max_iters,
+                                           uint32_t *__restrict__ flags,
+                                           uint32_t *__restrict__ list_out,
+                                           Ctrl *__restrict__ ctrl, uint32_t round, int max_iters,
                                            uint32_t (*tb)[TS + 1]) {
     using P = Pix<T>;
     constexpr bool first = INITIAL;
@@ -269,7 +276,6 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
             }
         }
     }
-    if (lane == 0) atomicAdd(&ctrl->tiles[t & (NCNT - 1)], 1ull);
     if (!changed && stable) return;
 
     const uint64_t col_out = col_prev;
@@ -279,44 +285,51 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
     if (lane == 0) {
         const uint32_t nxt = round + 1;
         const bool left = (bc >> 1) & 1, right = (bc >> (TS - 2)) & 1;
-        bool any = !stable;
-        if (!stable) mark(flags, d, ty, tx, nxt);
-        if (bt) { mark(flags, d, ty - 1, tx, nxt); any = true; }
-        if (bb) { mark(flags, d, ty + 1, tx, nxt); any = true; }
-        if (left) { mark(flags, d, ty, tx - 1, nxt); any = true; }
-        if (right) { mark(flags, d, ty, tx + 1, nxt); any = true; }
+        if (!stable) mark(flags, list_out, ctrl, d, ty, tx, nxt);
+        if (bt) mark(flags, list_out, ctrl, d, ty - 1, tx, nxt);
+        if (bb) mark(flags, list_out, ctrl, d, ty + 1, tx, nxt);
+        if (left) mark(flags, list_out, ctrl, d, ty, tx - 1, nxt);
+        if (right) mark(flags, list_out, ctrl, d, ty, tx + 1, nxt);
         if (CONN == 8) {
-            if ((bt >> 1) & 1) mark(flags, d, ty - 1, tx - 1, nxt);
-            if ((bt >> (TS - 2)) & 1) mark(flags, d, ty - 1, tx + 1, nxt);
-            if ((bb >> 1) & 1) mark(flags, d, ty + 1, tx - 1, nxt);
-            if ((bb >> (TS - 2)) & 1) mark(flags, d, ty + 1, tx + 1, nxt);
-        }
-        if (any) {
-            unsigned long long *m = &ctrl->mark.v;
-            if (__hip_atomic_load(m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < nxt)
-                __hip_atomic_fetch_max(m, (unsigned long long)nxt, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
+            if ((bt >> 1) & 1) mark(flags, list_out, ctrl, d, ty - 1, tx - 1, nxt);
+            if ((bt >> (TS - 2)) & 1) mark(flags, list_out, ctrl, d, ty - 1, tx + 1, nxt);
+            if ((bb >> 1) & 1) mark(flags, list_out, ctrl, d, ty + 1, tx - 1, nxt);
+            if ((bb >> (TS - 2)) & 1) mark(flags, list_out, ctrl, d, ty + 1, tx + 1, nxt);
         }
     }
 }
 
-// One tile round. Grid: one 64-thread block per tile of the launch.
+// One tile round. Round 1 runs one 64-thread block per tile of the launch;
+// later rounds run a fixed grid that strides over the round's dirty list.
 template <typename T, int CONN>
-__global__ __launch_bounds__(64) void k_tile_round(Imgs imgs, uint32_t *__restrict__ flags,
+__global__ __launch_bounds__(64) void k_tile_round(Imgs imgs, int64_t n_tiles,
+                                                   uint32_t *__restrict__ flags,
+                                                   uint32_t *__restrict__ lists,
                                                    Ctrl *__restrict__ ctrl, uint32_t round,
-                                                   int first, int max_iters) {
+                                                   int max_iters) {
     __shared__ uint32_t tb[TS][TS + 1]; // transpose buffer
-    const int64_t t = blockIdx.x;
     const int lane = threadIdx.x;
-    if (!first && flags[t] < round) return;
-    const ImgDesc d = load_desc(imgs, t);
-    if (d.done) return;
-    if (d.op == MR_OP_FILL) {
-        if (first) visit_tile<T, CONN, true, true>(d, t, lane, flags, ctrl, round, max_iters, tb);
-        else visit_tile<T, CONN, true, false>(d, t, lane, flags, ctrl, round, max_iters, tb);
-    } else {
-        if (first) visit_tile<T, CONN, false, true>(d, t, lane, flags, ctrl, round, max_iters, tb);
-        else visit_tile<T, CONN, false, false>(d, t, lane, flags, ctrl, round, max_iters, tb);
+    uint32_t *list_out = lists + ((round + 1) & 1) * n_tiles;
+    if (round == 1) {
+        const int64_t t = blockIdx.x;
+        const ImgDesc d = load_desc(imgs, t);
+        if (d.done) return;
+        if (d.op == MR_OP_FILL)
+            visit_tile<T, CONN, true, true>(d, t, lane, flags, list_out, ctrl, round, max_iters, tb);
+        else
+            visit_tile<T, CONN, false, true>(d, t, lane, flags, list_out, ctrl, round, max_iters, tb);
+        return;
+    }
+    const uint32_t *list_in = lists + (round & 1) * n_tiles;
+    const uint32_t n = ctrl->round_tiles[round];
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const int64_t t = list_in[i];
+        const ImgDesc d = load_desc(imgs, t);
+        if (d.done) continue;
+        if (d.op == MR_OP_FILL)
+            visit_tile<T, CONN, true, false>(d, t, lane, flags, list_out, ctrl, round, max_iters, tb);
+        else
+            visit_tile<T, CONN, false, false>(d, t, lane, flags, list_out, ctrl, round, max_iters, tb);
     }
 }
 
@@ -377,77 +390,69 @@ __device__ __forceinline__ uint32_t ring_pop(Ctrl *ctrl, uint32_t *ring, uint64_
 // pixel takes min(I, max of J over itself and its neighbours). Raised pixels
 // are stored, their bits form the tile's frontier bitmap rows, and the tile
 // enters the ring. Tiles that are not dirty only clear their bitmap and flag.
-template <typename T>
-__device__ __forceinline__ void load_row(const ImgDesc &d, int64_t gy, int64_t gx, bool frozen,
-                                         uint32_t &j, uint32_t &i) {
+template <typename T, int CONN, bool FILL>
+__device__ __forceinline__ void seed_tile(const ImgDesc &d, int64_t t, int lane, Ctrl *ctrl,
+                                          uint64_t *bitmap, uint32_t *qflag, uint32_t *ring,
+                                          uint64_t cap) {
     using P = Pix<T>;
-    j = 0;
-    i = 0;
-    if (gx >= 0 && gx < d.W && gy >= 0 && gy < d.H) {
-        j = P::key(((cgptr<T>)d.J)[gy * d.pJ + gx]);
-        i = P::key(((cgptr<T>)d.I)[gy * d.pI + gx]);
-        if (d.op == MR_OP_FILL) i = P::KMAX - i;
-    }
-    if (frozen) i = j;
-}
-
-template <typename T, int CONN>
-__global__ __launch_bounds__(64) void k_seed(Imgs imgs, const uint32_t *__restrict__ flags,
-                                             uint32_t round, Ctrl *__restrict__ ctrl,
-                                             uint64_t *__restrict__ bitmap,
-                                             uint32_t *__restrict__ qflag,
-                                             uint32_t *__restrict__ ring, uint64_t cap) {
-    using P = Pix<T>;
-    const int64_t t = blockIdx.x;
-    const int lane = threadIdx.x;
-    const ImgDesc d = load_desc(imgs, t);
-    if (d.done || flags[t] < round) {
-        bitmap[t * TS + lane] = 0;
-        if (lane == 0) qflag[t] = 0;
-        return;
-    }
     const int64_t lt = t - d.tile_base;
     const int ty = (int)(lt / d.ntx), tx = (int)(lt - (int64_t)ty * d.ntx);
     const int64_t gy0 = (int64_t)ty * TI - 1, gx = (int64_t)tx * TI - 1 + lane;
-    const bool halo_lane = lane == 0 || lane == TS - 1;
-
-    uint32_t jp, ip, jc, ic, jn, in_;
-    load_row<T>(d, gy0, gx, true, jp, ip);
-    load_row<T>(d, gy0 + 1, gx, halo_lane, jc, ic);
+    uint32_t J[TS], I[TS];
+    load_tile<T, FILL, false>(d, gy0, gx, lane, J, I);
     uint64_t myrow = 0; // lane r ends up holding row r's bits
     uint32_t nseed = 0;
     gptr<T> Jw = (gptr<T>)d.J;
+    uint32_t off = (uint32_t)gy0 * (uint32_t)d.pJ + (uint32_t)gx;
+#pragma unroll
     for (int r = 1; r < TS - 1; ++r) {
-        load_row<T>(d, gy0 + r + 1, gx, halo_lane || r + 1 == TS - 1, jn, in_);
-        uint32_t n = max(jp, jn);
-        n = max(n, max(from_lower_lane(jc), from_upper_lane(jc)));
+        off += (uint32_t)d.pJ;
+        uint32_t n = max(J[r - 1], J[r + 1]);
+        n = max(n, max(from_lower_lane(J[r]), from_upper_lane(J[r])));
         if (CONN == 8) {
-            n = max(n, max(from_lower_lane(jp), from_upper_lane(jp)));
-            n = max(n, max(from_lower_lane(jn), from_upper_lane(jn)));
+            n = max(n, max(from_lower_lane(J[r - 1]), from_upper_lane(J[r - 1])));
+            n = max(n, max(from_lower_lane(J[r + 1]), from_upper_lane(J[r + 1])));
         }
-        const uint32_t v = min(max(jc, n), ic);
-        const bool raised = v > jc; // frozen lanes and outside pixels have I == J
+        const uint32_t v = min(max(J[r], n), I[r]);
+        const bool raised = v > J[r]; // frozen halo and outside pixels have I == J
         const uint64_t bits = __ballot(raised);
-        if (raised) Jw[(gy0 + r) * d.pJ + gx] = P::val(v);
+        if (raised) Jw[off] = P::val(v);
         if (lane == r) myrow = bits;
         nseed += (uint32_t)__popcll(bits);
-        jp = jc;
-        jc = jn;
-        ic = in_;
     }
     bitmap[t * TS + lane] = myrow;
-    if (lane == 0) {
-        if (nseed) {
-            qflag[t] = 1;
-            __hip_atomic_fetch_add(&ctrl->seeds_total.v, (unsigned long long)nseed,
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            qflag[t] = 0;
-        }
+    if (lane == 0 && nseed) {
+        qflag[t] = 1;
+        __hip_atomic_fetch_add(&ctrl->seeds_total.v, (unsigned long long)nseed,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ring_push(ctrl, ring, cap, (uint32_t)t);
     }
-    // the bitmap rows must be visible before the tile can be popped
-    __threadfence();
-    if (lane == 0 && nseed) ring_push(ctrl, ring, cap, (uint32_t)t);
+}
+
+// One relaxation step over each tile on the dirty list of `round` (the
+// round after the last one run): every interior pixel takes min(I, max of J
+// over itself and its neighbours). Raised pixels are stored, their bits form
+// the tile's rows of the frontier bitmap (one ballot per row), and the tile
+// enters the frontier ring. The bitmap and flags start cleared.
+template <typename T, int CONN>
+__global__ __launch_bounds__(64) void k_seed(Imgs imgs, int64_t n_tiles,
+                                             const uint32_t *__restrict__ lists, uint32_t round,
+                                             Ctrl *__restrict__ ctrl,
+                                             uint64_t *__restrict__ bitmap,
+                                             uint32_t *__restrict__ qflag,
+                                             uint32_t *__restrict__ ring, uint64_t cap) {
+    const int lane = threadIdx.x;
+    const uint32_t *list_in = lists + (round & 1) * n_tiles;
+    const uint32_t n = ctrl->round_tiles[round];
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const int64_t t = list_in[i];
+        const ImgDesc d = load_desc(imgs, t);
+        if (d.done) continue;
+        if (d.op == MR_OP_FILL)
+            seed_tile<T, CONN, true>(d, t, lane, ctrl, bitmap, qflag, ring, cap);
+        else
+            seed_tile<T, CONN, false>(d, t, lane, ctrl, bitmap, qflag, ring, cap);
+    }
 }
 
 // ------------------------------------------------------------------- queue
@@ -524,7 +529,9 @@ __global__ __launch_bounds__(64 * QWAVES) void k_queue(Imgs imgs, Ctrl *__restri
                 if (lane == 0) atomicAdd(&ctrl->watchdog, 1ull);
                 break;
             }
-            __builtin_amdgcn_s_sleep(8);
+            // back off so idle waves do not crowd the ring counters
+            const unsigned long long nap = idle < 6 ? (1ull << idle) : 64;
+            for (unsigned long long k = 0; k < nap; ++k) __builtin_amdgcn_s_sleep(32);
             continue;
         }
         idle = 0;
@@ -613,10 +620,12 @@ __global__ void k_clear_u32(uint32_t *p, int64_t n, uint32_t v) {
         p[i] = v;
 }
 
-__global__ void k_clear_ctrl(Ctrl *c) {
+__global__ void k_clear_ctrl(Ctrl *c, uint32_t first_round_tiles) {
     unsigned long long *p = (unsigned long long *)c;
     const int n = (int)(sizeof(Ctrl) / sizeof(unsigned long long));
     for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) c->round_tiles[1] = first_round_tiles;
 }
 
 // Fill-holes epilogue: out = NOT J over the interior of every tile of the
@@ -654,46 +663,61 @@ hipError_t launch_clear_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_clear_ctrl(Ctrl *c, hipStream_t s) {
-    hipLaunchKernelGGL(k_clear_ctrl, dim3(1), dim3(256), 0, s, c);
+hipError_t launch_clear_ctrl(Ctrl *c, uint32_t first_round_tiles, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_ctrl, dim3(1), dim3(256), 0, s, c, first_round_tiles);
     return hipGetLastError();
 }
 
 template <typename T, int CONN>
-static hipError_t tile_round_t(const Imgs &imgs, int64_t n_tiles, uint32_t *flags, Ctrl *ctrl,
-                               uint32_t round, int first, int max_iters, hipStream_t s) {
-    hipLaunchKernelGGL((k_tile_round<T, CONN>), dim3((unsigned)n_tiles), dim3(64), 0, s, imgs,
-                       flags, ctrl, round, first, max_iters);
+static hipError_t tile_round_t(const Imgs &imgs, int64_t n_tiles, uint32_t *flags,
+                               uint32_t *lists, Ctrl *ctrl, uint32_t round, int max_iters,
+                               int grid, hipStream_t s) {
+    const unsigned g = round == 1 ? (unsigned)n_tiles : (unsigned)grid;
+    hipLaunchKernelGGL((k_tile_round<T, CONN>), dim3(g), dim3(64), 0, s, imgs, n_tiles, flags,
+                       lists, ctrl, round, max_iters);
     return hipGetLastError();
 }
 
 hipError_t launch_tile_round(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
-                             uint32_t *flags, Ctrl *ctrl, uint32_t round, int first,
-                             int max_iters, hipStream_t s) {
+                             uint32_t *flags, uint32_t *lists, Ctrl *ctrl, uint32_t round,
+                             int max_iters, int grid, hipStream_t s) {
     if (tbytes == 1)
-        return conn == 8 ? tile_round_t<uint8_t, 8>(imgs, n_tiles, flags, ctrl, round, first, max_iters, s)
-                         : tile_round_t<uint8_t, 4>(imgs, n_tiles, flags, ctrl, round, first, max_iters, s);
-    return conn == 8 ? tile_round_t<int32_t, 8>(imgs, n_tiles, flags, ctrl, round, first, max_iters, s)
-                     : tile_round_t<int32_t, 4>(imgs, n_tiles, flags, ctrl, round, first, max_iters, s);
+        return conn == 8 ? tile_round_t<uint8_t, 8>(imgs, n_tiles, flags, lists, ctrl, round, max_iters, grid, s)
+                         : tile_round_t<uint8_t, 4>(imgs, n_tiles, flags, lists, ctrl, round, max_iters, grid, s);
+    return conn == 8 ? tile_round_t<int32_t, 8>(imgs, n_tiles, flags, lists, ctrl, round, max_iters, grid, s)
+                     : tile_round_t<int32_t, 4>(imgs, n_tiles, flags, lists, ctrl, round, max_iters, grid, s);
 }
 
 template <typename T, int CONN>
-static hipError_t seed_t(const Imgs &imgs, int64_t n_tiles, const uint32_t *flags,
+static hipError_t seed_t(const Imgs &imgs, int64_t n_tiles, const uint32_t *lists,
                          uint32_t round, Ctrl *ctrl, uint64_t *bitmap, uint32_t *qflag,
-                         uint32_t *ring, uint64_t cap, hipStream_t s) {
-    hipLaunchKernelGGL((k_seed<T, CONN>), dim3((unsigned)n_tiles), dim3(64), 0, s, imgs, flags,
-                       round, ctrl, bitmap, qflag, ring, cap);
+                         uint32_t *ring, uint64_t cap, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_seed<T, CONN>), dim3((unsigned)grid), dim3(64), 0, s, imgs, n_tiles,
+                       lists, round, ctrl, bitmap, qflag, ring, cap);
     return hipGetLastError();
 }
 
 hipError_t launch_seed(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
-                       const uint32_t *flags, uint32_t round, Ctrl *ctrl, uint64_t *bitmap,
-                       uint32_t *qflag, uint32_t *ring, uint64_t cap, hipStream_t s) {
+                       const uint32_t *lists, uint32_t round, Ctrl *ctrl, uint64_t *bitmap,
+                       uint32_t *qflag, uint32_t *ring, uint64_t cap, int grid, hipStream_t s) {
     if (tbytes == 1)
-        return conn == 8 ? seed_t<uint8_t, 8>(imgs, n_tiles, flags, round, ctrl, bitmap, qflag, ring, cap, s)
-                         : seed_t<uint8_t, 4>(imgs, n_tiles, flags, round, ctrl, bitmap, qflag, ring, cap, s);
-    return conn == 8 ? seed_t<int32_t, 8>(imgs, n_tiles, flags, round, ctrl, bitmap, qflag, ring, cap, s)
-                     : seed_t<int32_t, 4>(imgs, n_tiles, flags, round, ctrl, bitmap, qflag, ring, cap, s);
+        return conn == 8 ? seed_t<uint8_t, 8>(imgs, n_tiles, lists, round, ctrl, bitmap, qflag, ring, cap, grid, s)
+                         : seed_t<uint8_t, 4>(imgs, n_tiles, lists, round, ctrl, bitmap, qflag, ring, cap, grid, s);
+    return conn == 8 ? seed_t<int32_t, 8>(imgs, n_tiles, lists, round, ctrl, bitmap, qflag, ring, cap, grid, s)
+                     : seed_t<int32_t, 4>(imgs, n_tiles, lists, round, ctrl, bitmap, qflag, ring, cap, grid, s);
+}
+
+__global__ void k_clear_u64(uint64_t *p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+hipError_t launch_clear_u64(uint64_t *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_clear_u64, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+    return hipGetLastError();
 }
 
 template <typename T, int CONN>

@@ -68,6 +68,9 @@ def lib():
         L.mr_fill_holes.restype = c_int
         L.mr_read_counters.argtypes = [vp, ctypes.POINTER(Counters), vp]
         L.mr_read_counters.restype = c_int
+        L.mr_read_round_tiles.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), i32,
+                                          ctypes.POINTER(i32), vp]
+        L.mr_read_round_tiles.restype = c_int
         L.mr_last_error.argtypes = []
         L.mr_last_error.restype = ctypes.c_char_p
         L.mr_abi_version.argtypes = []
@@ -164,6 +167,17 @@ def fill_holes(img: torch.Tensor, conn: int = 8, tune=None,
     _check(lib().mr_fill_holes(img.data_ptr(), H, W, pitch, t, conn, workspace.data_ptr(),
                                workspace.numel(), _tune_ptr(tune), _stream_ptr(stream)))
     return img
+
+
+def read_round_tiles(workspace: torch.Tensor, stream=None) -> list:
+    """Tile visits per round of the last call that used ``workspace``; the
+    last entry is the number of tiles the seed pass started from."""
+    cap = 1001
+    buf = (ctypes.c_uint32 * cap)()
+    n = ctypes.c_int32()
+    _check(lib().mr_read_round_tiles(workspace.data_ptr(), buf, cap, ctypes.byref(n),
+                                     _stream_ptr(stream)))
+    return [int(buf[i]) for i in range(min(cap, n.value + 1))]
 
 
 def read_counters(workspace: torch.Tensor, stream=None) -> dict:
