@@ -91,6 +91,8 @@ typedef struct {
     uint64_t cas_retries; /* failed compare-and-swap attempts (u8 updates) */
     uint64_t overflows;   /* entries that did not fit the device ring and were
                              handed back to tile rounds (never an error) */
+    uint64_t sweeps;      /* sweep iterations summed over all tile visits (one
+                             iteration = down, up, right and left sweeps) */
 } mr_counters;
 
 /* Fills *out with the default knobs. */

@@ -40,9 +40,9 @@ uint64_t next_pow2(uint64_t v) {
 // queue always drains long before this on a working device).
 constexpr unsigned long long SPIN_CAP = 1ull << 16;
 
-// Grid of the list-driven kernels (tile rounds after the first, seed): enough
-// 64-thread blocks to fill every SIMD twice over.
-int list_grid() {
+// Grid of the flag-scanning kernels (tile rounds after the first, seed):
+// enough 64-thread blocks to fill every SIMD twice over.
+int scan_grid() {
     static int g = 0;
     if (!g) {
         int dev = 0, cus = 0;
@@ -60,7 +60,7 @@ int list_grid() {
 struct Layout {
     int64_t n_tiles = 0;
     uint64_t ring_cap = 0;
-    size_t off_desc = 0, off_flags = 0, off_lists = 0, off_qflag = 0, off_bitmap = 0, off_ring = 0, off_plane = 0, total = 0;
+    size_t off_desc = 0, off_flags = 0, off_qflag = 0, off_bitmap = 0, off_ring = 0, off_plane = 0, total = 0;
     int64_t plane_pitch = 0;
 };
 
@@ -73,8 +73,6 @@ Layout layout_for(int64_t n_tiles, int64_t fill_plane_bytes, int64_t plane_pitch
     o = align_up(o + sizeof(ImgDesc), 256);
     L.off_flags = o;
     o = align_up(o + (size_t)n_tiles * 4, 256);
-    L.off_lists = o;
-    o = align_up(o + (size_t)n_tiles * 8, 256);
     L.off_qflag = o;
     o = align_up(o + (size_t)n_tiles * 4, 256);
     L.off_bitmap = o;
@@ -118,7 +116,7 @@ int check_image(int op, int64_t H, int64_t W, int64_t pitch, int t, int conn) {
     // kernels address a plane with 32-bit element offsets
     const int64_t p = pitch ? pitch : W;
     const int64_t pp = (W + 63) / 64 * 64;
-    if (H * std::max(p, pp) >= (1ll << 32))
+    if (H * std::max(p, pp) + 4 >= (1ll << 32))
         return fail(MR_EINVAL, "image plane too large: H * pitch must stay below 2^32 elements");
     return MR_OK;
 }
@@ -153,11 +151,10 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
     char *base = (char *)ws;
     Ctrl *ctrl = (Ctrl *)base;
     uint32_t *flags = (uint32_t *)(base + L.off_flags);
-    uint32_t *lists = (uint32_t *)(base + L.off_lists);
     uint32_t *qflag = (uint32_t *)(base + L.off_qflag);
     uint64_t *bitmap = (uint64_t *)(base + L.off_bitmap);
     uint32_t *ring = (uint32_t *)(base + L.off_ring);
-    const int grid = list_grid();
+    const int grid = scan_grid();
     hipError_t e;
 
     if ((e = launch_clear_ctrl(ctrl, (uint32_t)L.n_tiles, s)) != hipSuccess)
@@ -165,12 +162,12 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
     if ((e = launch_clear_u32(flags, L.n_tiles, 0u, s)) != hipSuccess) return hip_fail(e, "clear");
 
     uint32_t round = 1;
-    if ((e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl, round,
+    if ((e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, ctrl, round,
                                tn.max_sweeps, grid, s)) != hipSuccess)
         return hip_fail(e, "tile round");
     if (tn.sweep_rounds > 0) {
         for (round = 2; round <= (uint32_t)tn.sweep_rounds; ++round)
-            if ((e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl, round,
+            if ((e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, ctrl, round,
                                        tn.max_sweeps, grid, s)) != hipSuccess)
                 return hip_fail(e, "tile round");
         if ((e = launch_store_u64(&ctrl->rounds, (unsigned long long)tn.sweep_rounds, s)) !=
@@ -180,7 +177,7 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
             (e = launch_clear_u64(bitmap, L.n_tiles * TS, s)) != hipSuccess ||
             (e = launch_clear_u32(ring, (int64_t)L.ring_cap, Q_EMPTY, s)) != hipSuccess)
             return hip_fail(e, "clear");
-        if ((e = launch_seed(tbytes, conn, imgs, L.n_tiles, lists, round, ctrl, bitmap, qflag,
+        if ((e = launch_seed(tbytes, conn, imgs, L.n_tiles, flags, round, ctrl, bitmap, qflag,
                              ring, L.ring_cap, grid, s)) != hipSuccess)
             return hip_fail(e, "seed");
         int blocks = tn.persistent_blocks;
@@ -192,19 +189,19 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
             return hip_fail(e, "queue");
     } else {
         // converge mode: rounds until a round leaves no dirty tile, polling
-        // the next round's list length every few rounds
+        // every few rounds
         unsigned long long *hw = host_word();
         if (!hw) return fail(MR_EHIP, "cannot allocate a pinned host word");
         const uint32_t poll = 8;
         while (true) {
             for (uint32_t k = 0; k < poll && round < MAX_ROUNDS; ++k) {
                 ++round;
-                if ((e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl,
-                                           round, tn.max_sweeps, grid, s)) != hipSuccess)
+                if ((e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, ctrl, round,
+                                           tn.max_sweeps, grid, s)) != hipSuccess)
                     return hip_fail(e, "tile round");
             }
             *hw = 0;
-            if ((e = hipMemcpyAsync(hw, &ctrl->round_tiles[round + 1], sizeof(uint32_t),
+            if ((e = hipMemcpyAsync(hw, &ctrl->marked[round + 1], sizeof(uint32_t),
                                     hipMemcpyDeviceToHost, s)) != hipSuccess)
                 return hip_fail(e, "poll copy");
             if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "poll sync");
@@ -316,6 +313,7 @@ int mr_read_counters(const void *ws, mr_counters *out, void *stream) {
         c.pushes += h.pushes[i];
         c.cas_retries += h.cas[i];
         c.overflows += h.ovf[i];
+        c.sweeps += h.iters[i];
     }
     *out = c;
     if (h.watchdog) return fail(MR_EHIP, "a queue workgroup hit its spin cap");

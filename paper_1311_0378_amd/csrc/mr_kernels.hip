@@ -13,7 +13,7 @@
 //    diagonal neighbours taken from the adjacent lanes by DPP; the tile is
 //    transposed through LDS for the right and left sweeps. Sweeps repeat until
 //    the tile is stable, then the interior is stored and the tiles whose halo
-//    changed are marked dirty for the next round.
+//    changed are marked dirty for the next round, which visits only those.
 //  * k_seed -- one relaxation step over each tile still dirty after the last
 //    round; every raised pixel is compacted by wave ballot into the tile's row
 //    of the frontier bitmap, and the tile into the device frontier ring.
@@ -110,24 +110,105 @@ template <> struct Atom<uint8_t> {
 // ------------------------------------------------------------------ tiles
 
 
+// Buffer resource over one uint8 plane of `bytes` bytes, used only when the
+// plane base and pitch are multiples of 16, so every 16-byte chunk load is
+// aligned and the per-dword range check matches whole memory words. Loads past
+// the end, or at the huge offsets used for rows outside the image, return 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *p, uint64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0,
+                                             (int)(uint32_t)min<uint64_t>(bytes, 0xFFFFFFF0ull),
+                                             0x00020000);
+}
+
+__device__ __forceinline__ bool stage_ok(const void *p, int64_t pitch) {
+    return ((uintptr_t)p & 15) == 0 && (pitch & 15) == 0;
+}
+
+// uint8 staging: row r of a tile (image row gy0 + r) is fetched as five
+// 16-byte chunks covering image columns a .. a+79, a = gx0 rounded down to 16,
+// and kept in LDS at r * SROW. SROW is an odd number of dwords, so column
+// reads (lane = column) and row reads (lane = row) are both free of bank
+// conflicts.
+constexpr int SROW = 84;
+constexpr int STAGE_BYTES = TS * SROW;
+static_assert(2 * STAGE_BYTES <= TS * (TS + 1) * 4, "the stage must fit in the transpose buffer");
+
+__device__ __forceinline__ void stage_u8(__amdgpu_buffer_rsrc_t rs, int64_t gy0, int64_t H,
+                                         uint32_t pitch, int64_t a, int lane, uint8_t *st) {
+    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+    v4u v[5];
+    int base[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const int q = k * 64 + lane;
+        const int row = q / 5, ch = q - row * 5;
+        const int64_t gy = gy0 + row;
+        const int64_t off = gy * (int64_t)pitch + a + ch * 16;
+        const bool in = gy >= 0 && gy < H && off >= 0;
+        v[k] = __builtin_amdgcn_raw_buffer_load_b128(rs, in ? (uint32_t)off : 0xFFFFFFF0u, 0, 0);
+        base[k] = row * SROW + ch * 16;
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        uint32_t *w = (uint32_t *)(st + base[k]);
+        w[0] = v[k].x;
+        w[1] = v[k].y;
+        w[2] = v[k].z;
+        w[3] = v[k].w;
+    }
+}
+
 // Load one 64 x 64 register tile. INITIAL builds the starting working image
 // (reconstruction: min(marker, mask); fill-holes: the complement on the image
 // border and the minimum inside) instead of reading it; FILL reads the input
-// image and complements it into the mask. Every load is issued unconditionally
-// from a clamped, in-bounds address and outside pixels are replaced by key 0
-// afterwards, so all loads of the tile can be in flight together. The halo
-// ring gets I = J, which freezes it: min(max(J, n), J) = J.
+// image and complements it into the mask. Outside pixels become key 0. The
+// halo ring gets I = J, which freezes it: min(max(J, n), J) = J.
+// uint8 tiles whose planes are 16-byte aligned are staged through LDS
+// (`stage`, at least 2 * STAGE_BYTES); other uint8 planes and int32 rows (which
+// are already 256-byte coalesced loads) go straight to registers from
+// clamped, in-bounds addresses.
 template <typename T, bool FILL, bool INITIAL>
 __device__ __forceinline__ void load_tile(const ImgDesc &d, int64_t gy0, int64_t gx, int lane,
-                                          uint32_t (&J)[TS], uint32_t (&I)[TS]) {
+                                          uint32_t (&J)[TS], uint32_t (&I)[TS], uint8_t *stage) {
     using P = Pix<T>;
-    cgptr<T> Jp = (cgptr<T>)d.J;
-    cgptr<T> Ip = (cgptr<T>)d.I;
     const int64_t H = d.H, W = d.W;
     const bool xin = gx >= 0 && gx < W;
-    const uint32_t xc = (uint32_t)min(max(gx, (int64_t)0), W - 1);
     const bool halo_lane = lane == 0 || lane == TS - 1;
-    const bool xedge = xc == 0 || xc == (uint32_t)(W - 1);
+    const bool xedge = gx == 0 || gx == W - 1;
+    if (sizeof(T) == 1 && stage_ok(d.I, d.pI) && stage_ok(d.J, d.pJ)) {
+        const int64_t gx0 = gx - lane;
+        const int64_t a = gx0 & ~(int64_t)15;
+        const int sh = (int)(gx0 - a) + lane;
+        uint8_t *stI = stage, *stJ = stage + STAGE_BYTES;
+        stage_u8(plane_rsrc(d.I, (uint64_t)(H * d.pI)), gy0, H, (uint32_t)d.pI, a, lane, stI);
+        const bool needJ = !(FILL && INITIAL);
+        if (needJ)
+            stage_u8(plane_rsrc(d.J, (uint64_t)(H * d.pJ)), gy0, H, (uint32_t)d.pJ, a, lane, stJ);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < TS; ++r) {
+            const int64_t gy = gy0 + r;
+            const bool ok = xin && gy >= 0 && gy < H;
+            uint32_t iv = stI[r * SROW + sh];
+            if (FILL) iv = P::KMAX - iv;
+            uint32_t jv;
+            if (FILL && INITIAL)
+                jv = (xedge || gy == 0 || gy == H - 1) ? iv : 0u;
+            else if (INITIAL)
+                jv = min((uint32_t)stJ[r * SROW + sh], iv);
+            else
+                jv = stJ[r * SROW + sh];
+            jv = ok ? jv : 0u;
+            iv = ok ? iv : 0u;
+            J[r] = jv;
+            I[r] = (halo_lane || r == 0 || r == TS - 1) ? jv : iv;
+        }
+        __syncthreads();
+        return;
+    }
+    cgptr<T> Jp = (cgptr<T>)d.J;
+    cgptr<T> Ip = (cgptr<T>)d.I;
+    const uint32_t xc = (uint32_t)min(max(gx, (int64_t)0), W - 1);
 #pragma unroll
     for (int r = 0; r < TS; ++r) {
         const int64_t gy = gy0 + r;
@@ -162,31 +243,46 @@ __device__ __forceinline__ void transpose(uint32_t (&A)[TS], uint32_t (*tb)[TS +
     __syncthreads();
 }
 
-// Forward sweep along the registers: A[r] takes max over the previous
-// register's three lanes (one for 4-connectivity), limited by B[r]. Values
-// only rise, so callers detect change by comparing column sums.
-template <int CONN>
-__device__ __forceinline__ void sweep_fwd(uint32_t (&A)[TS], const uint32_t (&B)[TS]) {
-#pragma unroll
-    for (int r = 1; r < TS - 1; ++r) {
-        const uint32_t u = A[r - 1];
-        uint32_t n = u;
-        if (CONN == 8) n = max(n, max(from_lower_lane(u), from_upper_lane(u)));
-        const uint32_t v = min(max(A[r], n), B[r]);
-        A[r] = v;
-    }
+// med3(j, n, i) = min(max(j, n), i) whenever j <= i, which holds for every
+// key the kernels hold (the working image never exceeds the mask, and the
+// frozen halo has i == j): one VALU instead of two.
+__device__ __forceinline__ uint32_t med3(uint32_t j, uint32_t n, uint32_t i) {
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(j), "v"(n), "v"(i));
+    return r;
 }
 
-template <int CONN>
+// One 8-connected row step: med3(j, max of u over lanes l-1, l, l+1, i).
+// Both lane shifts ride on DPP max instructions. The leading s_nop covers the
+// DPP read-after-VALU-write hazard on u, which is written by the previous
+// row's step immediately before.
+__device__ __forceinline__ uint32_t step3(uint32_t j, uint32_t u, uint32_t i) {
+    uint32_t r, t;
+    asm("s_nop 1\n\t"
+        "v_max_u32_dpp %1, %2, %2 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_max_u32_dpp %1, %2, %1 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_med3_u32 %0, %3, %1, %4"
+        : "=v"(r), "=&v"(t)
+        : "v"(u), "v"(j), "v"(i));
+    return r;
+}
+
+// Sweeps along the registers. With DIAG, A[r] takes the max over the three
+// lanes of the previous register (the 3 neighbours in the previous row), else
+// only the same lane; the result is limited by B[r]. Values only rise, so
+// callers detect change by comparing column sums.
+template <bool DIAG>
+__device__ __forceinline__ void sweep_fwd(uint32_t (&A)[TS], const uint32_t (&B)[TS]) {
+#pragma unroll
+    for (int r = 1; r < TS - 1; ++r)
+        A[r] = DIAG ? step3(A[r], A[r - 1], B[r]) : med3(A[r], A[r - 1], B[r]);
+}
+
+template <bool DIAG>
 __device__ __forceinline__ void sweep_bwd(uint32_t (&A)[TS], const uint32_t (&B)[TS]) {
 #pragma unroll
-    for (int r = TS - 2; r >= 1; --r) {
-        const uint32_t u = A[r + 1];
-        uint32_t n = u;
-        if (CONN == 8) n = max(n, max(from_lower_lane(u), from_upper_lane(u)));
-        const uint32_t v = min(max(A[r], n), B[r]);
-        A[r] = v;
-    }
+    for (int r = TS - 2; r >= 1; --r)
+        A[r] = DIAG ? step3(A[r], A[r + 1], B[r]) : med3(A[r], A[r + 1], B[r]);
 }
 
 // Sum of the interior rows of a column. Keys only rise, so the sum rises iff
@@ -206,16 +302,13 @@ __device__ __forceinline__ uint64_t col_sum(const uint32_t (&A)[TS]) {
     return s;
 }
 
-// Put tile (ty, tx) of image d on the dirty list of round `nxt`, once:
-// flags hold the latest round a tile is listed for.
-__device__ __forceinline__ void mark(uint32_t *flags, uint32_t *list_out, Ctrl *ctrl,
-                                     const ImgDesc &d, int ty, int tx, uint32_t nxt) {
+// Mark tile (ty, tx) of image d dirty for round `nxt`. flags[t] is the latest
+// round a tile is dirty for; every writer of round nxt - 1 stores the same
+// value, so plain stores suffice.
+__device__ __forceinline__ void mark(uint32_t *flags, const ImgDesc &d, int ty, int tx,
+                                     uint32_t nxt) {
     if (ty < 0 || ty >= d.nty || tx < 0 || tx >= d.ntx) return;
-    const int64_t nb = d.tile_base + (int64_t)ty * d.ntx + tx;
-    if (atomicMax(flags + nb, nxt) < nxt) {
-        const uint32_t i = atomicAdd(&ctrl->round_tiles[nxt], 1u);
-        list_out[i] = (uint32_t)nb;
-    }
+    flags[d.tile_base + (int64_t)ty * d.ntx + tx] = nxt;
 }
 
 // One visit of one tile: load, sweep to a local fixed point (or the cap),
@@ -223,7 +316,6 @@ __device__ __forceinline__ void mark(uint32_t *flags, uint32_t *list_out, Ctrl *
 template <typename T, int CONN, bool FILL, bool INITIAL>
 __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane,
                                            uint32_t *__restrict__ flags,
-                                           uint32_t *__restrict__ list_out,
                                            Ctrl *__restrict__ ctrl, uint32_t round, int max_iters,
                                            uint32_t (*tb)[TS + 1]) {
     using P = Pix<T>;
@@ -233,7 +325,7 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
     const int64_t gy0 = (int64_t)ty * TI - 1, gx = (int64_t)tx * TI - 1 + lane;
 
     uint32_t J[TS], I[TS], IT[TS];
-    load_tile<T, FILL, INITIAL>(d, gy0, gx, lane, J, I);
+    load_tile<T, FILL, INITIAL>(d, gy0, gx, lane, J, I, (uint8_t *)tb);
 #pragma unroll
     for (int r = 0; r < TS; ++r) IT[r] = I[r];
     transpose(IT, tb, lane);
@@ -243,12 +335,18 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
     uint64_t col_prev = col_in;
 
     bool stable = false, changed = false;
-    for (int it = 0; it < max_iters; ++it) {
-        sweep_fwd<CONN>(J, I);
-        sweep_bwd<CONN>(J, I);
+    // Down and up sweeps take the 3 (8-connectivity) or 1 (4-connectivity)
+    // neighbours of the adjacent row; on the transposed tile the right and
+    // left sweeps take only the in-row neighbour, because the vertical sweeps
+    // already test the diagonal ones. A full iteration that changes nothing
+    // therefore means every pixel is stable against all its neighbours.
+    int it = 0;
+    for (; it < max_iters; ++it) {
+        sweep_fwd<CONN == 8>(J, I);
+        sweep_bwd<CONN == 8>(J, I);
         transpose(J, tb, lane);
-        sweep_fwd<CONN>(J, IT);
-        sweep_bwd<CONN>(J, IT);
+        sweep_fwd<false>(J, IT);
+        sweep_bwd<false>(J, IT);
         transpose(J, tb, lane);
         const uint64_t col_now = col_sum<T>(J);
         const bool ch = col_now != col_prev;
@@ -259,6 +357,8 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
         }
         changed = true;
     }
+    if (lane == 0)
+        atomicAdd(&ctrl->iters[t & (NCNT - 1)], (unsigned long long)(it + (stable ? 1 : 0)));
 
     const bool in_lane = lane >= 1 && lane <= TS - 2;
     if (changed || first) {
@@ -285,52 +385,63 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
     if (lane == 0) {
         const uint32_t nxt = round + 1;
         const bool left = (bc >> 1) & 1, right = (bc >> (TS - 2)) & 1;
-        if (!stable) mark(flags, list_out, ctrl, d, ty, tx, nxt);
-        if (bt) mark(flags, list_out, ctrl, d, ty - 1, tx, nxt);
-        if (bb) mark(flags, list_out, ctrl, d, ty + 1, tx, nxt);
-        if (left) mark(flags, list_out, ctrl, d, ty, tx - 1, nxt);
-        if (right) mark(flags, list_out, ctrl, d, ty, tx + 1, nxt);
+        if (!stable) mark(flags, d, ty, tx, nxt);
+        if (bt) mark(flags, d, ty - 1, tx, nxt);
+        if (bb) mark(flags, d, ty + 1, tx, nxt);
+        if (left) mark(flags, d, ty, tx - 1, nxt);
+        if (right) mark(flags, d, ty, tx + 1, nxt);
         if (CONN == 8) {
-            if ((bt >> 1) & 1) mark(flags, list_out, ctrl, d, ty - 1, tx - 1, nxt);
-            if ((bt >> (TS - 2)) & 1) mark(flags, list_out, ctrl, d, ty - 1, tx + 1, nxt);
-            if ((bb >> 1) & 1) mark(flags, list_out, ctrl, d, ty + 1, tx - 1, nxt);
-            if ((bb >> (TS - 2)) & 1) mark(flags, list_out, ctrl, d, ty + 1, tx + 1, nxt);
+            if ((bt >> 1) & 1) mark(flags, d, ty - 1, tx - 1, nxt);
+            if ((bt >> (TS - 2)) & 1) mark(flags, d, ty - 1, tx + 1, nxt);
+            if ((bb >> 1) & 1) mark(flags, d, ty + 1, tx - 1, nxt);
+            if ((bb >> (TS - 2)) & 1) mark(flags, d, ty + 1, tx + 1, nxt);
         }
+        if (!stable || bt || bb || left || right) ctrl->marked[nxt] = 1u;
     }
 }
 
+// Tiles are scanned for dirt in chunks of CHUNK consecutive ids: one flag
+// load per lane and a wave ballot give the chunk's dirty tiles.
+constexpr int CHUNK = 16;
+
 // One tile round. Round 1 runs one 64-thread block per tile of the launch;
-// later rounds run a fixed grid that strides over the round's dirty list.
+// later rounds run a fixed grid whose blocks scan the flags of interleaved
+// chunks and visit the tiles dirty for this round.
 template <typename T, int CONN>
-__global__ __launch_bounds__(64) void k_tile_round(Imgs imgs, int64_t n_tiles,
-                                                   uint32_t *__restrict__ flags,
-                                                   uint32_t *__restrict__ lists,
-                                                   Ctrl *__restrict__ ctrl, uint32_t round,
-                                                   int max_iters) {
-    __shared__ uint32_t tb[TS][TS + 1]; // transpose buffer
+__global__ __launch_bounds__(64, 2) void k_tile_round(Imgs imgs, int64_t n_tiles,
+                                                      uint32_t *__restrict__ flags,
+                                                      Ctrl *__restrict__ ctrl, uint32_t round,
+                                                      int max_iters) {
+    __shared__ uint32_t tb[TS][TS + 1]; // transpose buffer (and load stage)
     const int lane = threadIdx.x;
-    uint32_t *list_out = lists + ((round + 1) & 1) * n_tiles;
     if (round == 1) {
         const int64_t t = blockIdx.x;
         const ImgDesc d = load_desc(imgs, t);
         if (d.done) return;
         if (d.op == MR_OP_FILL)
-            visit_tile<T, CONN, true, true>(d, t, lane, flags, list_out, ctrl, round, max_iters, tb);
+            visit_tile<T, CONN, true, true>(d, t, lane, flags, ctrl, round, max_iters, tb);
         else
-            visit_tile<T, CONN, false, true>(d, t, lane, flags, list_out, ctrl, round, max_iters, tb);
+            visit_tile<T, CONN, false, true>(d, t, lane, flags, ctrl, round, max_iters, tb);
         return;
     }
-    const uint32_t *list_in = lists + (round & 1) * n_tiles;
-    const uint32_t n = ctrl->round_tiles[round];
-    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
-        const int64_t t = list_in[i];
-        const ImgDesc d = load_desc(imgs, t);
-        if (d.done) continue;
-        if (d.op == MR_OP_FILL)
-            visit_tile<T, CONN, true, false>(d, t, lane, flags, list_out, ctrl, round, max_iters, tb);
-        else
-            visit_tile<T, CONN, false, false>(d, t, lane, flags, list_out, ctrl, round, max_iters, tb);
+    uint32_t visits = 0;
+    for (int64_t c0 = (int64_t)blockIdx.x * CHUNK; c0 < n_tiles;
+         c0 += (int64_t)gridDim.x * CHUNK) {
+        const int64_t tt = c0 + lane;
+        uint64_t m = __ballot(lane < CHUNK && tt < n_tiles && flags[tt] >= round);
+        while (m) {
+            const int64_t t = c0 + (__ffsll((unsigned long long)m) - 1);
+            m &= m - 1;
+            const ImgDesc d = load_desc(imgs, t);
+            if (d.done) continue;
+            ++visits;
+            if (d.op == MR_OP_FILL)
+                visit_tile<T, CONN, true, false>(d, t, lane, flags, ctrl, round, max_iters, tb);
+            else
+                visit_tile<T, CONN, false, false>(d, t, lane, flags, ctrl, round, max_iters, tb);
+        }
     }
+    if (lane == 0 && visits) atomicAdd(&ctrl->round_tiles[round], visits);
 }
 
 // ------------------------------------------------------------ frontier ring
@@ -393,13 +504,13 @@ __device__ __forceinline__ uint32_t ring_pop(Ctrl *ctrl, uint32_t *ring, uint64_
 template <typename T, int CONN, bool FILL>
 __device__ __forceinline__ void seed_tile(const ImgDesc &d, int64_t t, int lane, Ctrl *ctrl,
                                           uint64_t *bitmap, uint32_t *qflag, uint32_t *ring,
-                                          uint64_t cap) {
+                                          uint64_t cap, uint8_t *stage) {
     using P = Pix<T>;
     const int64_t lt = t - d.tile_base;
     const int ty = (int)(lt / d.ntx), tx = (int)(lt - (int64_t)ty * d.ntx);
     const int64_t gy0 = (int64_t)ty * TI - 1, gx = (int64_t)tx * TI - 1 + lane;
     uint32_t J[TS], I[TS];
-    load_tile<T, FILL, false>(d, gy0, gx, lane, J, I);
+    load_tile<T, FILL, false>(d, gy0, gx, lane, J, I, stage);
     uint64_t myrow = 0; // lane r ends up holding row r's bits
     uint32_t nseed = 0;
     gptr<T> Jw = (gptr<T>)d.J;
@@ -429,30 +540,38 @@ __device__ __forceinline__ void seed_tile(const ImgDesc &d, int64_t t, int lane,
     }
 }
 
-// One relaxation step over each tile on the dirty list of `round` (the
-// round after the last one run): every interior pixel takes min(I, max of J
-// over itself and its neighbours). Raised pixels are stored, their bits form
-// the tile's rows of the frontier bitmap (one ballot per row), and the tile
-// enters the frontier ring. The bitmap and flags start cleared.
+// One relaxation step over each tile dirty for `round` (the round after the
+// last one run): every interior pixel takes min(I, max of J over itself and
+// its neighbours). Raised pixels are stored, their bits form the tile's rows
+// of the frontier bitmap (one ballot per row), and the tile enters the
+// frontier ring. The bitmap and queue flags start cleared.
 template <typename T, int CONN>
 __global__ __launch_bounds__(64) void k_seed(Imgs imgs, int64_t n_tiles,
-                                             const uint32_t *__restrict__ lists, uint32_t round,
+                                             const uint32_t *__restrict__ flags, uint32_t round,
                                              Ctrl *__restrict__ ctrl,
                                              uint64_t *__restrict__ bitmap,
                                              uint32_t *__restrict__ qflag,
                                              uint32_t *__restrict__ ring, uint64_t cap) {
+    __shared__ uint8_t stage[2 * STAGE_BYTES];
     const int lane = threadIdx.x;
-    const uint32_t *list_in = lists + (round & 1) * n_tiles;
-    const uint32_t n = ctrl->round_tiles[round];
-    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
-        const int64_t t = list_in[i];
-        const ImgDesc d = load_desc(imgs, t);
-        if (d.done) continue;
-        if (d.op == MR_OP_FILL)
-            seed_tile<T, CONN, true>(d, t, lane, ctrl, bitmap, qflag, ring, cap);
-        else
-            seed_tile<T, CONN, false>(d, t, lane, ctrl, bitmap, qflag, ring, cap);
+    uint32_t visits = 0;
+    for (int64_t c0 = (int64_t)blockIdx.x * CHUNK; c0 < n_tiles;
+         c0 += (int64_t)gridDim.x * CHUNK) {
+        const int64_t tt = c0 + lane;
+        uint64_t m = __ballot(lane < CHUNK && tt < n_tiles && flags[tt] >= round);
+        while (m) {
+            const int64_t t = c0 + (__ffsll((unsigned long long)m) - 1);
+            m &= m - 1;
+            const ImgDesc d = load_desc(imgs, t);
+            if (d.done) continue;
+            ++visits;
+            if (d.op == MR_OP_FILL)
+                seed_tile<T, CONN, true>(d, t, lane, ctrl, bitmap, qflag, ring, cap, stage);
+            else
+                seed_tile<T, CONN, false>(d, t, lane, ctrl, bitmap, qflag, ring, cap, stage);
+        }
     }
+    if (lane == 0 && visits) atomicAdd(&ctrl->round_tiles[round], visits);
 }
 
 // ------------------------------------------------------------------- queue
@@ -669,42 +788,44 @@ hipError_t launch_clear_ctrl(Ctrl *c, uint32_t first_round_tiles, hipStream_t s)
 }
 
 template <typename T, int CONN>
-static hipError_t tile_round_t(const Imgs &imgs, int64_t n_tiles, uint32_t *flags,
-                               uint32_t *lists, Ctrl *ctrl, uint32_t round, int max_iters,
-                               int grid, hipStream_t s) {
-    const unsigned g = round == 1 ? (unsigned)n_tiles : (unsigned)grid;
+static hipError_t tile_round_t(const Imgs &imgs, int64_t n_tiles, uint32_t *flags, Ctrl *ctrl,
+                               uint32_t round, int max_iters, int grid, hipStream_t s) {
+    const int64_t chunks = (n_tiles + CHUNK - 1) / CHUNK;
+    const unsigned g = round == 1 ? (unsigned)n_tiles : (unsigned)std::min<int64_t>(grid, chunks);
     hipLaunchKernelGGL((k_tile_round<T, CONN>), dim3(g), dim3(64), 0, s, imgs, n_tiles, flags,
-                       lists, ctrl, round, max_iters);
+                       ctrl, round, max_iters);
     return hipGetLastError();
 }
 
 hipError_t launch_tile_round(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
-                             uint32_t *flags, uint32_t *lists, Ctrl *ctrl, uint32_t round,
-                             int max_iters, int grid, hipStream_t s) {
+                             uint32_t *flags, Ctrl *ctrl, uint32_t round, int max_iters,
+                             int grid, hipStream_t s) {
     if (tbytes == 1)
-        return conn == 8 ? tile_round_t<uint8_t, 8>(imgs, n_tiles, flags, lists, ctrl, round, max_iters, grid, s)
-                         : tile_round_t<uint8_t, 4>(imgs, n_tiles, flags, lists, ctrl, round, max_iters, grid, s);
-    return conn == 8 ? tile_round_t<int32_t, 8>(imgs, n_tiles, flags, lists, ctrl, round, max_iters, grid, s)
-                     : tile_round_t<int32_t, 4>(imgs, n_tiles, flags, lists, ctrl, round, max_iters, grid, s);
+        return conn == 8 ? tile_round_t<uint8_t, 8>(imgs, n_tiles, flags, ctrl, round, max_iters, grid, s)
+                         : tile_round_t<uint8_t, 4>(imgs, n_tiles, flags, ctrl, round, max_iters, grid, s);
+    return conn == 8 ? tile_round_t<int32_t, 8>(imgs, n_tiles, flags, ctrl, round, max_iters, grid, s)
+                     : tile_round_t<int32_t, 4>(imgs, n_tiles, flags, ctrl, round, max_iters, grid, s);
 }
 
 template <typename T, int CONN>
-static hipError_t seed_t(const Imgs &imgs, int64_t n_tiles, const uint32_t *lists,
+static hipError_t seed_t(const Imgs &imgs, int64_t n_tiles, const uint32_t *flags,
                          uint32_t round, Ctrl *ctrl, uint64_t *bitmap, uint32_t *qflag,
                          uint32_t *ring, uint64_t cap, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_seed<T, CONN>), dim3((unsigned)grid), dim3(64), 0, s, imgs, n_tiles,
-                       lists, round, ctrl, bitmap, qflag, ring, cap);
+    const int64_t chunks = (n_tiles + CHUNK - 1) / CHUNK;
+    const unsigned g = (unsigned)std::min<int64_t>(grid, chunks);
+    hipLaunchKernelGGL((k_seed<T, CONN>), dim3(g), dim3(64), 0, s, imgs, n_tiles, flags, round,
+                       ctrl, bitmap, qflag, ring, cap);
     return hipGetLastError();
 }
 
 hipError_t launch_seed(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
-                       const uint32_t *lists, uint32_t round, Ctrl *ctrl, uint64_t *bitmap,
+                       const uint32_t *flags, uint32_t round, Ctrl *ctrl, uint64_t *bitmap,
                        uint32_t *qflag, uint32_t *ring, uint64_t cap, int grid, hipStream_t s) {
     if (tbytes == 1)
-        return conn == 8 ? seed_t<uint8_t, 8>(imgs, n_tiles, lists, round, ctrl, bitmap, qflag, ring, cap, grid, s)
-                         : seed_t<uint8_t, 4>(imgs, n_tiles, lists, round, ctrl, bitmap, qflag, ring, cap, grid, s);
-    return conn == 8 ? seed_t<int32_t, 8>(imgs, n_tiles, lists, round, ctrl, bitmap, qflag, ring, cap, grid, s)
-                     : seed_t<int32_t, 4>(imgs, n_tiles, lists, round, ctrl, bitmap, qflag, ring, cap, grid, s);
+        return conn == 8 ? seed_t<uint8_t, 8>(imgs, n_tiles, flags, round, ctrl, bitmap, qflag, ring, cap, grid, s)
+                         : seed_t<uint8_t, 4>(imgs, n_tiles, flags, round, ctrl, bitmap, qflag, ring, cap, grid, s);
+    return conn == 8 ? seed_t<int32_t, 8>(imgs, n_tiles, flags, round, ctrl, bitmap, qflag, ring, cap, grid, s)
+                     : seed_t<int32_t, 4>(imgs, n_tiles, flags, round, ctrl, bitmap, qflag, ring, cap, grid, s);
 }
 
 __global__ void k_clear_u64(uint64_t *p, int64_t n) {

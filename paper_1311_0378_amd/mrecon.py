@@ -37,7 +37,8 @@ class Tune(ctypes.Structure):
 
 class Counters(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in
-                ("rounds", "tiles", "seeds", "pops", "pushes", "cas_retries", "overflows")]
+                ("rounds", "tiles", "seeds", "pops", "pushes", "cas_retries", "overflows",
+                 "sweeps")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -97,6 +97,22 @@ def test_serpentine_queue_heavy(conn):
         check(got, want)
 
 
+@pytest.mark.parametrize("W", [1, 5, 17, 62, 63, 77, 130])
+@pytest.mark.parametrize("conn", [4, 8])
+def test_aligned_pitch_shapes(W, conn):
+    """Rows padded to a multiple of 16 bytes take the staged wide-load path;
+    odd widths leave ragged tails inside the padding and at the plane end."""
+    rng = np.random.default_rng(W * 10 + conn)
+    for H in (1, 3, 66, 131):
+        mask = rng.integers(0, 7, (H, W)).astype(np.uint8)
+        marker = rng.integers(0, 7, (H, W)).astype(np.uint8)
+        pad = (-W) % 16
+        want, _ = oracle.recon_dilate(marker, mask, conn)
+        check(gpu_recon(marker, mask, conn, pad=pad), want)
+        wantf, _ = oracle.fill_holes(mask, conn)
+        check(gpu_fill(mask, conn, pad=pad), wantf)
+
+
 def test_pitched_rows():
     marker, mask = synth.make_tile(200, 333, 20, 8, "u8", 0.0)
     want, _ = oracle.recon_dilate(marker, mask, 8)
