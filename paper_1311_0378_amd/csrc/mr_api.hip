@@ -40,8 +40,8 @@ uint64_t next_pow2(uint64_t v) {
 // queue always drains long before this on a working device).
 constexpr unsigned long long SPIN_CAP = 1ull << 16;
 
-// Grid of the flag-scanning kernels (tile rounds after the first, seed):
-// enough 64-thread blocks to fill every SIMD twice over.
+// Grid of the persistent tile kernels (tile rounds, seed): two 64-thread
+// blocks per SIMD, the tile kernel's occupancy.
 int scan_grid() {
     static int g = 0;
     if (!g) {
@@ -60,7 +60,7 @@ int scan_grid() {
 struct Layout {
     int64_t n_tiles = 0;
     uint64_t ring_cap = 0;
-    size_t off_desc = 0, off_flags = 0, off_qflag = 0, off_bitmap = 0, off_ring = 0, off_plane = 0, total = 0;
+    size_t off_desc = 0, off_flags = 0, off_lists = 0, off_qflag = 0, off_bitmap = 0, off_ring = 0, off_plane = 0, total = 0;
     int64_t plane_pitch = 0;
 };
 
@@ -73,6 +73,8 @@ Layout layout_for(int64_t n_tiles, int64_t fill_plane_bytes, int64_t plane_pitch
     o = align_up(o + sizeof(ImgDesc), 256);
     L.off_flags = o;
     o = align_up(o + (size_t)n_tiles * 4, 256);
+    L.off_lists = o;
+    o = align_up(o + (size_t)n_tiles * 8, 256);
     L.off_qflag = o;
     o = align_up(o + (size_t)n_tiles * 4, 256);
     L.off_bitmap = o;
@@ -151,6 +153,7 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
     char *base = (char *)ws;
     Ctrl *ctrl = (Ctrl *)base;
     uint32_t *flags = (uint32_t *)(base + L.off_flags);
+    uint32_t *lists = (uint32_t *)(base + L.off_lists);
     uint32_t *qflag = (uint32_t *)(base + L.off_qflag);
     uint64_t *bitmap = (uint64_t *)(base + L.off_bitmap);
     uint32_t *ring = (uint32_t *)(base + L.off_ring);
@@ -162,12 +165,12 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
     if ((e = launch_clear_u32(flags, L.n_tiles, 0u, s)) != hipSuccess) return hip_fail(e, "clear");
 
     uint32_t round = 1;
-    if ((e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, ctrl, round,
+    if ((e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl, round,
                                tn.max_sweeps, grid, s)) != hipSuccess)
         return hip_fail(e, "tile round");
     if (tn.sweep_rounds > 0) {
         for (round = 2; round <= (uint32_t)tn.sweep_rounds; ++round)
-            if ((e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, ctrl, round,
+            if ((e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl, round,
                                        tn.max_sweeps, grid, s)) != hipSuccess)
                 return hip_fail(e, "tile round");
         if ((e = launch_store_u64(&ctrl->rounds, (unsigned long long)tn.sweep_rounds, s)) !=
@@ -177,7 +180,7 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
             (e = launch_clear_u64(bitmap, L.n_tiles * TS, s)) != hipSuccess ||
             (e = launch_clear_u32(ring, (int64_t)L.ring_cap, Q_EMPTY, s)) != hipSuccess)
             return hip_fail(e, "clear");
-        if ((e = launch_seed(tbytes, conn, imgs, L.n_tiles, flags, round, ctrl, bitmap, qflag,
+        if ((e = launch_seed(tbytes, conn, imgs, L.n_tiles, lists, round, ctrl, bitmap, qflag,
                              ring, L.ring_cap, grid, s)) != hipSuccess)
             return hip_fail(e, "seed");
         int blocks = tn.persistent_blocks;
@@ -196,12 +199,12 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
         while (true) {
             for (uint32_t k = 0; k < poll && round < MAX_ROUNDS; ++k) {
                 ++round;
-                if ((e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, ctrl, round,
+                if ((e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl, round,
                                            tn.max_sweeps, grid, s)) != hipSuccess)
                     return hip_fail(e, "tile round");
             }
             *hw = 0;
-            if ((e = hipMemcpyAsync(hw, &ctrl->marked[round + 1], sizeof(uint32_t),
+            if ((e = hipMemcpyAsync(hw, &ctrl->round_tiles[round + 1], sizeof(uint32_t),
                                     hipMemcpyDeviceToHost, s)) != hipSuccess)
                 return hip_fail(e, "poll copy");
             if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "poll sync");

@@ -56,11 +56,10 @@ struct Ctrl {
     unsigned long long iters[NCNT];  // sweep iterations over all tile visits (spread)
     unsigned long long rounds;       // written by the host sequence
     unsigned long long watchdog;     // non-zero if a queue block hit its spin cap
-    // round_tiles[r]: tiles visited in round r (round 1 = all tiles, written
-    // by the host sequence); round_tiles[k+1] is what the seed pass visited
-    // after k rounds. marked[r] is non-zero once a tile was marked for round r.
+    // round_tiles[r]: length of the dirty list of round r (round 1 = all
+    // tiles, written by the host sequence); round_tiles[k+1] is what the seed
+    // pass starts from after k rounds.
     uint32_t round_tiles[MAX_ROUNDS + 2];
-    uint32_t marked[MAX_ROUNDS + 2];
 };
 
 // Launch-wide view of the images: a device array of descriptors sorted by
@@ -75,13 +74,14 @@ constexpr uint32_t Q_EMPTY = 0xFFFFFFFFu;
 // Host-side launchers (defined in mr_kernels.hip).
 hipError_t launch_clear_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_clear_ctrl(Ctrl *c, uint32_t first_round_tiles, hipStream_t s);
-// Round r visits every tile (r == 1) or the tiles whose flag is >= r, and
-// sets the flag of every tile it dirties to r + 1.
+// Round r visits every tile (r == 1) or the dirty list lists[(r & 1) *
+// n_tiles ...] of length ctrl->round_tiles[r], and puts each tile it dirties
+// on the other half for round r + 1 (flags[t] = latest round t is listed for).
 hipError_t launch_tile_round(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
-                             uint32_t *flags, Ctrl *ctrl, uint32_t round, int max_iters,
-                             int grid, hipStream_t s);
+                             uint32_t *flags, uint32_t *lists, Ctrl *ctrl, uint32_t round,
+                             int max_iters, int grid, hipStream_t s);
 hipError_t launch_seed(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
-                       const uint32_t *flags, uint32_t round, Ctrl *ctrl, uint64_t *bitmap,
+                       const uint32_t *lists, uint32_t round, Ctrl *ctrl, uint64_t *bitmap,
                        uint32_t *qflag, uint32_t *ring, uint64_t cap, int grid, hipStream_t s);
 hipError_t launch_clear_u64(uint64_t *p, int64_t n, hipStream_t s);
 hipError_t launch_queue(int tbytes, int conn, const Imgs &imgs, Ctrl *ctrl, uint64_t *bitmap,

@@ -13,7 +13,7 @@
 //    diagonal neighbours taken from the adjacent lanes by DPP; the tile is
 //    transposed through LDS for the right and left sweeps. Sweeps repeat until
 //    the tile is stable, then the interior is stored and the tiles whose halo
-//    changed are marked dirty for the next round, which visits only those.
+//    changed go on the next round's dirty list, which is all it visits.
 //  * k_seed -- one relaxation step over each tile still dirty after the last
 //    round; every raised pixel is compacted by wave ballot into the tile's row
 //    of the frontier bitmap, and the tile into the device frontier ring.
@@ -302,20 +302,32 @@ __device__ __forceinline__ uint64_t col_sum(const uint32_t (&A)[TS]) {
     return s;
 }
 
-// Mark tile (ty, tx) of image d dirty for round `nxt`. flags[t] is the latest
-// round a tile is dirty for; every writer of round nxt - 1 stores the same
-// value, so plain stores suffice.
-__device__ __forceinline__ void mark(uint32_t *flags, const ImgDesc &d, int ty, int tx,
-                                     uint32_t nxt) {
-    if (ty < 0 || ty >= d.nty || tx < 0 || tx >= d.ntx) return;
-    flags[d.tile_base + (int64_t)ty * d.ntx + tx] = nxt;
+// Tiles newly made dirty by one wave wait in an LDS batch and go to the next
+// round's list with one counter update per batch, not one per tile.
+constexpr int APP_CAP = 64;
+struct Appender {
+    uint32_t *buf;      // LDS, APP_CAP entries
+    uint32_t cnt;       // wave-uniform
+    uint32_t *list_out; // next round's dirty list
+    uint32_t *counter;  // its length
+};
+
+__device__ __forceinline__ void app_flush(Appender &a, int lane) {
+    if (a.cnt == 0) return;
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(a.counter, a.cnt);
+    base = __shfl(base, 0);
+    __syncthreads();
+    for (uint32_t i = lane; i < a.cnt; i += 64) a.list_out[base + i] = a.buf[i];
+    __syncthreads();
+    a.cnt = 0;
 }
 
 // One visit of one tile: load, sweep to a local fixed point (or the cap),
 // store, and mark the neighbours whose halo changed.
 template <typename T, int CONN, bool FILL, bool INITIAL>
 __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane,
-                                           uint32_t *__restrict__ flags,
+                                           uint32_t *__restrict__ flags, Appender &app,
                                            Ctrl *__restrict__ ctrl, uint32_t round, int max_iters,
                                            uint32_t (*tb)[TS + 1]) {
     using P = Pix<T>;
@@ -382,66 +394,72 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
     const uint64_t bt = __ballot(in_lane && J[1] != top_in);
     const uint64_t bb = __ballot(in_lane && J[TS - 2] != bot_in);
     const uint64_t bc = __ballot(col_out != col_in);
-    if (lane == 0) {
-        const uint32_t nxt = round + 1;
-        const bool left = (bc >> 1) & 1, right = (bc >> (TS - 2)) & 1;
-        if (!stable) mark(flags, d, ty, tx, nxt);
-        if (bt) mark(flags, d, ty - 1, tx, nxt);
-        if (bb) mark(flags, d, ty + 1, tx, nxt);
-        if (left) mark(flags, d, ty, tx - 1, nxt);
-        if (right) mark(flags, d, ty, tx + 1, nxt);
-        if (CONN == 8) {
-            if ((bt >> 1) & 1) mark(flags, d, ty - 1, tx - 1, nxt);
-            if ((bt >> (TS - 2)) & 1) mark(flags, d, ty - 1, tx + 1, nxt);
-            if ((bb >> 1) & 1) mark(flags, d, ty + 1, tx - 1, nxt);
-            if ((bb >> (TS - 2)) & 1) mark(flags, d, ty + 1, tx + 1, nxt);
-        }
-        if (!stable || bt || bb || left || right) ctrl->marked[nxt] = 1u;
+    // Lanes 0..8 each consider one tile to mark dirty for the next round:
+    // itself (if the sweep cap stopped it early) and the neighbours whose halo
+    // holds a changed border pixel. The atomic max on the flag lets exactly
+    // one marker put a tile on the next list.
+    const uint32_t nxt = round + 1;
+    bool want = false;
+    int dy = 0, dx = 0;
+    switch (lane) {
+    case 0: want = !stable; break;
+    case 1: want = bt != 0; dy = -1; break;
+    case 2: want = bb != 0; dy = 1; break;
+    case 3: want = (bc >> 1) & 1; dx = -1; break;
+    case 4: want = (bc >> (TS - 2)) & 1; dx = 1; break;
+    case 5: want = CONN == 8 && ((bt >> 1) & 1); dy = -1; dx = -1; break;
+    case 6: want = CONN == 8 && ((bt >> (TS - 2)) & 1); dy = -1; dx = 1; break;
+    case 7: want = CONN == 8 && ((bb >> 1) & 1); dy = 1; dx = -1; break;
+    case 8: want = CONN == 8 && ((bb >> (TS - 2)) & 1); dy = 1; dx = 1; break;
+    default: break;
     }
+    const int ny = ty + dy, nx = tx + dx;
+    want = want && ny >= 0 && ny < d.nty && nx >= 0 && nx < d.ntx;
+    uint32_t nb = 0;
+    bool fresh = false;
+    if (want) {
+        nb = (uint32_t)(d.tile_base + (int64_t)ny * d.ntx + nx);
+        fresh = atomicMax(flags + nb, nxt) < nxt;
+    }
+    const uint64_t fm = __ballot(fresh);
+    if (fresh) app.buf[app.cnt + __popcll(fm & ((1ull << lane) - 1))] = nb;
+    app.cnt += (uint32_t)__popcll(fm);
 }
 
-// Tiles are scanned for dirt in chunks of CHUNK consecutive ids: one flag
-// load per lane and a wave ballot give the chunk's dirty tiles.
-constexpr int CHUNK = 16;
-
-// One tile round. Round 1 runs one 64-thread block per tile of the launch;
-// later rounds run a fixed grid whose blocks scan the flags of interleaved
-// chunks and visit the tiles dirty for this round.
+// One tile round on a persistent grid (two waves per SIMD). Round 1 visits
+// every tile; round r > 1 visits its dirty list. Tiles are dealt to the waves
+// by static interleave, so no wave gets more than one tile above another.
 template <typename T, int CONN>
 __global__ __launch_bounds__(64, 2) void k_tile_round(Imgs imgs, int64_t n_tiles,
                                                       uint32_t *__restrict__ flags,
+                                                      uint32_t *__restrict__ lists,
                                                       Ctrl *__restrict__ ctrl, uint32_t round,
                                                       int max_iters) {
     __shared__ uint32_t tb[TS][TS + 1]; // transpose buffer (and load stage)
+    __shared__ uint32_t abuf[APP_CAP];
     const int lane = threadIdx.x;
-    if (round == 1) {
-        const int64_t t = blockIdx.x;
+    Appender app{abuf, 0, lists + ((round + 1) & 1) * n_tiles, &ctrl->round_tiles[round + 1]};
+    const uint32_t *list_in = lists + (round & 1) * n_tiles;
+    const int64_t n = round == 1 ? n_tiles : (int64_t)ctrl->round_tiles[round];
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const int64_t t = round == 1 ? i : (int64_t)list_in[i];
         const ImgDesc d = load_desc(imgs, t);
-        if (d.done) return;
-        if (d.op == MR_OP_FILL)
-            visit_tile<T, CONN, true, true>(d, t, lane, flags, ctrl, round, max_iters, tb);
-        else
-            visit_tile<T, CONN, false, true>(d, t, lane, flags, ctrl, round, max_iters, tb);
-        return;
-    }
-    uint32_t visits = 0;
-    for (int64_t c0 = (int64_t)blockIdx.x * CHUNK; c0 < n_tiles;
-         c0 += (int64_t)gridDim.x * CHUNK) {
-        const int64_t tt = c0 + lane;
-        uint64_t m = __ballot(lane < CHUNK && tt < n_tiles && flags[tt] >= round);
-        while (m) {
-            const int64_t t = c0 + (__ffsll((unsigned long long)m) - 1);
-            m &= m - 1;
-            const ImgDesc d = load_desc(imgs, t);
-            if (d.done) continue;
-            ++visits;
-            if (d.op == MR_OP_FILL)
-                visit_tile<T, CONN, true, false>(d, t, lane, flags, ctrl, round, max_iters, tb);
-            else
-                visit_tile<T, CONN, false, false>(d, t, lane, flags, ctrl, round, max_iters, tb);
+        if (!d.done) {
+            if (round == 1) {
+                if (d.op == MR_OP_FILL)
+                    visit_tile<T, CONN, true, true>(d, t, lane, flags, app, ctrl, round, max_iters, tb);
+                else
+                    visit_tile<T, CONN, false, true>(d, t, lane, flags, app, ctrl, round, max_iters, tb);
+            } else {
+                if (d.op == MR_OP_FILL)
+                    visit_tile<T, CONN, true, false>(d, t, lane, flags, app, ctrl, round, max_iters, tb);
+                else
+                    visit_tile<T, CONN, false, false>(d, t, lane, flags, app, ctrl, round, max_iters, tb);
+            }
         }
+        if (app.cnt > APP_CAP - 9) app_flush(app, lane);
     }
-    if (lane == 0 && visits) atomicAdd(&ctrl->round_tiles[round], visits);
+    app_flush(app, lane);
 }
 
 // ------------------------------------------------------------ frontier ring
@@ -547,31 +565,24 @@ __device__ __forceinline__ void seed_tile(const ImgDesc &d, int64_t t, int lane,
 // frontier ring. The bitmap and queue flags start cleared.
 template <typename T, int CONN>
 __global__ __launch_bounds__(64) void k_seed(Imgs imgs, int64_t n_tiles,
-                                             const uint32_t *__restrict__ flags, uint32_t round,
+                                             const uint32_t *__restrict__ lists, uint32_t round,
                                              Ctrl *__restrict__ ctrl,
                                              uint64_t *__restrict__ bitmap,
                                              uint32_t *__restrict__ qflag,
                                              uint32_t *__restrict__ ring, uint64_t cap) {
     __shared__ uint8_t stage[2 * STAGE_BYTES];
     const int lane = threadIdx.x;
-    uint32_t visits = 0;
-    for (int64_t c0 = (int64_t)blockIdx.x * CHUNK; c0 < n_tiles;
-         c0 += (int64_t)gridDim.x * CHUNK) {
-        const int64_t tt = c0 + lane;
-        uint64_t m = __ballot(lane < CHUNK && tt < n_tiles && flags[tt] >= round);
-        while (m) {
-            const int64_t t = c0 + (__ffsll((unsigned long long)m) - 1);
-            m &= m - 1;
-            const ImgDesc d = load_desc(imgs, t);
-            if (d.done) continue;
-            ++visits;
-            if (d.op == MR_OP_FILL)
-                seed_tile<T, CONN, true>(d, t, lane, ctrl, bitmap, qflag, ring, cap, stage);
-            else
-                seed_tile<T, CONN, false>(d, t, lane, ctrl, bitmap, qflag, ring, cap, stage);
-        }
+    const uint32_t *list_in = lists + (round & 1) * n_tiles;
+    const int64_t n = ctrl->round_tiles[round];
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const int64_t t = list_in[i];
+        const ImgDesc d = load_desc(imgs, t);
+        if (d.done) continue;
+        if (d.op == MR_OP_FILL)
+            seed_tile<T, CONN, true>(d, t, lane, ctrl, bitmap, qflag, ring, cap, stage);
+        else
+            seed_tile<T, CONN, false>(d, t, lane, ctrl, bitmap, qflag, ring, cap, stage);
     }
-    if (lane == 0 && visits) atomicAdd(&ctrl->round_tiles[round], visits);
 }
 
 // ------------------------------------------------------------------- queue
@@ -788,44 +799,43 @@ hipError_t launch_clear_ctrl(Ctrl *c, uint32_t first_round_tiles, hipStream_t s)
 }
 
 template <typename T, int CONN>
-static hipError_t tile_round_t(const Imgs &imgs, int64_t n_tiles, uint32_t *flags, Ctrl *ctrl,
-                               uint32_t round, int max_iters, int grid, hipStream_t s) {
-    const int64_t chunks = (n_tiles + CHUNK - 1) / CHUNK;
-    const unsigned g = round == 1 ? (unsigned)n_tiles : (unsigned)std::min<int64_t>(grid, chunks);
+static hipError_t tile_round_t(const Imgs &imgs, int64_t n_tiles, uint32_t *flags,
+                               uint32_t *lists, Ctrl *ctrl, uint32_t round, int max_iters,
+                               int grid, hipStream_t s) {
+    const unsigned g = (unsigned)std::min<int64_t>(grid, n_tiles);
     hipLaunchKernelGGL((k_tile_round<T, CONN>), dim3(g), dim3(64), 0, s, imgs, n_tiles, flags,
-                       ctrl, round, max_iters);
+                       lists, ctrl, round, max_iters);
     return hipGetLastError();
 }
 
 hipError_t launch_tile_round(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
-                             uint32_t *flags, Ctrl *ctrl, uint32_t round, int max_iters,
-                             int grid, hipStream_t s) {
+                             uint32_t *flags, uint32_t *lists, Ctrl *ctrl, uint32_t round,
+                             int max_iters, int grid, hipStream_t s) {
     if (tbytes == 1)
-        return conn == 8 ? tile_round_t<uint8_t, 8>(imgs, n_tiles, flags, ctrl, round, max_iters, grid, s)
-                         : tile_round_t<uint8_t, 4>(imgs, n_tiles, flags, ctrl, round, max_iters, grid, s);
-    return conn == 8 ? tile_round_t<int32_t, 8>(imgs, n_tiles, flags, ctrl, round, max_iters, grid, s)
-                     : tile_round_t<int32_t, 4>(imgs, n_tiles, flags, ctrl, round, max_iters, grid, s);
+        return conn == 8 ? tile_round_t<uint8_t, 8>(imgs, n_tiles, flags, lists, ctrl, round, max_iters, grid, s)
+                         : tile_round_t<uint8_t, 4>(imgs, n_tiles, flags, lists, ctrl, round, max_iters, grid, s);
+    return conn == 8 ? tile_round_t<int32_t, 8>(imgs, n_tiles, flags, lists, ctrl, round, max_iters, grid, s)
+                     : tile_round_t<int32_t, 4>(imgs, n_tiles, flags, lists, ctrl, round, max_iters, grid, s);
 }
 
 template <typename T, int CONN>
-static hipError_t seed_t(const Imgs &imgs, int64_t n_tiles, const uint32_t *flags,
+static hipError_t seed_t(const Imgs &imgs, int64_t n_tiles, const uint32_t *lists,
                          uint32_t round, Ctrl *ctrl, uint64_t *bitmap, uint32_t *qflag,
                          uint32_t *ring, uint64_t cap, int grid, hipStream_t s) {
-    const int64_t chunks = (n_tiles + CHUNK - 1) / CHUNK;
-    const unsigned g = (unsigned)std::min<int64_t>(grid, chunks);
-    hipLaunchKernelGGL((k_seed<T, CONN>), dim3(g), dim3(64), 0, s, imgs, n_tiles, flags, round,
+    const unsigned g = (unsigned)std::min<int64_t>(grid, n_tiles);
+    hipLaunchKernelGGL((k_seed<T, CONN>), dim3(g), dim3(64), 0, s, imgs, n_tiles, lists, round,
                        ctrl, bitmap, qflag, ring, cap);
     return hipGetLastError();
 }
 
 hipError_t launch_seed(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
-                       const uint32_t *flags, uint32_t round, Ctrl *ctrl, uint64_t *bitmap,
+                       const uint32_t *lists, uint32_t round, Ctrl *ctrl, uint64_t *bitmap,
                        uint32_t *qflag, uint32_t *ring, uint64_t cap, int grid, hipStream_t s) {
     if (tbytes == 1)
-        return conn == 8 ? seed_t<uint8_t, 8>(imgs, n_tiles, flags, round, ctrl, bitmap, qflag, ring, cap, grid, s)
-                         : seed_t<uint8_t, 4>(imgs, n_tiles, flags, round, ctrl, bitmap, qflag, ring, cap, grid, s);
-    return conn == 8 ? seed_t<int32_t, 8>(imgs, n_tiles, flags, round, ctrl, bitmap, qflag, ring, cap, grid, s)
-                     : seed_t<int32_t, 4>(imgs, n_tiles, flags, round, ctrl, bitmap, qflag, ring, cap, grid, s);
+        return conn == 8 ? seed_t<uint8_t, 8>(imgs, n_tiles, lists, round, ctrl, bitmap, qflag, ring, cap, grid, s)
+                         : seed_t<uint8_t, 4>(imgs, n_tiles, lists, round, ctrl, bitmap, qflag, ring, cap, grid, s);
+    return conn == 8 ? seed_t<int32_t, 8>(imgs, n_tiles, lists, round, ctrl, bitmap, qflag, ring, cap, grid, s)
+                     : seed_t<int32_t, 4>(imgs, n_tiles, lists, round, ctrl, bitmap, qflag, ring, cap, grid, s);
 }
 
 __global__ void k_clear_u64(uint64_t *p, int64_t n) {
