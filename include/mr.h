@@ -134,6 +134,26 @@ int mr_read_counters(const void *ws, mr_counters *out, void *stream);
 int mr_read_round_tiles(const void *ws, uint32_t *out, int32_t cap, int32_t *n_rounds,
                         void *stream);
 
+/* Per-launch device timing (measurement support). While enabled, every
+ * tile-round, seed and queue kernel that a call on this thread enqueues is
+ * bracketed by two HIP events recorded on the call's stream; the records
+ * accumulate until collected. Enabling adds two event records per launch. */
+enum { MR_K_TILE_ROUND = 0, MR_K_SEED = 1, MR_K_QUEUE = 2 };
+typedef struct {
+    int32_t kind;  /* MR_K_* */
+    int32_t round; /* tile round number (MR_K_TILE_ROUND), else 0 */
+    float ms;      /* device time between the two events */
+} mr_launch_time;
+
+/* Turns per-launch timing on (on != 0) or off for the calling thread.
+ * Returns MR_OK. */
+int mr_timing_enable(int on);
+
+/* Waits for the recorded events, writes up to `cap` records in launch order
+ * to `out`, sets *n to the number of records held, and clears them.
+ * Errors: MR_EINVAL (null n, or out null with cap > 0), MR_EHIP. */
+int mr_timing_collect(mr_launch_time *out, int32_t cap, int32_t *n);
+
 /* Message for the last error returned to the calling thread ("" if none). */
 const char *mr_last_error(void);
 

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "mr_internal.h"
 
@@ -139,12 +140,68 @@ mr_tune effective_tune(const mr_tune *tn) {
     return tn ? *tn : d;
 }
 
-// Pinned word the converge mode polls through.
+// Per-launch timing records of the calling thread (mr_timing_enable).
+struct TimedLaunch {
+    int32_t kind, round;
+    hipEvent_t a, b;
+};
+struct Timing {
+    bool on = false;
+    std::vector<TimedLaunch> recs;
+    std::vector<hipEvent_t> pool;
+    ~Timing() {
+        for (auto &r : recs) {
+            hipEventDestroy(r.a);
+            hipEventDestroy(r.b);
+        }
+        for (auto e : pool) hipEventDestroy(e);
+    }
+    hipEvent_t get() {
+        hipEvent_t e = nullptr;
+        if (!pool.empty()) {
+            e = pool.back();
+            pool.pop_back();
+        } else if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+        }
+        return e;
+    }
+};
+thread_local Timing g_timing;
+
+// Brackets one launch with events when timing is on.
+struct LaunchTimer {
+    hipStream_t s;
+    int32_t kind, round;
+    hipEvent_t a = nullptr;
+    LaunchTimer(hipStream_t s_, int32_t kind_, int32_t round_) : s(s_), kind(kind_), round(round_) {
+        if (g_timing.on && (a = g_timing.get())) hipEventRecord(a, s);
+    }
+    ~LaunchTimer() {
+        if (!a) return;
+        hipEvent_t b = g_timing.get();
+        if (!b) {
+            g_timing.pool.push_back(a);
+            return;
+        }
+        hipEventRecord(b, s);
+        g_timing.recs.push_back({kind, round, a, b});
+    }
+};
+
+// Pinned words the converge mode polls through (one round's band counts).
 unsigned long long *host_word() {
     static thread_local unsigned long long *w = nullptr;
-    if (!w && hipHostMalloc((void **)&w, sizeof *w, hipHostMallocDefault) != hipSuccess)
+    if (!w && hipHostMalloc((void **)&w, sizeof(uint32_t) * NBANDS, hipHostMallocDefault) !=
+                  hipSuccess)
         w = nullptr;
     return w;
+}
+
+uint64_t round_total(const Ctrl &h, size_t r) {
+    uint64_t n = 0;
+    for (int b = 0; b < NBANDS; ++b) n += h.round_tiles[r][b];
+    return n;
 }
 
 // The whole propagation over the images of one launch.
@@ -160,19 +217,26 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
     const int grid = scan_grid();
     hipError_t e;
 
-    if ((e = launch_clear_ctrl(ctrl, (uint32_t)L.n_tiles, s)) != hipSuccess)
+    if ((e = launch_clear_ctrl(ctrl, L.n_tiles, s)) != hipSuccess)
         return hip_fail(e, "clear");
     if ((e = launch_clear_u32(flags, L.n_tiles, 0u, s)) != hipSuccess) return hip_fail(e, "clear");
 
     uint32_t round = 1;
-    if ((e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl, round,
-                               tn.max_sweeps, grid, s)) != hipSuccess)
-        return hip_fail(e, "tile round");
+    {
+        LaunchTimer lt(s, MR_K_TILE_ROUND, (int32_t)round);
+        e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl, round,
+                              tn.max_sweeps, grid, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "tile round");
     if (tn.sweep_rounds > 0) {
-        for (round = 2; round <= (uint32_t)tn.sweep_rounds; ++round)
-            if ((e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl, round,
-                                       tn.max_sweeps, grid, s)) != hipSuccess)
-                return hip_fail(e, "tile round");
+        for (round = 2; round <= (uint32_t)tn.sweep_rounds; ++round) {
+            {
+                LaunchTimer lt(s, MR_K_TILE_ROUND, (int32_t)round);
+                e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl, round,
+                                      tn.max_sweeps, grid, s);
+            }
+            if (e != hipSuccess) return hip_fail(e, "tile round");
+        }
         if ((e = launch_store_u64(&ctrl->rounds, (unsigned long long)tn.sweep_rounds, s)) !=
             hipSuccess)
             return hip_fail(e, "store");
@@ -180,16 +244,22 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
             (e = launch_clear_u64(bitmap, L.n_tiles * TS, s)) != hipSuccess ||
             (e = launch_clear_u32(ring, (int64_t)L.ring_cap, Q_EMPTY, s)) != hipSuccess)
             return hip_fail(e, "clear");
-        if ((e = launch_seed(tbytes, conn, imgs, L.n_tiles, lists, round, ctrl, bitmap, qflag,
-                             ring, L.ring_cap, grid, s)) != hipSuccess)
-            return hip_fail(e, "seed");
+        {
+            LaunchTimer lt(s, MR_K_SEED, 0);
+            e = launch_seed(tbytes, conn, imgs, L.n_tiles, lists, round, ctrl, bitmap, qflag, ring,
+                            L.ring_cap, grid, s);
+        }
+        if (e != hipSuccess) return hip_fail(e, "seed");
         int blocks = tn.persistent_blocks;
         const int maxb = queue_max_blocks(tbytes, conn);
         if (maxb <= 0) return fail(MR_EHIP, "cannot size the queue launch");
         if (blocks == 0 || blocks > maxb) blocks = maxb;
-        if ((e = launch_queue(tbytes, conn, imgs, ctrl, bitmap, qflag, ring, L.ring_cap, blocks,
-                              SPIN_CAP, s)) != hipSuccess)
-            return hip_fail(e, "queue");
+        {
+            LaunchTimer lt(s, MR_K_QUEUE, 0);
+            e = launch_queue(tbytes, conn, imgs, ctrl, bitmap, qflag, ring, L.ring_cap, blocks,
+                             SPIN_CAP, s);
+        }
+        if (e != hipSuccess) return hip_fail(e, "queue");
     } else {
         // converge mode: rounds until a round leaves no dirty tile, polling
         // every few rounds
@@ -199,16 +269,20 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
         while (true) {
             for (uint32_t k = 0; k < poll && round < MAX_ROUNDS; ++k) {
                 ++round;
-                if ((e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl, round,
-                                           tn.max_sweeps, grid, s)) != hipSuccess)
-                    return hip_fail(e, "tile round");
+                {
+                    LaunchTimer lt(s, MR_K_TILE_ROUND, (int32_t)round);
+                    e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl,
+                                          round, tn.max_sweeps, grid, s);
+                }
+                if (e != hipSuccess) return hip_fail(e, "tile round");
             }
-            *hw = 0;
-            if ((e = hipMemcpyAsync(hw, &ctrl->round_tiles[round + 1], sizeof(uint32_t),
+            if ((e = hipMemcpyAsync(hw, ctrl->round_tiles[round + 1], sizeof(uint32_t) * NBANDS,
                                     hipMemcpyDeviceToHost, s)) != hipSuccess)
                 return hip_fail(e, "poll copy");
             if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "poll sync");
-            if (*hw == 0) break;
+            uint64_t next = 0;
+            for (int b = 0; b < NBANDS; ++b) next += ((const uint32_t *)hw)[b];
+            if (next == 0) break;
             if (round >= MAX_ROUNDS) return fail(MR_EHIP, "tile rounds did not converge");
         }
         if ((e = launch_store_u64(&ctrl->rounds, (unsigned long long)round, s)) != hipSuccess)
@@ -272,7 +346,7 @@ extern "C" {
 
 void mr_default_tune(mr_tune *out) {
     if (!out) return;
-    out->sweep_rounds = 4;
+    out->sweep_rounds = -1;
     out->max_sweeps = 16;
     out->persistent_blocks = 0;
     out->reserved = 0;
@@ -310,7 +384,7 @@ int mr_read_counters(const void *ws, mr_counters *out, void *stream) {
     c.rounds = h.rounds;
     c.seeds = h.seeds_total.v;
     for (unsigned long long r = 1; r <= h.rounds && r <= (unsigned long long)MAX_ROUNDS; ++r)
-        c.tiles += h.round_tiles[r];
+        c.tiles += round_total(h, r);
     for (int i = 0; i < NCNT; ++i) {
         c.pops += h.pops[i];
         c.pushes += h.pushes[i];
@@ -333,8 +407,32 @@ int mr_read_round_tiles(const void *ws, uint32_t *out, int32_t cap, int32_t *n_r
     if ((e = hipStreamSynchronize((hipStream_t)stream)) != hipSuccess) return hip_fail(e, "sync");
     const int n = (int)std::min<unsigned long long>(h.rounds + 1, MAX_ROUNDS);
     *n_rounds = (int32_t)h.rounds;
-    for (int i = 0; i < cap && i < n; ++i) out[i] = h.round_tiles[i + 1];
+    for (int i = 0; i < cap && i < n; ++i) out[i] = (uint32_t)round_total(h, i + 1);
     return MR_OK;
+}
+
+int mr_timing_enable(int on) {
+    g_timing.on = on != 0;
+    return MR_OK;
+}
+
+int mr_timing_collect(mr_launch_time *out, int32_t cap, int32_t *n) {
+    g_err.clear();
+    if (!n || cap < 0 || (cap > 0 && !out)) return fail(MR_EINVAL, "bad pointer or cap");
+    *n = (int32_t)g_timing.recs.size();
+    int rc = MR_OK;
+    for (size_t i = 0; i < g_timing.recs.size(); ++i) {
+        TimedLaunch &r = g_timing.recs[i];
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess && rc == MR_OK) rc = hip_fail(e, "event");
+        if ((int32_t)i < cap) out[i] = mr_launch_time{r.kind, r.round, ms};
+        g_timing.pool.push_back(r.a);
+        g_timing.pool.push_back(r.b);
+    }
+    g_timing.recs.clear();
+    return rc;
 }
 
 const char *mr_last_error(void) { return g_err.c_str(); }

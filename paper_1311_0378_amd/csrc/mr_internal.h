@@ -40,6 +40,12 @@ struct alignas(128) Line {
 };
 
 constexpr int NCNT = 64;      // spread counters, summed on the host
+// Tile ids are split into NBANDS contiguous bands, one per XCD of the
+// MI355X: band b holds tiles [b * n / NBANDS, (b + 1) * n / NBANDS). A block
+// of a persistent tile kernel serves band blockIdx.x % NBANDS, which keeps
+// neighbouring tiles (which share cache lines) in one XCD's L2 under the
+// round-robin dispatch of workgroups to XCDs.
+constexpr int NBANDS = 8;
 constexpr int MAX_ROUNDS = 1000; // tile rounds per call (sweep_rounds bound)
 
 struct Ctrl {
@@ -56,10 +62,10 @@ struct Ctrl {
     unsigned long long iters[NCNT];  // sweep iterations over all tile visits (spread)
     unsigned long long rounds;       // written by the host sequence
     unsigned long long watchdog;     // non-zero if a queue block hit its spin cap
-    // round_tiles[r]: length of the dirty list of round r (round 1 = all
-    // tiles, written by the host sequence); round_tiles[k+1] is what the seed
-    // pass starts from after k rounds.
-    uint32_t round_tiles[MAX_ROUNDS + 2];
+    // round_tiles[r][b]: length of band b's dirty list for round r (round 1:
+    // the band's size, written when the block is cleared); round k + 1's lists
+    // are what the seed pass starts from after k rounds.
+    uint32_t round_tiles[MAX_ROUNDS + 2][NBANDS];
 };
 
 // Launch-wide view of the images: a device array of descriptors sorted by
@@ -73,10 +79,11 @@ constexpr uint32_t Q_EMPTY = 0xFFFFFFFFu;
 
 // Host-side launchers (defined in mr_kernels.hip).
 hipError_t launch_clear_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
-hipError_t launch_clear_ctrl(Ctrl *c, uint32_t first_round_tiles, hipStream_t s);
-// Round r visits every tile (r == 1) or the dirty list lists[(r & 1) *
-// n_tiles ...] of length ctrl->round_tiles[r], and puts each tile it dirties
-// on the other half for round r + 1 (flags[t] = latest round t is listed for).
+hipError_t launch_clear_ctrl(Ctrl *c, int64_t n_tiles, hipStream_t s);
+// Round r visits every tile (r == 1) or the dirty lists of round r -- band
+// b's at lists[(r & 1) * n_tiles + band start], ctrl->round_tiles[r][b] long
+// -- and lists each tile it dirties for round r + 1 in the other half
+// (flags[t] = the latest round t is listed for).
 hipError_t launch_tile_round(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
                              uint32_t *flags, uint32_t *lists, Ctrl *ctrl, uint32_t round,
                              int max_iters, int grid, hipStream_t s);

@@ -304,21 +304,44 @@ __device__ __forceinline__ uint64_t col_sum(const uint32_t (&A)[TS]) {
 
 // Tiles newly made dirty by one wave wait in an LDS batch and go to the next
 // round's list with one counter update per batch, not one per tile.
+__device__ __forceinline__ int64_t band_lo(int64_t n_tiles, int b) {
+    return (int64_t)b * n_tiles / NBANDS;
+}
+
+__device__ __forceinline__ int band_of(int64_t n_tiles, int64_t t) {
+    int b = (int)(t * NBANDS / n_tiles);
+    while (b + 1 < NBANDS && band_lo(n_tiles, b + 1) <= t) ++b;
+    while (b > 0 && band_lo(n_tiles, b) > t) --b;
+    return b;
+}
+
 constexpr int APP_CAP = 64;
 struct Appender {
     uint32_t *buf;      // LDS, APP_CAP entries
     uint32_t cnt;       // wave-uniform
-    uint32_t *list_out; // next round's dirty list
-    uint32_t *counter;  // its length
+    uint32_t *list_out; // next round's dirty lists (band b's at its band start)
+    uint32_t *counter;  // their lengths, NBANDS of them
+    int64_t n_tiles;
 };
 
+// Append the batch: each lane takes one entry, and each band present gets
+// one counter update.
 __device__ __forceinline__ void app_flush(Appender &a, int lane) {
     if (a.cnt == 0) return;
-    uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(a.counter, a.cnt);
-    base = __shfl(base, 0);
     __syncthreads();
-    for (uint32_t i = lane; i < a.cnt; i += 64) a.list_out[base + i] = a.buf[i];
+    const bool valid = (uint32_t)lane < a.cnt;
+    const uint32_t e = valid ? a.buf[lane] : 0u;
+    const int be = valid ? band_of(a.n_tiles, e) : -1;
+#pragma unroll
+    for (int b = 0; b < NBANDS; ++b) {
+        const uint64_t m = __ballot(be == b);
+        if (!m) continue;
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(a.counter + b, (uint32_t)__popcll(m));
+        base = __shfl(base, 0);
+        if (be == b)
+            a.list_out[band_lo(a.n_tiles, b) + base + __popcll(m & ((1ull << lane) - 1))] = e;
+    }
     __syncthreads();
     a.cnt = 0;
 }
@@ -426,9 +449,10 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
     app.cnt += (uint32_t)__popcll(fm);
 }
 
-// One tile round on a persistent grid (two waves per SIMD). Round 1 visits
-// every tile; round r > 1 visits its dirty list. Tiles are dealt to the waves
-// by static interleave, so no wave gets more than one tile above another.
+// One tile round on a persistent grid (two waves per SIMD). Block b serves
+// band b % NBANDS; round 1 visits every tile of the band, round r > 1 the
+// band's dirty list. Tiles are dealt to the band's blocks by static
+// interleave, so no block gets more than one tile above another.
 template <typename T, int CONN>
 __global__ __launch_bounds__(64, 2) void k_tile_round(Imgs imgs, int64_t n_tiles,
                                                       uint32_t *__restrict__ flags,
@@ -438,11 +462,15 @@ __global__ __launch_bounds__(64, 2) void k_tile_round(Imgs imgs, int64_t n_tiles
     __shared__ uint32_t tb[TS][TS + 1]; // transpose buffer (and load stage)
     __shared__ uint32_t abuf[APP_CAP];
     const int lane = threadIdx.x;
-    Appender app{abuf, 0, lists + ((round + 1) & 1) * n_tiles, &ctrl->round_tiles[round + 1]};
-    const uint32_t *list_in = lists + (round & 1) * n_tiles;
-    const int64_t n = round == 1 ? n_tiles : (int64_t)ctrl->round_tiles[round];
-    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
-        const int64_t t = round == 1 ? i : (int64_t)list_in[i];
+    const int band = blockIdx.x % NBANDS;
+    const int64_t local = blockIdx.x / NBANDS, per = gridDim.x / NBANDS;
+    const int64_t lo = band_lo(n_tiles, band);
+    Appender app{abuf, 0, lists + ((round + 1) & 1) * n_tiles, ctrl->round_tiles[round + 1],
+                 n_tiles};
+    const uint32_t *list_in = lists + (round & 1) * n_tiles + lo;
+    const int64_t n = ctrl->round_tiles[round][band];
+    for (int64_t i = local; i < n; i += per) {
+        const int64_t t = round == 1 ? lo + i : (int64_t)list_in[i];
         const ImgDesc d = load_desc(imgs, t);
         if (!d.done) {
             if (round == 1) {
@@ -572,9 +600,11 @@ __global__ __launch_bounds__(64) void k_seed(Imgs imgs, int64_t n_tiles,
                                              uint32_t *__restrict__ ring, uint64_t cap) {
     __shared__ uint8_t stage[2 * STAGE_BYTES];
     const int lane = threadIdx.x;
-    const uint32_t *list_in = lists + (round & 1) * n_tiles;
-    const int64_t n = ctrl->round_tiles[round];
-    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const int band = blockIdx.x % NBANDS;
+    const int64_t local = blockIdx.x / NBANDS, per = gridDim.x / NBANDS;
+    const uint32_t *list_in = lists + (round & 1) * n_tiles + band_lo(n_tiles, band);
+    const int64_t n = ctrl->round_tiles[round][band];
+    for (int64_t i = local; i < n; i += per) {
         const int64_t t = list_in[i];
         const ImgDesc d = load_desc(imgs, t);
         if (d.done) continue;
@@ -750,12 +780,14 @@ __global__ void k_clear_u32(uint32_t *p, int64_t n, uint32_t v) {
         p[i] = v;
 }
 
-__global__ void k_clear_ctrl(Ctrl *c, uint32_t first_round_tiles) {
+__global__ void k_clear_ctrl(Ctrl *c, int64_t n_tiles) {
     unsigned long long *p = (unsigned long long *)c;
     const int n = (int)(sizeof(Ctrl) / sizeof(unsigned long long));
     for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
     __syncthreads();
-    if (threadIdx.x == 0) c->round_tiles[1] = first_round_tiles;
+    if (threadIdx.x < NBANDS)
+        c->round_tiles[1][threadIdx.x] =
+            (uint32_t)(band_lo(n_tiles, threadIdx.x + 1) - band_lo(n_tiles, threadIdx.x));
 }
 
 // Fill-holes epilogue: out = NOT J over the interior of every tile of the
@@ -793,8 +825,8 @@ hipError_t launch_clear_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_clear_ctrl(Ctrl *c, uint32_t first_round_tiles, hipStream_t s) {
-    hipLaunchKernelGGL(k_clear_ctrl, dim3(1), dim3(256), 0, s, c, first_round_tiles);
+hipError_t launch_clear_ctrl(Ctrl *c, int64_t n_tiles, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_ctrl, dim3(1), dim3(256), 0, s, c, n_tiles);
     return hipGetLastError();
 }
 
@@ -802,7 +834,8 @@ template <typename T, int CONN>
 static hipError_t tile_round_t(const Imgs &imgs, int64_t n_tiles, uint32_t *flags,
                                uint32_t *lists, Ctrl *ctrl, uint32_t round, int max_iters,
                                int grid, hipStream_t s) {
-    const unsigned g = (unsigned)std::min<int64_t>(grid, n_tiles);
+    const int64_t want = std::max<int64_t>(NBANDS, (n_tiles + NBANDS - 1) / NBANDS * NBANDS);
+    const unsigned g = (unsigned)(std::min<int64_t>(grid, want) / NBANDS * NBANDS);
     hipLaunchKernelGGL((k_tile_round<T, CONN>), dim3(g), dim3(64), 0, s, imgs, n_tiles, flags,
                        lists, ctrl, round, max_iters);
     return hipGetLastError();
@@ -822,7 +855,8 @@ template <typename T, int CONN>
 static hipError_t seed_t(const Imgs &imgs, int64_t n_tiles, const uint32_t *lists,
                          uint32_t round, Ctrl *ctrl, uint64_t *bitmap, uint32_t *qflag,
                          uint32_t *ring, uint64_t cap, int grid, hipStream_t s) {
-    const unsigned g = (unsigned)std::min<int64_t>(grid, n_tiles);
+    const int64_t want = std::max<int64_t>(NBANDS, (n_tiles + NBANDS - 1) / NBANDS * NBANDS);
+    const unsigned g = (unsigned)(std::min<int64_t>(grid, want) / NBANDS * NBANDS);
     hipLaunchKernelGGL((k_seed<T, CONN>), dim3(g), dim3(64), 0, s, imgs, n_tiles, lists, round,
                        ctrl, bitmap, qflag, ring, cap);
     return hipGetLastError();

@@ -35,6 +35,13 @@ class Tune(ctypes.Structure):
                 ("persistent_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class LaunchTime(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("round", ctypes.c_int32), ("ms", ctypes.c_float)]
+
+
+KIND_NAMES = {0: "tile_round", 1: "seed", 2: "queue"}
+
+
 class Counters(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in
                 ("rounds", "tiles", "seeds", "pops", "pushes", "cas_retries", "overflows",
@@ -72,6 +79,10 @@ def lib():
         L.mr_read_round_tiles.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), i32,
                                           ctypes.POINTER(i32), vp]
         L.mr_read_round_tiles.restype = c_int
+        L.mr_timing_enable.argtypes = [c_int]
+        L.mr_timing_enable.restype = c_int
+        L.mr_timing_collect.argtypes = [ctypes.POINTER(LaunchTime), i32, ctypes.POINTER(i32)]
+        L.mr_timing_collect.restype = c_int
         L.mr_last_error.argtypes = []
         L.mr_last_error.restype = ctypes.c_char_p
         L.mr_abi_version.argtypes = []
@@ -179,6 +190,22 @@ def read_round_tiles(workspace: torch.Tensor, stream=None) -> list:
     _check(lib().mr_read_round_tiles(workspace.data_ptr(), buf, cap, ctypes.byref(n),
                                      _stream_ptr(stream)))
     return [int(buf[i]) for i in range(min(cap, n.value + 1))]
+
+
+def timing_enable(on: bool = True) -> None:
+    """Bracket every tile-round, seed and queue launch of this thread's calls
+    with HIP events on the call's stream."""
+    _check(lib().mr_timing_enable(1 if on else 0))
+
+
+def timing_collect() -> list:
+    """Wait for and return the recorded launches as ``(kind, round, ms)``."""
+    n = ctypes.c_int32()
+    cap = 1 << 16
+    buf = (LaunchTime * cap)()
+    _check(lib().mr_timing_collect(buf, cap, ctypes.byref(n)))
+    return [(KIND_NAMES.get(buf[i].kind, str(buf[i].kind)), int(buf[i].round), float(buf[i].ms))
+            for i in range(min(cap, n.value))]
 
 
 def read_counters(workspace: torch.Tensor, stream=None) -> dict:

@@ -25,7 +25,7 @@ def test_abi_version(L):
 
 def test_default_tune():
     t = mrecon.default_tune()
-    assert t.sweep_rounds >= 1 and 1 <= t.max_sweeps <= 1024 and t.reserved == 0
+    assert t.sweep_rounds != 0 and 1 <= t.max_sweeps <= 1024 and t.reserved == 0
 
 
 def test_workspace_bytes_grows_with_size():
