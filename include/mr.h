@@ -122,6 +122,52 @@ int mr_recon_dilate(void *marker_inout, const void *mask, int64_t H, int64_t W, 
 int mr_fill_holes(void *img_inout, int64_t H, int64_t W, int64_t pitch, mr_dtype t, int conn,
                   void *ws, size_t ws_bytes, const mr_tune *tune, void *stream);
 
+/* ------------------------------------------------------------- batches */
+
+/* One image of a batch (the tiles of a whole-slide image are independent
+ * images here: no propagation crosses from one to another). */
+typedef struct {
+    void *data_inout;  /* device: the marker (MR_OP_RECON) or the image
+                          (MR_OP_FILL); replaced by the result */
+    const void *mask;  /* device: the mask (MR_OP_RECON, same pitch as the
+                          data); NULL for MR_OP_FILL */
+    int64_t H, W;
+    int64_t pitch;     /* elements, >= W; 0 = W */
+    int32_t op;        /* MR_OP_RECON or MR_OP_FILL */
+    int32_t reserved;  /* must be 0 */
+} mr_tile;
+
+/* Workspace bytes for mr_batch over tiles[0..n). 0 on invalid arguments. */
+size_t mr_batch_workspace_bytes(const mr_tile *tiles, int32_t n, mr_dtype t, int conn,
+                                const mr_tune *tune);
+
+/* Runs every image of the batch through one launch sequence: the tile
+ * rounds, seed pass and queue phase each cover all images at once, so small
+ * and large images share the GPU. Pixel type and connectivity are common to
+ * the batch; op may differ per image. `tiles` is host memory, read before the
+ * call returns. Errors as for mr_recon_dilate, checked for every image. */
+int mr_batch(const mr_tile *tiles, int32_t n, mr_dtype t, int conn, void *ws, size_t ws_bytes,
+             const mr_tune *tune, void *stream);
+
+/* A batch captured once into a HIP graph, for repeated launches over the same
+ * buffers (new data copied into them between launches). Needs
+ * tune->sweep_rounds > 0 (a fixed number of tile rounds, then the queue
+ * phase), because the converge mode waits on the host. */
+typedef struct mr_graph mr_graph;
+int mr_batch_graph_create(const mr_tile *tiles, int32_t n, mr_dtype t, int conn, void *ws,
+                          size_t ws_bytes, const mr_tune *tune, mr_graph **out);
+int mr_graph_launch(mr_graph *g, void *stream);
+void mr_graph_destroy(mr_graph *g);
+
+/* Autotuner: times candidate tunings (sweep rounds before the queue phase,
+ * sweep cap per tile visit) of mr_batch on this batch and writes the fastest
+ * to *out. The tiles' data are restored afterwards. ws must hold
+ * mr_autotune_workspace_bytes bytes (the batch workspace plus a backup of
+ * the data). Waits for `stream`. */
+size_t mr_autotune_workspace_bytes(const mr_tile *tiles, int32_t n, mr_dtype t, int conn);
+int mr_autotune(const mr_tile *tiles, int32_t n, mr_dtype t, int conn, void *ws, size_t ws_bytes,
+                void *stream, mr_tune *out);
+
 /* Copies the work counters held in a workspace to *out. Waits for `stream`.
  * Errors: MR_EINVAL (null pointer), MR_EHIP. */
 int mr_read_counters(const void *ws, mr_counters *out, void *stream);

@@ -65,13 +65,14 @@ struct Layout {
     int64_t plane_pitch = 0;
 };
 
-Layout layout_for(int64_t n_tiles, int64_t fill_plane_bytes, int64_t plane_pitch) {
+Layout layout_for(int64_t n_tiles, int64_t fill_plane_bytes, int64_t plane_pitch,
+                  int64_t n_imgs = 1) {
     Layout L;
     L.n_tiles = n_tiles;
     L.ring_cap = next_pow2((uint64_t)n_tiles + 8192);
     size_t o = align_up(sizeof(Ctrl), 256);
     L.off_desc = o;
-    o = align_up(o + sizeof(ImgDesc), 256);
+    o = align_up(o + sizeof(ImgDesc) * (size_t)n_imgs, 256);
     L.off_flags = o;
     o = align_up(o + (size_t)n_tiles * 4, 256);
     L.off_lists = o;
@@ -340,7 +341,93 @@ int run_single(int op, void *J_io, const void *I, int64_t H, int64_t W, int64_t 
     return run_sequence(t, conn, imgs, L, ws, tn, (hipStream_t)stream, op == MR_OP_FILL);
 }
 
+// ---------------------------------------------------------------- batches
+
+size_t plane_bytes(int64_t H, int64_t W, int t) {
+    return align_up((size_t)H * align_up((size_t)W, 64) * (size_t)t, 256);
+}
+
+struct BatchPlan {
+    Layout L;
+    std::vector<ImgDesc> descs;
+    bool any_fill = false;
+    size_t data_bytes = 0; // sum of H * W * t (autotune backup)
+};
+
+// Checks every image and lays the batch out in a workspace (ws may be null
+// when only the size is wanted).
+int plan_batch(const mr_tile *tiles, int32_t n, int t, int conn, void *ws, BatchPlan &bp) {
+    if (!tiles || n < 1) return fail(MR_EINVAL, "need at least one tile");
+    int64_t n_tiles = 0, fill_bytes = 0;
+    bp.descs.resize((size_t)n);
+    for (int32_t i = 0; i < n; ++i) {
+        const mr_tile &tl = tiles[i];
+        int rc = check_image(tl.op, tl.H, tl.W, tl.pitch, t, conn);
+        if (rc != MR_OK) return fail(rc, "tile %d: %s", i, g_err.c_str());
+        if (tl.reserved != 0) return fail(MR_EINVAL, "tile %d: reserved must be 0", i);
+        if (!tl.data_inout) return fail(MR_EINVAL, "tile %d: null data pointer", i);
+        if (tl.op == MR_OP_RECON && !tl.mask) return fail(MR_EINVAL, "tile %d: null mask", i);
+        if ((uintptr_t)tl.data_inout % t || (tl.mask && (uintptr_t)tl.mask % t))
+            return fail(MR_EINVAL, "tile %d: pointers must be aligned to the pixel size", i);
+        ImgDesc &d = bp.descs[(size_t)i];
+        d = ImgDesc{};
+        d.H = tl.H;
+        d.W = tl.W;
+        d.op = tl.op;
+        d.ntx = (int32_t)tiles_across(tl.W);
+        d.nty = (int32_t)tiles_across(tl.H);
+        d.tile_base = n_tiles;
+        d.done = 0;
+        const int64_t pitch = tl.pitch ? tl.pitch : tl.W;
+        if (tl.op == MR_OP_RECON) {
+            d.J = tl.data_inout;
+            d.I = tl.mask;
+            d.pJ = d.pI = pitch;
+        } else {
+            d.J = (void *)(uintptr_t)fill_bytes; // offset for now, based below
+            d.I = tl.data_inout;
+            d.out = tl.data_inout;
+            d.pJ = (int64_t)align_up((size_t)tl.W, 64);
+            d.pI = pitch;
+            fill_bytes += (int64_t)plane_bytes(tl.H, tl.W, t);
+            bp.any_fill = true;
+        }
+        d.px_base = 0;
+        n_tiles += (int64_t)d.ntx * d.nty;
+        bp.data_bytes += align_up((size_t)tl.H * tl.W * t, 256);
+        if (n_tiles >= (1ll << 31) - 1) return fail(MR_EINVAL, "batch too large");
+    }
+    bp.L = layout_for(n_tiles, fill_bytes, 0, n);
+    for (auto &d : bp.descs)
+        if (d.op == MR_OP_FILL)
+            d.J = ws ? (void *)((char *)ws + bp.L.off_plane + (uintptr_t)d.J) : nullptr;
+    return MR_OK;
+}
+
+int run_batch(const mr_tile *tiles, int32_t n, int t, int conn, void *ws, size_t ws_bytes,
+              const mr_tune *tune, hipStream_t s) {
+    int rc;
+    if ((rc = check_tune(tune)) != MR_OK) return rc;
+    if (!ws) return fail(MR_EINVAL, "null workspace");
+    if ((uintptr_t)ws % 256) return fail(MR_EINVAL, "workspace must be 256-byte aligned");
+    BatchPlan bp;
+    if ((rc = plan_batch(tiles, n, t, conn, ws, bp)) != MR_OK) return rc;
+    if (ws_bytes < bp.L.total)
+        return fail(MR_ENOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes,
+                    bp.L.total);
+    ImgDesc *dd = (ImgDesc *)((char *)ws + bp.L.off_desc);
+    hipError_t e = launch_put_descs(dd, bp.descs.data(), n, s);
+    if (e != hipSuccess) return hip_fail(e, "descriptors");
+    Imgs imgs{dd, n};
+    return run_sequence(t, conn, imgs, bp.L, ws, effective_tune(tune), s, bp.any_fill);
+}
+
 } // namespace
+
+struct mr_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
 
 extern "C" {
 
@@ -370,6 +457,152 @@ int mr_fill_holes(void *img_inout, int64_t H, int64_t W, int64_t pitch, mr_dtype
                   void *ws, size_t ws_bytes, const mr_tune *tune, void *stream) {
     return run_single(MR_OP_FILL, img_inout, nullptr, H, W, pitch, (int)t, conn, ws, ws_bytes,
                       tune, stream);
+}
+
+size_t mr_batch_workspace_bytes(const mr_tile *tiles, int32_t n, mr_dtype t, int conn,
+                                const mr_tune *tune) {
+    g_err.clear();
+    if (check_tune(tune) != MR_OK) return 0;
+    BatchPlan bp;
+    if (plan_batch(tiles, n, (int)t, conn, nullptr, bp) != MR_OK) return 0;
+    return bp.L.total;
+}
+
+int mr_batch(const mr_tile *tiles, int32_t n, mr_dtype t, int conn, void *ws, size_t ws_bytes,
+             const mr_tune *tune, void *stream) {
+    g_err.clear();
+    return run_batch(tiles, n, (int)t, conn, ws, ws_bytes, tune, (hipStream_t)stream);
+}
+
+int mr_batch_graph_create(const mr_tile *tiles, int32_t n, mr_dtype t, int conn, void *ws,
+                          size_t ws_bytes, const mr_tune *tune, mr_graph **out) {
+    g_err.clear();
+    if (!out) return fail(MR_EINVAL, "null output handle");
+    *out = nullptr;
+    if (!tune || tune->sweep_rounds <= 0)
+        return fail(MR_EINVAL, "a graph needs tune->sweep_rounds > 0 (the converge mode waits "
+                               "on the host)");
+    hipStream_t s = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "stream");
+    const bool timing = g_timing.on;
+    g_timing.on = false;
+    mr_graph *g = new mr_graph();
+    int rc = MR_OK;
+    if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+        rc = hip_fail(e, "begin capture");
+    } else {
+        rc = run_batch(tiles, n, (int)t, conn, ws, ws_bytes, tune, s);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(s, &graph);
+        if (rc == MR_OK && e != hipSuccess) rc = hip_fail(e, "end capture");
+        g->graph = graph;
+        if (rc == MR_OK && (e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0)) !=
+                               hipSuccess)
+            rc = hip_fail(e, "instantiate");
+    }
+    g_timing.on = timing;
+    hipStreamDestroy(s);
+    if (rc != MR_OK) {
+        mr_graph_destroy(g);
+        return rc;
+    }
+    *out = g;
+    return MR_OK;
+}
+
+int mr_graph_launch(mr_graph *g, void *stream) {
+    g_err.clear();
+    if (!g || !g->exec) return fail(MR_EINVAL, "null graph");
+    hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+    return e == hipSuccess ? MR_OK : hip_fail(e, "graph launch");
+}
+
+void mr_graph_destroy(mr_graph *g) {
+    if (!g) return;
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    if (g->graph) hipGraphDestroy(g->graph);
+    delete g;
+}
+
+size_t mr_autotune_workspace_bytes(const mr_tile *tiles, int32_t n, mr_dtype t, int conn) {
+    g_err.clear();
+    BatchPlan bp;
+    if (plan_batch(tiles, n, (int)t, conn, nullptr, bp) != MR_OK) return 0;
+    return bp.L.total + bp.data_bytes;
+}
+
+int mr_autotune(const mr_tile *tiles, int32_t n, mr_dtype t, int conn, void *ws, size_t ws_bytes,
+                void *stream, mr_tune *out) {
+    g_err.clear();
+    if (!out) return fail(MR_EINVAL, "null output tune");
+    if (!ws || (uintptr_t)ws % 256) return fail(MR_EINVAL, "bad workspace");
+    const int ti = (int)t;
+    BatchPlan bp;
+    int rc;
+    if ((rc = plan_batch(tiles, n, ti, conn, ws, bp)) != MR_OK) return rc;
+    if (ws_bytes < bp.L.total + bp.data_bytes)
+        return fail(MR_ENOMEM, "workspace too small for the autotuner: %zu given, %zu needed",
+                    ws_bytes, bp.L.total + bp.data_bytes);
+    hipStream_t s = (hipStream_t)stream;
+    char *backup = (char *)ws + bp.L.total;
+    // copy the data aside, and back before every candidate and at the end
+    auto copy_all = [&](bool to_backup) -> hipError_t {
+        size_t off = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            const mr_tile &tl = tiles[i];
+            const size_t row = (size_t)tl.W * ti, pitch = (size_t)(tl.pitch ? tl.pitch : tl.W) * ti;
+            hipError_t e = to_backup
+                ? hipMemcpy2DAsync(backup + off, row, tl.data_inout, pitch, row, (size_t)tl.H,
+                                   hipMemcpyDeviceToDevice, s)
+                : hipMemcpy2DAsync(tl.data_inout, pitch, backup + off, row, row, (size_t)tl.H,
+                                   hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return e;
+            off += align_up((size_t)tl.H * tl.W * ti, 256);
+        }
+        return hipSuccess;
+    };
+    hipError_t e = copy_all(true);
+    if (e != hipSuccess) return hip_fail(e, "backup");
+    static const int cand[][2] = {{-1, 16}, {-1, 3}, {4, 16}, {8, 16}, {12, 16}, {16, 16},
+                                  {24, 16}, {32, 16}, {48, 16}, {16, 3}};
+    hipEvent_t a = nullptr, b = nullptr;
+    if ((e = hipEventCreate(&a)) != hipSuccess || (e = hipEventCreate(&b)) != hipSuccess)
+        return hip_fail(e, "event");
+    const bool timing = g_timing.on;
+    g_timing.on = false;
+    float best = 1e30f;
+    mr_tune bt;
+    mr_default_tune(&bt);
+    for (const auto &c : cand) {
+        mr_tune tn;
+        mr_default_tune(&tn);
+        tn.sweep_rounds = c[0];
+        tn.max_sweeps = c[1];
+        float t_best = 1e30f;
+        for (int rep = 0; rep < 2 && rc == MR_OK; ++rep) {
+            if ((e = copy_all(false)) != hipSuccess) { rc = hip_fail(e, "restore"); break; }
+            hipEventRecord(a, s);
+            rc = run_batch(tiles, n, ti, conn, ws, ws_bytes, &tn, s);
+            hipEventRecord(b, s);
+            if ((e = hipEventSynchronize(b)) != hipSuccess) { rc = hip_fail(e, "sync"); break; }
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, a, b);
+            t_best = std::min(t_best, ms);
+        }
+        if (rc != MR_OK) break;
+        if (t_best < best) {
+            best = t_best;
+            bt = tn;
+        }
+    }
+    g_timing.on = timing;
+    if (rc == MR_OK && (e = copy_all(false)) != hipSuccess) rc = hip_fail(e, "restore");
+    if (rc == MR_OK && (e = hipStreamSynchronize(s)) != hipSuccess) rc = hip_fail(e, "sync");
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    if (rc == MR_OK) *out = bt;
+    return rc;
 }
 
 int mr_read_counters(const void *ws, mr_counters *out, void *stream) {

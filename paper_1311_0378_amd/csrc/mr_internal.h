@@ -97,6 +97,10 @@ hipError_t launch_queue(int tbytes, int conn, const Imgs &imgs, Ctrl *ctrl, uint
 hipError_t launch_fill_output(int tbytes, const Imgs &imgs, int64_t n_tiles, hipStream_t s);
 hipError_t launch_store_u64(unsigned long long *p, unsigned long long v, hipStream_t s);
 hipError_t launch_put_desc(ImgDesc *dst, const ImgDesc &v, hipStream_t s);
+// Writes n descriptors (n <= DESC_CHUNK per launch) through kernel arguments,
+// which keeps uploads stream-ordered and capturable.
+constexpr int DESC_CHUNK = 16;
+hipError_t launch_put_descs(ImgDesc *dst, const ImgDesc *v, int n, hipStream_t s);
 int queue_max_blocks(int tbytes, int conn);
 
 } // namespace mr

@@ -816,6 +816,15 @@ __global__ void k_store_u64(unsigned long long *p, unsigned long long v) { *p = 
 
 __global__ void k_put_desc(ImgDesc *dst, ImgDesc v) { *dst = v; }
 
+struct DescChunk {
+    ImgDesc d[DESC_CHUNK];
+    int n;
+};
+
+__global__ void k_put_descs(ImgDesc *dst, DescChunk c) {
+    if ((int)threadIdx.x < c.n) dst[threadIdx.x] = c.d[threadIdx.x];
+}
+
 // ---------------------------------------------------------------- launchers
 
 hipError_t launch_clear_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
@@ -936,6 +945,18 @@ hipError_t launch_fill_output(int tbytes, const Imgs &imgs, int64_t n_tiles, hip
 hipError_t launch_put_desc(ImgDesc *dst, const ImgDesc &v, hipStream_t s) {
     hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(1), 0, s, dst, v);
     return hipGetLastError();
+}
+
+hipError_t launch_put_descs(ImgDesc *dst, const ImgDesc *v, int n, hipStream_t s) {
+    for (int i = 0; i < n; i += DESC_CHUNK) {
+        DescChunk c{};
+        c.n = std::min(DESC_CHUNK, n - i);
+        for (int k = 0; k < c.n; ++k) c.d[k] = v[i + k];
+        hipLaunchKernelGGL(k_put_descs, dim3(1), dim3(DESC_CHUNK), 0, s, dst + i, c);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_store_u64(unsigned long long *p, unsigned long long v, hipStream_t s) {

@@ -35,6 +35,12 @@ class Tune(ctypes.Structure):
                 ("persistent_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class Tile(ctypes.Structure):
+    _fields_ = [("data_inout", ctypes.c_void_p), ("mask", ctypes.c_void_p),
+                ("H", ctypes.c_int64), ("W", ctypes.c_int64), ("pitch", ctypes.c_int64),
+                ("op", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class LaunchTime(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("round", ctypes.c_int32), ("ms", ctypes.c_float)]
 
@@ -79,6 +85,22 @@ def lib():
         L.mr_read_round_tiles.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), i32,
                                           ctypes.POINTER(i32), vp]
         L.mr_read_round_tiles.restype = c_int
+        TP = ctypes.POINTER(Tile)
+        L.mr_batch_workspace_bytes.argtypes = [TP, i32, c_int, c_int, ctypes.POINTER(Tune)]
+        L.mr_batch_workspace_bytes.restype = sz
+        L.mr_batch.argtypes = [TP, i32, c_int, c_int, vp, sz, ctypes.POINTER(Tune), vp]
+        L.mr_batch.restype = c_int
+        L.mr_batch_graph_create.argtypes = [TP, i32, c_int, c_int, vp, sz, ctypes.POINTER(Tune),
+                                            ctypes.POINTER(vp)]
+        L.mr_batch_graph_create.restype = c_int
+        L.mr_graph_launch.argtypes = [vp, vp]
+        L.mr_graph_launch.restype = c_int
+        L.mr_graph_destroy.argtypes = [vp]
+        L.mr_graph_destroy.restype = None
+        L.mr_autotune_workspace_bytes.argtypes = [TP, i32, c_int, c_int]
+        L.mr_autotune_workspace_bytes.restype = sz
+        L.mr_autotune.argtypes = [TP, i32, c_int, c_int, vp, sz, vp, ctypes.POINTER(Tune)]
+        L.mr_autotune.restype = c_int
         L.mr_timing_enable.argtypes = [c_int]
         L.mr_timing_enable.restype = c_int
         L.mr_timing_collect.argtypes = [ctypes.POINTER(LaunchTime), i32, ctypes.POINTER(i32)]
@@ -179,6 +201,91 @@ def fill_holes(img: torch.Tensor, conn: int = 8, tune=None,
     _check(lib().mr_fill_holes(img.data_ptr(), H, W, pitch, t, conn, workspace.data_ptr(),
                                workspace.numel(), _tune_ptr(tune), _stream_ptr(stream)))
     return img
+
+
+def make_tiles(items):
+    """``items``: sequence of ``(data, mask, op)`` with ``mask`` None for
+    fill-holes. Returns ``(Tile array, n, pixel type, torch dtype)``."""
+    items = list(items)
+    if not items:
+        raise ValueError("empty batch")
+    arr = (Tile * len(items))()
+    dtype = items[0][0].dtype
+    for i, (data, mask, op) in enumerate(items):
+        H, W, pitch, t = _image_args(data)
+        if data.dtype != dtype:
+            raise TypeError("all images of a batch share one pixel type")
+        if mask is not None and (mask.shape != data.shape or mask.stride() != data.stride()
+                                 or mask.dtype != dtype):
+            raise ValueError(f"image {i}: mask must match the data's shape, dtype and strides")
+        arr[i] = Tile(data.data_ptr(), mask.data_ptr() if mask is not None else None,
+                      H, W, pitch, int(op), 0)
+    return arr, len(items), _DTYPES[dtype], dtype
+
+
+def batch_workspace_bytes(items, conn: int = 8, tune=None) -> int:
+    arr, n, t, _ = make_tiles(items)
+    nb = lib().mr_batch_workspace_bytes(arr, n, t, conn, _tune_ptr(tune))
+    if nb == 0:
+        raise MrError(MR_EINVAL, lib().mr_last_error().decode())
+    return int(nb)
+
+
+def batch(items, conn: int = 8, tune=None, workspace: torch.Tensor | None = None, stream=None):
+    """Reconstruction / fill-holes of every ``(data, mask, op)`` item in one
+    launch sequence; results replace each ``data`` in place."""
+    arr, n, t, _ = make_tiles(items)
+    dev = items[0][0].device
+    if workspace is None:
+        workspace = alloc_workspace(batch_workspace_bytes(items, conn, tune), dev)
+    _check(lib().mr_batch(arr, n, t, conn, workspace.data_ptr(), workspace.numel(),
+                          _tune_ptr(tune), _stream_ptr(stream)))
+    return workspace
+
+
+class BatchGraph:
+    """A batch captured into a HIP graph; ``launch()`` replays it on the same
+    buffers. Needs a tune with sweep_rounds > 0."""
+
+    def __init__(self, items, conn: int = 8, tune=None, workspace: torch.Tensor | None = None):
+        arr, n, t, _ = make_tiles(items)
+        self.items = list(items)  # keep the tensors alive
+        if workspace is None:
+            workspace = alloc_workspace(batch_workspace_bytes(items, conn, tune),
+                                        items[0][0].device)
+        self.workspace = workspace
+        h = ctypes.c_void_p()
+        _check(lib().mr_batch_graph_create(arr, n, t, conn, workspace.data_ptr(),
+                                           workspace.numel(), _tune_ptr(tune), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib().mr_graph_launch(self._h, _stream_ptr(stream)))
+
+    def close(self):
+        if self._h:
+            lib().mr_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(items, conn: int = 8, stream=None) -> Tune:
+    """Time candidate tunings of ``batch`` on these items (their data are
+    restored) and return the fastest."""
+    arr, n, t, _ = make_tiles(items)
+    nb = lib().mr_autotune_workspace_bytes(arr, n, t, conn)
+    if nb == 0:
+        raise MrError(MR_EINVAL, lib().mr_last_error().decode())
+    ws = alloc_workspace(int(nb), items[0][0].device)
+    out = Tune()
+    _check(lib().mr_autotune(arr, n, t, conn, ws.data_ptr(), ws.numel(), _stream_ptr(stream),
+                             ctypes.byref(out)))
+    return out
 
 
 def read_round_tiles(workspace: torch.Tensor, stream=None) -> list:

@@ -95,3 +95,49 @@ def test_fill_rejects(L):
 
 def test_read_counters_rejects_null(L):
     assert L.mr_read_counters(None, None, None) == mrecon.MR_EINVAL
+
+
+def _tiles(specs):
+    arr = (mrecon.Tile * len(specs))()
+    for i, (data, mask, H, W, pitch, op, res) in enumerate(specs):
+        arr[i] = mrecon.Tile(data, mask, H, W, pitch, op, res)
+    return arr
+
+
+@pytest.mark.parametrize("spec", [
+    (FAKE, 0, 8, 8, 0, 0, 0),        # recon without a mask
+    (0, FAKE, 8, 8, 0, 0, 0),        # null data
+    (FAKE, FAKE, 0, 8, 0, 0, 0),     # empty image
+    (FAKE, FAKE, 8, 8, 4, 0, 0),     # pitch < W
+    (FAKE, FAKE, 8, 8, 0, 3, 0),     # unknown op
+    (FAKE, FAKE, 8, 8, 0, 0, 1),     # reserved set
+])
+def test_batch_rejects(L, spec):
+    arr = _tiles([(FAKE, FAKE, 16, 16, 0, 0, 0), spec])
+    assert L.mr_batch_workspace_bytes(arr, 2, 1, 8, None) == 0
+    assert b"tile 1" in L.mr_last_error()
+    rc = L.mr_batch(arr, 2, 1, 8, ctypes.c_void_p(FAKE), 1 << 40, None, None)
+    assert rc == mrecon.MR_EINVAL
+
+
+def test_batch_workspace_sizes(L):
+    one = _tiles([(FAKE, FAKE, 300, 200, 0, 0, 0)])
+    two = _tiles([(FAKE, FAKE, 300, 200, 0, 0, 0), (FAKE, 0, 100, 90, 0, 1, 0)])
+    a = L.mr_batch_workspace_bytes(one, 1, 1, 8, None)
+    b = L.mr_batch_workspace_bytes(two, 2, 1, 8, None)
+    assert 0 < a < b
+    assert b - a >= 100 * 128  # the fill image's working plane
+    assert L.mr_batch_workspace_bytes(one, 0, 1, 8, None) == 0
+    assert L.mr_autotune_workspace_bytes(one, 1, 1, 8) >= a + 300 * 200
+    rc = L.mr_batch(one, 1, 1, 8, ctypes.c_void_p(FAKE), a - 256, None, None)
+    assert rc == mrecon.MR_ENOMEM
+
+
+def test_graph_needs_fixed_rounds(L):
+    one = _tiles([(FAKE, FAKE, 30, 20, 0, 0, 0)])
+    h = ctypes.c_void_p()
+    t = mrecon.default_tune()
+    t.sweep_rounds = -1
+    rc = L.mr_batch_graph_create(one, 1, 1, 8, ctypes.c_void_p(FAKE), 1 << 30, ctypes.byref(t),
+                                 ctypes.byref(h))
+    assert rc == mrecon.MR_EINVAL and not h.value
