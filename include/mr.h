@@ -168,6 +168,64 @@ size_t mr_autotune_workspace_bytes(const mr_tile *tiles, int32_t n, mr_dtype t, 
 int mr_autotune(const mr_tile *tiles, int32_t n, mr_dtype t, int conn, void *ws, size_t ws_bytes,
                 void *stream, mr_tune *out);
 
+/* --------------------------------------------------------------- serving */
+
+/* A request: one image in host memory, answered in host memory. Rows are
+ * `ld` elements apart in all three host buffers (0 means W), so a job can be a
+ * window of a larger image. The buffers must stay valid until the job is
+ * reported done; pinned (page-locked) memory lets the copies run
+ * asynchronously, pageable memory works but copies synchronously. */
+typedef struct {
+    const void *data; /* H x W: the marker (MR_OP_RECON) or the image (MR_OP_FILL) */
+    const void *mask; /* H x W mask (MR_OP_RECON); NULL otherwise */
+    void *result;     /* H x W: receives the result; may alias data */
+    int64_t H, W;
+    int64_t ld;       /* host row pitch in elements, >= W, or 0 */
+    int32_t op;       /* MR_OP_RECON or MR_OP_FILL */
+    int32_t reserved; /* must be 0 */
+} mr_job;
+
+/* Continuous-batching server over a caller-provided device arena, the HBM
+ * budget (256-byte aligned, at least a few MiB). The arena's head holds the
+ * server's descriptors, per-tile arrays and counters; the rest is handed out
+ * to jobs, two planes each. A job is admitted when a slot, arena space and
+ * tile ids are free. Each step launches one tile round over every resident
+ * job on `stream`; a job admitted between steps joins the next round,
+ * overlapping the jobs already on the device. Dirty-tile lists (the
+ * frontiers) stay in the arena between steps. A job is finished when a round
+ * leaves none of its tiles dirty; its result is then copied back.
+ *
+ * Pipelining: input and result copies run on a second stream that the server
+ * creates, so they overlap the rounds; a step launches round r and then
+ * retires what round r-1 finished, so the device always has the next round
+ * queued. All calls for one server must come from one thread.
+ *
+ * Errors: MR_EINVAL (bad argument), MR_ENOMEM (arena too small), MR_EHIP. */
+typedef struct mr_server mr_server;
+int mr_server_create(void *arena, size_t arena_bytes, int32_t max_jobs, mr_dtype t, int conn,
+                     void *stream, mr_server **out);
+/* Admits a job: starts its input copies and returns its id.
+ * MR_EAGAIN: no slot, arena space or tile ids free now -- retry after steps.
+ * MR_EINVAL: the job is malformed or could never fit this arena. */
+int mr_server_submit(mr_server *s, const mr_job *job, uint64_t *id);
+/* Launches the next tile round (if any job is still working) and retires
+ * the jobs the previous round finished: their result copies are started.
+ * Blocks until the previous round has completed. */
+int mr_server_step(mr_server *s);
+/* Ids of jobs whose results have fully arrived in their host buffers since
+ * the last poll (up to cap), in the order they finished. Does not block. */
+int mr_server_poll(mr_server *s, uint64_t *done_ids, int32_t cap, int32_t *n_done);
+/* Steps until every job is finished and every result copy has completed;
+ * their ids stay available to mr_server_poll. */
+int mr_server_drain(mr_server *s);
+/* Jobs on the device (admitted and not yet fully returned), tile rounds
+ * launched, largest free arena block. */
+int mr_server_stats(const mr_server *s, int32_t *resident, uint64_t *rounds,
+                    size_t *free_bytes);
+/* Waits for the server's work, then frees its host-side state and streams
+ * (the arena stays the caller's). */
+void mr_server_destroy(mr_server *s);
+
 /* Copies the work counters held in a workspace to *out. Waits for `stream`.
  * Errors: MR_EINVAL (null pointer), MR_EHIP. */
 int mr_read_counters(const void *ws, mr_counters *out, void *stream);

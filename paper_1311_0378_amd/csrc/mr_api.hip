@@ -41,21 +41,7 @@ uint64_t next_pow2(uint64_t v) {
 // queue always drains long before this on a working device).
 constexpr unsigned long long SPIN_CAP = 1ull << 16;
 
-// Grid of the persistent tile kernels (tile rounds, seed): two 64-thread
-// blocks per SIMD, the tile kernel's occupancy.
-int scan_grid() {
-    static int g = 0;
-    if (!g) {
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-            cus > 0)
-            g = cus * 8;
-        else
-            g = 2048;
-    }
-    return g;
-}
+
 
 // Where everything lives inside a workspace.
 struct Layout {
@@ -215,7 +201,7 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
     uint32_t *qflag = (uint32_t *)(base + L.off_qflag);
     uint64_t *bitmap = (uint64_t *)(base + L.off_bitmap);
     uint32_t *ring = (uint32_t *)(base + L.off_ring);
-    const int grid = scan_grid();
+    const int grid = persistent_grid(); // two 64-thread blocks per SIMD
     hipError_t e;
 
     if ((e = launch_clear_ctrl(ctrl, L.n_tiles, s)) != hipSuccess)
@@ -317,7 +303,7 @@ int run_single(int op, void *J_io, const void *I, int64_t H, int64_t W, int64_t 
     d.ntx = (int32_t)tiles_across(W);
     d.nty = (int32_t)tiles_across(H);
     d.tile_base = 0;
-    d.px_base = 0;
+    d.first_round = 1;
     d.done = 0;
     if (op == MR_OP_RECON) {
         d.J = J_io;
@@ -335,6 +321,7 @@ int run_single(int op, void *J_io, const void *I, int64_t H, int64_t W, int64_t 
     const mr_tune tn = effective_tune(tune);
     Imgs imgs{};
     imgs.n = 1;
+    imgs.owner = nullptr;
     imgs.d = (const ImgDesc *)((char *)ws + L.off_desc);
     hipError_t e = launch_put_desc((ImgDesc *)imgs.d, d, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "descriptor");
@@ -392,7 +379,7 @@ int plan_batch(const mr_tile *tiles, int32_t n, int t, int conn, void *ws, Batch
             fill_bytes += (int64_t)plane_bytes(tl.H, tl.W, t);
             bp.any_fill = true;
         }
-        d.px_base = 0;
+        d.first_round = 1;
         n_tiles += (int64_t)d.ntx * d.nty;
         bp.data_bytes += align_up((size_t)tl.H * tl.W * t, 256);
         if (n_tiles >= (1ll << 31) - 1) return fail(MR_EINVAL, "batch too large");
@@ -418,11 +405,19 @@ int run_batch(const mr_tile *tiles, int32_t n, int t, int conn, void *ws, size_t
     ImgDesc *dd = (ImgDesc *)((char *)ws + bp.L.off_desc);
     hipError_t e = launch_put_descs(dd, bp.descs.data(), n, s);
     if (e != hipSuccess) return hip_fail(e, "descriptors");
-    Imgs imgs{dd, n};
+    Imgs imgs{dd, n, nullptr};
     return run_sequence(t, conn, imgs, bp.L, ws, effective_tune(tune), s, bp.any_fill);
 }
 
 } // namespace
+
+namespace mr {
+void clear_error() { g_err.clear(); }
+int set_error(int code, const char *msg) {
+    g_err = msg;
+    return code;
+}
+} // namespace mr
 
 struct mr_graph {
     hipGraph_t graph = nullptr;

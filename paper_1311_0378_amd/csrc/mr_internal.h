@@ -25,11 +25,11 @@ struct ImgDesc {
     void *out;         // fill-holes: where NOT J goes at the end; else null
     int64_t H, W;
     int64_t pJ, pI;    // pitches in elements (out uses pI)
-    int64_t tile_base; // first tile of this image in the launch's tile list
-    int64_t px_base;   // frontier id of pixel (0, 0); ids are px_base + y*W + x
-    int32_t ntx, nty;  // tiles across and down
-    int32_t op;        // MR_OP_RECON or MR_OP_FILL
-    int32_t done;      // serving: 1 once the image needs no more device work
+    int64_t tile_base;   // first tile id of this image (its tiles are consecutive)
+    int64_t first_round; // the tile round that builds its initial working image
+    int32_t ntx, nty;    // tiles across and down
+    int32_t op;          // MR_OP_RECON or MR_OP_FILL
+    int32_t done;        // serving: 1 once the image needs no more device work
 };
 
 // Device control block at the start of every workspace. Contended words sit
@@ -68,14 +68,21 @@ struct Ctrl {
     uint32_t round_tiles[MAX_ROUNDS + 2][NBANDS];
 };
 
-// Launch-wide view of the images: a device array of descriptors sorted by
-// tile_base (single-image calls keep theirs in the workspace).
+// Launch-wide view of the images: a device array of descriptors. Without an
+// owner table the descriptors are sorted by tile_base and a tile's image is
+// found by binary search; the server keeps owner[t] = descriptor index.
 struct Imgs {
     const ImgDesc *d;
     int32_t n;
+    const uint32_t *owner;
 };
 
 constexpr uint32_t Q_EMPTY = 0xFFFFFFFFu;
+
+// The calling thread's error message (mr_last_error), shared by all host
+// translation units.
+void clear_error();
+int set_error(int code, const char *msg);
 
 // Host-side launchers (defined in mr_kernels.hip).
 hipError_t launch_clear_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
@@ -87,6 +94,12 @@ hipError_t launch_clear_ctrl(Ctrl *c, int64_t n_tiles, hipStream_t s);
 hipError_t launch_tile_round(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
                              uint32_t *flags, uint32_t *lists, Ctrl *ctrl, uint32_t round,
                              int max_iters, int grid, hipStream_t s);
+// The same round with explicit list-length counters (NBANDS each) for this
+// round and the next; all_tiles visits every tile instead of a list.
+hipError_t launch_tile_round_ex(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
+                                uint32_t *flags, uint32_t *lists, const uint32_t *counts_in,
+                                uint32_t *counts_out, int all_tiles, Ctrl *ctrl,
+                                uint32_t round, int max_iters, int grid, hipStream_t s);
 hipError_t launch_seed(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
                        const uint32_t *lists, uint32_t round, Ctrl *ctrl, uint64_t *bitmap,
                        uint32_t *qflag, uint32_t *ring, uint64_t cap, int grid, hipStream_t s);
@@ -94,7 +107,8 @@ hipError_t launch_clear_u64(uint64_t *p, int64_t n, hipStream_t s);
 hipError_t launch_queue(int tbytes, int conn, const Imgs &imgs, Ctrl *ctrl, uint64_t *bitmap,
                         uint32_t *qflag, uint32_t *ring, uint64_t cap, int blocks,
                         unsigned long long spin_cap, hipStream_t s);
-hipError_t launch_fill_output(int tbytes, const Imgs &imgs, int64_t n_tiles, hipStream_t s);
+hipError_t launch_fill_output(int tbytes, const Imgs &imgs, int64_t n_tiles, hipStream_t s,
+                              int64_t t0 = 0);
 hipError_t launch_store_u64(unsigned long long *p, unsigned long long v, hipStream_t s);
 hipError_t launch_put_desc(ImgDesc *dst, const ImgDesc &v, hipStream_t s);
 // Writes n descriptors (n <= DESC_CHUNK per launch) through kernel arguments,
@@ -102,5 +116,16 @@ hipError_t launch_put_desc(ImgDesc *dst, const ImgDesc &v, hipStream_t s);
 constexpr int DESC_CHUNK = 16;
 hipError_t launch_put_descs(ImgDesc *dst, const ImgDesc *v, int n, hipStream_t s);
 int queue_max_blocks(int tbytes, int conn);
+int persistent_grid();
+
+// Server support: admit one image (descriptor, owner ids, every tile on the
+// dirty list of round `round`), and mark the images that still have tiles on
+// a round's lists (busy[owner] = stamp).
+hipError_t launch_server_admit(ImgDesc *descs, int32_t slot, const ImgDesc &d, uint32_t *owner,
+                               uint32_t *flags, uint32_t *lists_round, uint32_t *counts_round,
+                               int64_t n_tiles, uint32_t round, hipStream_t s);
+hipError_t launch_server_status(const uint32_t *lists_round, const uint32_t *counts_round,
+                                const uint32_t *owner, uint32_t *busy, int64_t n_tiles,
+                                uint32_t stamp, hipStream_t s);
 
 } // namespace mr

@@ -51,8 +51,10 @@ __device__ __forceinline__ uint32_t from_upper_lane(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130 /* wave_shl:1 */, 0xF, 0xF, true);
 }
 
-// Descriptor of the image that owns `tile` (binary search on tile_base).
+// Descriptor of the image that owns `tile` (owner table, else binary search
+// on tile_base).
 __device__ __forceinline__ ImgDesc load_desc(Imgs imgs, int64_t tile) {
+    if (imgs.owner) return imgs.d[imgs.owner[tile]];
     int lo = 0, hi = imgs.n - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -450,30 +452,32 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
 }
 
 // One tile round on a persistent grid (two waves per SIMD). Block b serves
-// band b % NBANDS; round 1 visits every tile of the band, round r > 1 the
+// band b % NBANDS and visits either every tile of the band (all_tiles) or the
 // band's dirty list. Tiles are dealt to the band's blocks by static
-// interleave, so no block gets more than one tile above another.
+// interleave, so no block gets more than one tile above another. A tile
+// builds its image's initial working values in the image's first round.
 template <typename T, int CONN>
 __global__ __launch_bounds__(64, 2) void k_tile_round(Imgs imgs, int64_t n_tiles,
                                                       uint32_t *__restrict__ flags,
                                                       uint32_t *__restrict__ lists,
-                                                      Ctrl *__restrict__ ctrl, uint32_t round,
-                                                      int max_iters) {
+                                                      const uint32_t *__restrict__ counts_in,
+                                                      uint32_t *__restrict__ counts_out,
+                                                      int all_tiles, Ctrl *__restrict__ ctrl,
+                                                      uint32_t round, int max_iters) {
     __shared__ uint32_t tb[TS][TS + 1]; // transpose buffer (and load stage)
     __shared__ uint32_t abuf[APP_CAP];
     const int lane = threadIdx.x;
     const int band = blockIdx.x % NBANDS;
     const int64_t local = blockIdx.x / NBANDS, per = gridDim.x / NBANDS;
     const int64_t lo = band_lo(n_tiles, band);
-    Appender app{abuf, 0, lists + ((round + 1) & 1) * n_tiles, ctrl->round_tiles[round + 1],
-                 n_tiles};
+    Appender app{abuf, 0, lists + ((round + 1) & 1) * n_tiles, counts_out, n_tiles};
     const uint32_t *list_in = lists + (round & 1) * n_tiles + lo;
-    const int64_t n = ctrl->round_tiles[round][band];
+    const int64_t n = all_tiles ? band_lo(n_tiles, band + 1) - lo : (int64_t)counts_in[band];
     for (int64_t i = local; i < n; i += per) {
-        const int64_t t = round == 1 ? lo + i : (int64_t)list_in[i];
+        const int64_t t = all_tiles ? lo + i : (int64_t)list_in[i];
         const ImgDesc d = load_desc(imgs, t);
         if (!d.done) {
-            if (round == 1) {
+            if (d.first_round == (int64_t)round) {
                 if (d.op == MR_OP_FILL)
                     visit_tile<T, CONN, true, true>(d, t, lane, flags, app, ctrl, round, max_iters, tb);
                 else
@@ -793,9 +797,9 @@ __global__ void k_clear_ctrl(Ctrl *c, int64_t n_tiles) {
 // Fill-holes epilogue: out = NOT J over the interior of every tile of the
 // launch whose image is a fill-holes image.
 template <typename T>
-__global__ __launch_bounds__(64) void k_fill_output(Imgs imgs) {
+__global__ __launch_bounds__(64) void k_fill_output(Imgs imgs, int64_t t0) {
     using P = Pix<T>;
-    const int64_t t = blockIdx.x;
+    const int64_t t = t0 + blockIdx.x;
     const int lane = threadIdx.x;
     const ImgDesc d = load_desc(imgs, t);
     if (d.op != MR_OP_FILL || d.done) return;
@@ -825,7 +829,70 @@ __global__ void k_put_descs(ImgDesc *dst, DescChunk c) {
     if ((int)threadIdx.x < c.n) dst[threadIdx.x] = c.d[threadIdx.x];
 }
 
+// ------------------------------------------------------------------ server
+
+// Admit one image: its descriptor, owner[t] for its tiles, and every one of
+// its tiles on the dirty list of `round` (where it builds its initial
+// values). One thread per tile.
+__global__ void k_server_admit(ImgDesc *descs, int32_t slot, ImgDesc d, uint32_t *owner,
+                               uint32_t *flags, uint32_t *lists_round, uint32_t *counts_round,
+                               int64_t n_tiles, uint32_t round) {
+    const int64_t nt = (int64_t)d.ntx * d.nty;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i == 0) descs[slot] = d;
+    if (i >= nt) return;
+    const int64_t t = d.tile_base + i;
+    owner[t] = (uint32_t)slot;
+    flags[t] = round;
+    const int b = band_of(n_tiles, t);
+    const uint32_t pos = atomicAdd(counts_round + b, 1u);
+    lists_round[band_lo(n_tiles, b) + pos] = (uint32_t)t;
+}
+
+// busy[image] = stamp for every image with a tile on the round's lists.
+__global__ void k_server_status(const uint32_t *lists_round, const uint32_t *counts_round,
+                                const uint32_t *owner, uint32_t *busy, int64_t n_tiles,
+                                uint32_t stamp) {
+    const int b = blockIdx.x % NBANDS;
+    const int64_t per = (gridDim.x / NBANDS) * (int64_t)blockDim.x;
+    const int64_t n = counts_round[b];
+    const uint32_t *l = lists_round + band_lo(n_tiles, b);
+    for (int64_t i = (blockIdx.x / NBANDS) * (int64_t)blockDim.x + threadIdx.x; i < n; i += per)
+        busy[owner[l[i]]] = stamp;
+}
+
 // ---------------------------------------------------------------- launchers
+
+int persistent_grid() {
+    static int g = 0;
+    if (!g) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            cus > 0)
+            g = cus * 8;
+        else
+            g = 2048;
+    }
+    return g;
+}
+
+hipError_t launch_server_admit(ImgDesc *descs, int32_t slot, const ImgDesc &d, uint32_t *owner,
+                               uint32_t *flags, uint32_t *lists_round, uint32_t *counts_round,
+                               int64_t n_tiles, uint32_t round, hipStream_t s) {
+    const int64_t nt = std::max<int64_t>(1, (int64_t)d.ntx * d.nty);
+    hipLaunchKernelGGL(k_server_admit, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, descs,
+                       slot, d, owner, flags, lists_round, counts_round, n_tiles, round);
+    return hipGetLastError();
+}
+
+hipError_t launch_server_status(const uint32_t *lists_round, const uint32_t *counts_round,
+                                const uint32_t *owner, uint32_t *busy, int64_t n_tiles,
+                                uint32_t stamp, hipStream_t s) {
+    hipLaunchKernelGGL(k_server_status, dim3(NBANDS * 32), dim3(256), 0, s, lists_round,
+                       counts_round, owner, busy, n_tiles, stamp);
+    return hipGetLastError();
+}
 
 hipError_t launch_clear_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
     if (n <= 0) return hipSuccess;
@@ -841,23 +908,34 @@ hipError_t launch_clear_ctrl(Ctrl *c, int64_t n_tiles, hipStream_t s) {
 
 template <typename T, int CONN>
 static hipError_t tile_round_t(const Imgs &imgs, int64_t n_tiles, uint32_t *flags,
-                               uint32_t *lists, Ctrl *ctrl, uint32_t round, int max_iters,
-                               int grid, hipStream_t s) {
+                               uint32_t *lists, const uint32_t *cin, uint32_t *cout, int all,
+                               Ctrl *ctrl, uint32_t round, int max_iters, int grid,
+                               hipStream_t s) {
     const int64_t want = std::max<int64_t>(NBANDS, (n_tiles + NBANDS - 1) / NBANDS * NBANDS);
     const unsigned g = (unsigned)(std::min<int64_t>(grid, want) / NBANDS * NBANDS);
     hipLaunchKernelGGL((k_tile_round<T, CONN>), dim3(g), dim3(64), 0, s, imgs, n_tiles, flags,
-                       lists, ctrl, round, max_iters);
+                       lists, cin, cout, all, ctrl, round, max_iters);
     return hipGetLastError();
+}
+
+hipError_t launch_tile_round_ex(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
+                                uint32_t *flags, uint32_t *lists, const uint32_t *cin,
+                                uint32_t *cout, int all, Ctrl *ctrl, uint32_t round,
+                                int max_iters, int grid, hipStream_t s) {
+    if (!ctrl) return hipErrorInvalidValue;
+    if (tbytes == 1)
+        return conn == 8 ? tile_round_t<uint8_t, 8>(imgs, n_tiles, flags, lists, cin, cout, all, ctrl, round, max_iters, grid, s)
+                         : tile_round_t<uint8_t, 4>(imgs, n_tiles, flags, lists, cin, cout, all, ctrl, round, max_iters, grid, s);
+    return conn == 8 ? tile_round_t<int32_t, 8>(imgs, n_tiles, flags, lists, cin, cout, all, ctrl, round, max_iters, grid, s)
+                     : tile_round_t<int32_t, 4>(imgs, n_tiles, flags, lists, cin, cout, all, ctrl, round, max_iters, grid, s);
 }
 
 hipError_t launch_tile_round(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
                              uint32_t *flags, uint32_t *lists, Ctrl *ctrl, uint32_t round,
                              int max_iters, int grid, hipStream_t s) {
-    if (tbytes == 1)
-        return conn == 8 ? tile_round_t<uint8_t, 8>(imgs, n_tiles, flags, lists, ctrl, round, max_iters, grid, s)
-                         : tile_round_t<uint8_t, 4>(imgs, n_tiles, flags, lists, ctrl, round, max_iters, grid, s);
-    return conn == 8 ? tile_round_t<int32_t, 8>(imgs, n_tiles, flags, lists, ctrl, round, max_iters, grid, s)
-                     : tile_round_t<int32_t, 4>(imgs, n_tiles, flags, lists, ctrl, round, max_iters, grid, s);
+    return launch_tile_round_ex(tbytes, conn, imgs, n_tiles, flags, lists,
+                                ctrl->round_tiles[round], ctrl->round_tiles[round + 1],
+                                round == 1, ctrl, round, max_iters, grid, s);
 }
 
 template <typename T, int CONN>
@@ -934,11 +1012,13 @@ hipError_t launch_queue(int tbytes, int conn, const Imgs &imgs, Ctrl *ctrl, uint
                      : queue_t<int32_t, 4>(imgs, ctrl, bitmap, qflag, ring, cap, blocks, spin_cap, s);
 }
 
-hipError_t launch_fill_output(int tbytes, const Imgs &imgs, int64_t n_tiles, hipStream_t s) {
+hipError_t launch_fill_output(int tbytes, const Imgs &imgs, int64_t n_tiles, hipStream_t s,
+                              int64_t t0) {
+    if (n_tiles <= 0) return hipSuccess;
     if (tbytes == 1)
-        hipLaunchKernelGGL(k_fill_output<uint8_t>, dim3((unsigned)n_tiles), dim3(64), 0, s, imgs);
+        hipLaunchKernelGGL(k_fill_output<uint8_t>, dim3((unsigned)n_tiles), dim3(64), 0, s, imgs, t0);
     else
-        hipLaunchKernelGGL(k_fill_output<int32_t>, dim3((unsigned)n_tiles), dim3(64), 0, s, imgs);
+        hipLaunchKernelGGL(k_fill_output<int32_t>, dim3((unsigned)n_tiles), dim3(64), 0, s, imgs, t0);
     return hipGetLastError();
 }
 

@@ -41,6 +41,12 @@ class Tile(ctypes.Structure):
                 ("op", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class Job(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("mask", ctypes.c_void_p), ("result", ctypes.c_void_p),
+                ("H", ctypes.c_int64), ("W", ctypes.c_int64), ("ld", ctypes.c_int64),
+                ("op", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class LaunchTime(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("round", ctypes.c_int32), ("ms", ctypes.c_float)]
 
@@ -101,6 +107,21 @@ def lib():
         L.mr_autotune_workspace_bytes.restype = sz
         L.mr_autotune.argtypes = [TP, i32, c_int, c_int, vp, sz, vp, ctypes.POINTER(Tune)]
         L.mr_autotune.restype = c_int
+        L.mr_server_create.argtypes = [vp, sz, i32, c_int, c_int, vp, ctypes.POINTER(vp)]
+        L.mr_server_create.restype = c_int
+        L.mr_server_submit.argtypes = [vp, ctypes.POINTER(Job), ctypes.POINTER(ctypes.c_uint64)]
+        L.mr_server_submit.restype = c_int
+        L.mr_server_step.argtypes = [vp]
+        L.mr_server_step.restype = c_int
+        L.mr_server_poll.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), i32, ctypes.POINTER(i32)]
+        L.mr_server_poll.restype = c_int
+        L.mr_server_drain.argtypes = [vp]
+        L.mr_server_drain.restype = c_int
+        L.mr_server_stats.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_uint64),
+                                      ctypes.POINTER(sz)]
+        L.mr_server_stats.restype = c_int
+        L.mr_server_destroy.argtypes = [vp]
+        L.mr_server_destroy.restype = None
         L.mr_timing_enable.argtypes = [c_int]
         L.mr_timing_enable.restype = c_int
         L.mr_timing_collect.argtypes = [ctypes.POINTER(LaunchTime), i32, ctypes.POINTER(i32)]
@@ -286,6 +307,103 @@ def autotune(items, conn: int = 8, stream=None) -> Tune:
     _check(lib().mr_autotune(arr, n, t, conn, ws.data_ptr(), ws.numel(), _stream_ptr(stream),
                              ctypes.byref(out)))
     return out
+
+
+def _host_rows(a, dtype):
+    """A 2-D host tensor whose rows are unit-stride (a window of a larger
+    image is fine), pinned if it is not already."""
+    t = torch.as_tensor(a)
+    if t.device.type != "cpu" or t.dim() != 2 or t.dtype != dtype:
+        raise TypeError(f"job images must be 2-D host arrays of {dtype}")
+    if t.stride(1) != 1 or t.stride(0) < t.shape[1]:
+        t = t.contiguous()
+    if not t.is_pinned():
+        t = t.contiguous().pin_memory()
+    return t
+
+
+class Server:
+    """Continuous-batching server over a device arena of ``arena_bytes``.
+
+    ``submit`` admits a job from host memory or returns None when it cannot
+    be admitted yet; ``step`` launches one tile round over every resident job
+    and retires what the round before finished; ``poll`` returns the jobs
+    whose results have arrived in host memory."""
+
+    def __init__(self, arena_bytes: int, max_jobs: int = 64, dtype=torch.uint8, conn: int = 8,
+                 device="cuda:0", stream=None):
+        self.dtype = dtype
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        _check(lib().mr_server_create(self.arena.data_ptr(), self.arena.numel(), int(max_jobs),
+                                      _DTYPES[dtype], int(conn), _stream_ptr(stream),
+                                      ctypes.byref(h)))
+        self._h = h
+        self.jobs = {}  # id -> (buffers kept alive until done, result)
+
+    def submit(self, data, mask=None, op=None, out=None):
+        """Admit ``data`` (the marker, or for fill-holes the image when
+        ``mask`` is None). ``out`` (same shape, pinned host memory, rows
+        unit-stride and with the same row pitch as ``data``) receives the
+        result; by default a pinned buffer is allocated. Returns the job id,
+        or None if there is no room right now."""
+        if op is None:
+            op = MR_OP_RECON if mask is not None else MR_OP_FILL
+        d = _host_rows(data, self.dtype)
+        m = _host_rows(mask, self.dtype) if mask is not None else None
+        if m is not None and m.shape != d.shape:
+            raise ValueError("marker and mask shapes differ")
+        if m is not None and m.stride(0) != d.stride(0):  # one row pitch for both
+            d, m = (_host_rows(x.contiguous(), self.dtype) for x in (d, m))
+        H, W = d.shape
+        if out is None:
+            out = torch.empty((H, d.stride(0)), dtype=self.dtype, pin_memory=True)[:, :W]
+        elif (tuple(out.shape) != (H, W) or out.stride(0) != d.stride(0) or out.stride(1) != 1
+              or not out.is_pinned()):
+            raise ValueError("out must be pinned, of the job's shape and row pitch")
+        job = Job(d.data_ptr(), m.data_ptr() if m is not None else None, out.data_ptr(),
+                  H, W, d.stride(0), int(op), 0)
+        jid = ctypes.c_uint64()
+        rc = lib().mr_server_submit(self._h, ctypes.byref(job), ctypes.byref(jid))
+        if rc == MR_EAGAIN:
+            return None
+        _check(rc)
+        self.jobs[jid.value] = (d, m, out)
+        return jid.value
+
+    def step(self):
+        _check(lib().mr_server_step(self._h))
+
+    def poll(self):
+        """[(job id, result tensor)] for the jobs whose results have arrived
+        since the last poll."""
+        cap = 4096
+        buf = (ctypes.c_uint64 * cap)()
+        n = ctypes.c_int32()
+        _check(lib().mr_server_poll(self._h, buf, cap, ctypes.byref(n)))
+        return [(int(buf[i]), self.jobs.pop(int(buf[i]))[2]) for i in range(n.value)]
+
+    def drain(self):
+        _check(lib().mr_server_drain(self._h))
+
+    def stats(self):
+        r = ctypes.c_int32()
+        rounds = ctypes.c_uint64()
+        fb = ctypes.c_size_t()
+        _check(lib().mr_server_stats(self._h, ctypes.byref(r), ctypes.byref(rounds),
+                                     ctypes.byref(fb)))
+        return {"resident": r.value, "rounds": rounds.value, "largest_free": fb.value}
+
+    def close(self):
+        if self._h:
+            lib().mr_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def read_round_tiles(workspace: torch.Tensor, stream=None) -> list:

@@ -141,3 +141,15 @@ def test_graph_needs_fixed_rounds(L):
     rc = L.mr_batch_graph_create(one, 1, 1, 8, ctypes.c_void_p(FAKE), 1 << 30, ctypes.byref(t),
                                  ctypes.byref(h))
     assert rc == mrecon.MR_EINVAL and not h.value
+
+
+@pytest.mark.parametrize("kw", [dict(arena=0), dict(arena=FAKE + 4), dict(max_jobs=0),
+                                dict(t=3), dict(conn=5)])
+def test_server_create_rejects(L, kw):
+    args = dict(arena=FAKE, size=1 << 30, max_jobs=8, t=1, conn=8)
+    args.update(kw)
+    h = ctypes.c_void_p()
+    rc = L.mr_server_create(ctypes.c_void_p(args["arena"]), args["size"], args["max_jobs"],
+                            args["t"], args["conn"], None, ctypes.byref(h))
+    assert rc == mrecon.MR_EINVAL and not h.value
+    assert L.mr_last_error()
