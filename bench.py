@@ -15,16 +15,37 @@ round: algorithmic bytes per launch = tiles visited x (interior pixels per
 tile) x 3 bytes per pixel (read J, read the mask, write J), over the launch's
 duration measured with HIP events on the call's stream during the timed
 steps. ``--gpus`` above 1 is refused: this build runs on one GPU.
+
+Two more legs are added to the same line (``--legs``):
+
+* ``batched``: 512 uneven u8 tiles (sides log-uniform 256-4096, per-tile
+  seeds, ~1.0 Gpixel in all), reconstruction 8-conn: one ``mr_recon_dilate``
+  per tile on one stream versus one batched launch sequence with the
+  autotuner's settings (replayed as a HIP graph when the settings allow it).
+  Every batched result is checked against the oracle.
+* ``served``: 2000 jobs (sides log-uniform 512-8192, 70 % reconstruction /
+  30 % fill-holes, ~15 Gpixel) answered from and to pinned host memory.
+  Each job is a window of one of two seeded 8192 x 8192 images, its first
+  column on a 64-byte boundary. Compared: sequential per-job launches (copy
+  in, one call, copy out, wait) versus the continuous-batching server with an
+  8 GiB arena, first back to back, then on one Poisson arrival trace at
+  0.8 x the sequential capacity (p50/p99 of completion - arrival). Untimed
+  passes afterwards hash every result of the sequential path and of the
+  server (back to back and on the trace), which must agree job by job; a
+  sample of jobs is checked against the oracle.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
 import platform
+import queue
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -113,6 +134,289 @@ def summarize_traffic(fetch_csv: str, write_csv: str, args) -> None:
     json.dump(rec, open(path, "w"), indent=1)
     print(json.dumps(rec))
 
+def pct(xs, q) -> float:
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q))
+
+
+def leg_batched(args, dev) -> dict:
+    """512 uneven tiles: per-tile calls versus one batched launch sequence."""
+    import torch
+    import oracle
+    from paper_1311_0378_amd import mrecon, synth
+
+    n = args.batch_n
+    shapes = synth.batch_shapes(n)
+    t0 = time.time()
+    with ThreadPoolExecutor(4) as ex:
+        tiles = list(ex.map(lambda i: synth.batch_tile(i, *shapes[i], n=n), range(n)))
+    npx = sum(H * W for H, W in shapes)
+    log(f"batched: generated {n} tiles, {npx / 1e9:.3f} Gpx, in {time.time() - t0:.1f}s")
+    src = [torch.from_numpy(m).to(dev) for m, _ in tiles]
+    msk = [torch.from_numpy(k).to(dev) for _, k in tiles]
+    work = [x.clone() for x in src]
+    items = [(w, k, mrecon.MR_OP_RECON) for w, k in zip(work, msk)]
+    stream = torch.cuda.current_stream()
+    reps, warm = args.batch_reps, 1
+
+    def restore():
+        for w, x in zip(work, src):
+            w.copy_(x)
+        torch.cuda.synchronize()
+
+    # one call per tile, library defaults, one workspace reused in stream order
+    ws = mrecon.alloc_workspace(max(mrecon.workspace_bytes(mrecon.MR_OP_RECON, H, W, torch.uint8, 8)
+                                    for H, W in shapes), dev)
+    per_tile_s, lat_ms = [], []
+    for rep in range(warm + reps):
+        restore()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+        t1 = time.perf_counter()
+        evs[0].record(stream)
+        for i in range(n):
+            mrecon.recon_dilate(work[i], msk[i], 8, workspace=ws, stream=stream)
+            evs[i + 1].record(stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        if rep >= warm:
+            per_tile_s.append(dt)
+            lat_ms += [evs[i].elapsed_time(evs[i + 1]) for i in range(n)]
+    per_tile_out = [w.clone() for w in work]
+    log(f"batched: per-tile calls {np.median(per_tile_s) * 1e3:.1f} ms")
+
+    restore()
+    t1 = time.time()
+    tune = mrecon.autotune(items, 8, stream=stream)
+    tuned = {"sweep_rounds": tune.sweep_rounds, "max_sweeps": tune.max_sweeps}
+    log(f"batched: autotune {tuned} in {time.time() - t1:.1f}s")
+    wsb = mrecon.alloc_workspace(mrecon.batch_workspace_bytes(items, 8, tune), dev)
+    graph = mrecon.BatchGraph(items, 8, tune, wsb) if tune.sweep_rounds > 0 else None
+    batched_s = []
+    for rep in range(warm + reps):
+        restore()
+        t1 = time.perf_counter()
+        if graph is not None:
+            graph.launch(stream)
+        else:
+            mrecon.batch(items, 8, tune, wsb, stream)
+        torch.cuda.synchronize()
+        if rep >= warm:
+            batched_s.append(time.perf_counter() - t1)
+    log(f"batched: one launch sequence {np.median(batched_s) * 1e3:.1f} ms")
+
+    same = all(bool(torch.equal(a, b)) for a, b in zip(work, per_tile_out))
+    exact = True
+    if not args.no_verify:
+        outs = [w.cpu().numpy() for w in work]
+        with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+            exact = all(ex.map(lambda i: bool(np.array_equal(
+                outs[i], oracle.recon_dilate(tiles[i][0], tiles[i][1], 8)[0])), range(n)))
+        log("batched: bit-exact vs oracle:", exact)
+    if graph is not None:
+        graph.close()
+    med_pt, med_b = float(np.median(per_tile_s)), float(np.median(batched_s))
+    return {
+        "workload": f"{n} u8 tiles, sides log-uniform 256-4096, recon conn8, "
+                    f"{npx / 1e9:.3f} Gpx",
+        "per_tile": {"mpx_s": round(npx / med_pt / 1e6, 1), "ms_p50": round(med_pt * 1e3, 2),
+                     "ms_p99": round(pct(per_tile_s, 99) * 1e3, 2),
+                     "tile_latency_ms_p50": round(pct(lat_ms, 50), 4),
+                     "tile_latency_ms_p99": round(pct(lat_ms, 99), 4)},
+        "batched": {"mpx_s": round(npx / med_b / 1e6, 1), "ms_p50": round(med_b * 1e3, 2),
+                    "ms_p99": round(pct(batched_s, 99) * 1e3, 2),
+                    "mode": "hip graph" if graph is not None else "direct launches",
+                    "tune": tuned},
+        "speedup": round(med_pt / med_b, 3),
+        "reps": reps,
+        "bit_exact": bool(exact and same) if not args.no_verify else None,
+        "batched_equals_per_tile": same,
+    }
+
+
+def leg_served(args, dev) -> dict:
+    """Serving trace: sequential per-job launches versus the server."""
+    import torch
+    import xxhash
+    import oracle
+    from paper_1311_0378_amd import mrecon, synth
+
+    n = args.serve_n
+    jobs = synth.serving_jobs(n)
+    wins = synth.serving_windows(jobs)
+    t0 = time.time()
+    bm, bk, bf = synth.serving_banks()
+    side = bm.shape[1]
+    pm, pk, pf = (torch.from_numpy(x).pin_memory() for x in (bm, bk, bf))
+    npx = sum(H * W for _, H, W in jobs)
+    log(f"served: {n} jobs, {npx / 1e9:.2f} Gpx, banks ready in {time.time() - t0:.1f}s")
+    u8 = torch.uint8
+    stream = torch.cuda.current_stream()
+    hip = ctypes.CDLL(os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so"))
+    hip.hipMemcpy2DAsync.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                     ctypes.c_size_t, ctypes.c_size_t, ctypes.c_size_t,
+                                     ctypes.c_int, ctypes.c_void_p]
+    H2D, D2H = 1, 2
+
+    def copy2d(dst, dpitch, src, spitch, H, W, kind):
+        rc = hip.hipMemcpy2DAsync(dst, dpitch, src, spitch, W, H, kind, stream.cuda_stream)
+        if rc != 0:
+            raise RuntimeError(f"hipMemcpy2DAsync failed ({rc})")
+
+    def views(i):
+        kind, H, W = jobs[i]
+        y, x = wins[i]
+        if kind == "recon":
+            return pm[y:y + H, x:x + W], pk[y:y + H, x:x + W]
+        return pf[y:y + H, x:x + W], None
+
+    max_jobs = 32
+    # result buffers: H rows of W, 64-byte aligned row pitch, in pinned blocks
+    pool = queue.SimpleQueue()
+    for _ in range(max_jobs + 16):
+        pool.put(torch.empty(side * side, dtype=u8, pin_memory=True))
+
+    def res_view(buf, i):
+        _, H, W = jobs[i]
+        ld = (W + 63) // 64 * 64
+        return buf[:H * ld].view(H, ld)[:, :W]
+
+    def digest(i, buf, hashes):
+        hashes[i] = xxhash.xxh3_64_intdigest(np.ascontiguousarray(res_view(buf, i).numpy()))
+        pool.put(buf)
+
+    def recycle(i, buf, hashes):
+        pool.put(buf)
+
+    d0 = torch.empty((side, side), dtype=u8, device=dev)
+    d1 = torch.empty((side, side), dtype=u8, device=dev)
+    ws = mrecon.alloc_workspace(max(mrecon.workspace_bytes(op, side, side, u8, 8)
+                                    for op in (mrecon.MR_OP_RECON, mrecon.MR_OP_FILL)), dev)
+
+    def wait_until(t):
+        while True:
+            d = t - time.perf_counter()
+            if d <= 0:
+                return
+            time.sleep(min(d, 2e-4))
+
+    def run_sequential(arr, hashing=False):
+        hasher = ThreadPoolExecutor(4)
+        consume = digest if hashing else recycle
+        hashes, lat, futs = [None] * n, [0.0] * n, []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(n):
+            if arr is not None:
+                wait_until(t0 + arr[i])
+            kind, H, W = jobs[i]
+            a, m = views(i)
+            buf = pool.get()
+            copy2d(d0.data_ptr(), side, a.data_ptr(), side, H, W, H2D)
+            if m is not None:
+                copy2d(d1.data_ptr(), side, m.data_ptr(), side, H, W, H2D)
+                mrecon.recon_dilate(d0[:H, :W], d1[:H, :W], 8, workspace=ws, stream=stream)
+            else:
+                mrecon.fill_holes(d0[:H, :W], 8, workspace=ws, stream=stream)
+            copy2d(buf.data_ptr(), (W + 63) // 64 * 64, d0.data_ptr(), side, H, W, D2H)
+            stream.synchronize()
+            lat[i] = time.perf_counter() - t0 - (arr[i] if arr is not None else 0.0)
+            futs.append(hasher.submit(consume, i, buf, hashes))
+        span = time.perf_counter() - t0 - (arr[0] if arr is not None else 0.0)
+        hasher.shutdown()
+        for f in futs:
+            f.result()
+        return hashes, lat, span
+
+    arena = 8 << 30
+
+    def run_served(arr, hashing=False):
+        hasher = ThreadPoolExecutor(4)
+        consume = digest if hashing else recycle
+        srv = mrecon.Server(arena, max_jobs=max_jobs, dtype=u8, conn=8, device=dev,
+                            stream=stream)
+        hashes, lat, futs = [None] * n, [0.0] * n, []
+        owned = {}
+        i = done = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while done < n:
+            now = time.perf_counter() - t0
+            while i < n and (arr is None or arr[i] <= now):
+                try:
+                    buf = pool.get_nowait()
+                except queue.Empty:
+                    break
+                a, m = views(i)
+                jid = srv.submit(a, m, out=res_view(buf, i))
+                if jid is None:
+                    pool.put(buf)
+                    break
+                owned[jid] = (i, buf)
+                i += 1
+            if srv.stats()["resident"]:
+                srv.step()
+            elif i < n and arr is not None:
+                wait_until(t0 + arr[i])
+            for jid, _ in srv.poll():
+                k, buf = owned.pop(jid)
+                lat[k] = time.perf_counter() - t0 - (arr[k] if arr is not None else 0.0)
+                futs.append(hasher.submit(consume, k, buf, hashes))
+                done += 1
+        span = time.perf_counter() - t0 - (arr[0] if arr is not None else 0.0)
+        rounds = srv.stats()["rounds"]
+        srv.close()
+        hasher.shutdown()
+        for f in futs:
+            f.result()
+        return hashes, lat, span, rounds
+
+    def summary(lat, span):
+        return {"mpx_s": round(npx / span / 1e6, 1), "latency_ms_p50": round(pct(lat, 50) * 1e3, 2),
+                "latency_ms_p99": round(pct(lat, 99) * 1e3, 2), "span_s": round(span, 3)}
+
+    # timed passes: results land in host memory and their buffers are reused
+    _, lat_sb, span_sb = run_sequential(None)
+    log(f"served: sequential back to back {span_sb:.2f}s")
+    _, lat_vb, span_vb, rounds_vb = run_served(None)
+    log(f"served: server back to back {span_vb:.2f}s, {rounds_vb} rounds")
+    rate = args.serve_load * n / span_sb
+    arr = synth.poisson_arrivals(n, rate)
+    _, lat_st, span_st = run_sequential(arr)
+    log(f"served: sequential on the trace {span_st:.2f}s")
+    _, lat_vt, span_vt, rounds_vt = run_served(arr)
+    log(f"served: server on the trace {span_vt:.2f}s")
+    # untimed verification passes: every result hashed, job by job
+    ref, _, _ = run_sequential(None, hashing=True)
+    h_vb, _, _, _ = run_served(None, hashing=True)
+    h_vt, _, _, _ = run_served(arr, hashing=True)
+    agree = ref == h_vb == h_vt and None not in ref
+
+    # oracle check on a sample: the first jobs of each kind up to 4 Mpx
+    sample = ([i for i, j in enumerate(jobs) if j[0] == "recon" and j[1] * j[2] <= 4 << 20][:8] +
+              [i for i, j in enumerate(jobs) if j[0] == "fill" and j[1] * j[2] <= 4 << 20][:8])
+
+    def check(i):
+        a, m = views(i)
+        a = np.ascontiguousarray(a.numpy())
+        want = (oracle.recon_dilate(a, np.ascontiguousarray(m.numpy()), 8) if m is not None
+                else oracle.fill_holes(a, 8))[0]
+        return xxhash.xxh3_64_intdigest(want) == ref[i]
+
+    with ThreadPoolExecutor(8) as ex:
+        oracle_ok = all(ex.map(check, sample))
+    log("served: all runs agree:", agree, "oracle sample ok:", oracle_ok)
+    return {
+        "workload": f"{n} jobs, sides log-uniform 512-8192, 70% recon / 30% fill-holes, u8 "
+                    f"conn8, {npx / 1e9:.2f} Gpx, host memory in and out",
+        "arena_gib": arena >> 30, "max_jobs": max_jobs,
+        "back_to_back": {"sequential": summary(lat_sb, span_sb),
+                         "served": summary(lat_vb, span_vb), "served_rounds": rounds_vb},
+        "trace": {"rate_jobs_s": round(rate, 2), "load_vs_sequential_capacity": args.serve_load,
+                  "sequential": summary(lat_st, span_st), "served": summary(lat_vt, span_vt),
+                  "served_rounds": rounds_vt},
+        "results_agree": bool(agree),
+        "oracle_sample": {"jobs": len(sample), "bit_exact": bool(oracle_ok)},
+    }
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -123,6 +427,12 @@ def main():
     ap.add_argument("--dtype", default="u8", choices=["u8", "i32"])
     ap.add_argument("--conn", type=int, default=8, choices=[4, 8])
     ap.add_argument("--tune", default="", help="k=v,... overrides of mr_tune")
+    ap.add_argument("--legs", default="batched,served",
+                    help="extra legs after the headline: comma list of batched, served, or none")
+    ap.add_argument("--batch-n", type=int, default=512)
+    ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--serve-n", type=int, default=2000)
+    ap.add_argument("--serve-load", type=float, default=0.8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -284,6 +594,17 @@ def main():
                 "kind": "oracle",
                 "sample": f"the whole {S}x{S} {dt} image, one sequential oracle run "
                           f"({t_or:.1f} s) on {cpu_model()}, {os.cpu_count()} threads visible"}
+    legs = [x for x in args.legs.split(",") if x and x != "none"]
+    unknown = set(legs) - {"batched", "served"}
+    if unknown:
+        raise SystemExit(f"unknown legs: {sorted(unknown)}")
+    del copies, wss, d_mask, d_src
+    torch.cuda.empty_cache()
+    if "batched" in legs:
+        result["batched"] = leg_batched(args, dev)
+        torch.cuda.empty_cache()
+    if "served" in legs:
+        result["served"] = leg_served(args, dev)
     print(json.dumps(result), flush=True)
 
 

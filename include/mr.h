@@ -170,19 +170,21 @@ int mr_autotune(const mr_tile *tiles, int32_t n, mr_dtype t, int conn, void *ws,
 
 /* --------------------------------------------------------------- serving */
 
-/* A request: one image in host memory, answered in host memory. Rows are
- * `ld` elements apart in all three host buffers (0 means W), so a job can be a
- * window of a larger image. The buffers must stay valid until the job is
- * reported done; pinned (page-locked) memory lets the copies run
- * asynchronously, pageable memory works but copies synchronously. */
+/* A request: one image in host memory, answered in host memory. Rows of
+ * the inputs are `ld` elements apart and rows of the result `ld_result` apart
+ * (0 means W), so a job can be a window of a larger image. The buffers must
+ * stay valid until the job is reported done; pinned (page-locked) memory
+ * lets the copies run asynchronously, pageable memory works but copies
+ * synchronously. */
 typedef struct {
     const void *data; /* H x W: the marker (MR_OP_RECON) or the image (MR_OP_FILL) */
     const void *mask; /* H x W mask (MR_OP_RECON); NULL otherwise */
     void *result;     /* H x W: receives the result; may alias data */
     int64_t H, W;
-    int64_t ld;       /* host row pitch in elements, >= W, or 0 */
-    int32_t op;       /* MR_OP_RECON or MR_OP_FILL */
-    int32_t reserved; /* must be 0 */
+    int64_t ld;        /* input row pitch in elements, >= W, or 0 */
+    int64_t ld_result; /* result row pitch in elements, >= W, or 0 */
+    int32_t op;        /* MR_OP_RECON or MR_OP_FILL */
+    int32_t reserved;  /* must be 0 */
 } mr_job;
 
 /* Continuous-batching server over a caller-provided device arena, the HBM
@@ -195,10 +197,12 @@ typedef struct {
  * frontiers) stay in the arena between steps. A job is finished when a round
  * leaves none of its tiles dirty; its result is then copied back.
  *
- * Pipelining: input and result copies run on a second stream that the server
- * creates, so they overlap the rounds; a step launches round r and then
- * retires what round r-1 finished, so the device always has the next round
- * queued. All calls for one server must come from one thread.
+ * Pipelining: input copies and result copies run on two streams that the
+ * server creates, so they overlap the rounds and each other (PCIe is full
+ * duplex); a step launches round r and then retires what round r-1 finished,
+ * so the device always has the next round queued. A finished job's arena
+ * space, tile ids and slot are reused only after its result copy has
+ * completed. All calls for one server must come from one thread.
  *
  * Errors: MR_EINVAL (bad argument), MR_ENOMEM (arena too small), MR_EHIP. */
 typedef struct mr_server mr_server;

@@ -11,19 +11,18 @@
 // instead of waiting for it to drain. A job is finished when a round leaves
 // none of its tiles dirty.
 //
-// Two streams: rounds (and admissions, which must land between rounds) run
-// on the caller's stream; input copies, the fill-holes epilogue and result
-// copies run on a copy stream of the server's own, so PCIe traffic overlaps
-// the rounds. Ordering between them is by events only:
+// Three streams: rounds (and admissions, which must land between rounds)
+// run on the caller's stream; input copies run on an upload stream, and the
+// fill-holes epilogue and result copies on a download stream, both the
+// server's own, so PCIe traffic overlaps the rounds and runs in both
+// directions at once. Ordering between them is by events:
 //  - an admission waits for its input copy;
 //  - a finished job's epilogue and result copy wait for the round that
 //    finished it;
-//  - the copy stream is in order, so a new job's input copy into arena space
-//    or tile ids that a finished job gave back runs after that job's result
-//    copy, and its admission (which rewrites the tile owners) after that job's
-//    epilogue has read them.
-// A finished job's slot (its descriptor and events) is kept until its result
-// copy has completed.
+//  - a finished job's arena space, tile ids and slot are handed out again
+//    only once the host has seen its result copy complete, so no later
+//    upload, admission (which rewrites tile owners and the descriptor) or
+//    round can touch them while the download stream still reads them.
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
@@ -110,6 +109,8 @@ struct Job {
 struct Returning {
     uint64_t id;
     int32_t slot;
+    size_t mem_off, mem_len;
+    int64_t tile_base, n_tiles;
 };
 
 } // namespace
@@ -120,7 +121,8 @@ struct mr_server {
     int32_t max_jobs = 0;
     int t = 1, conn = 8, max_sweeps = 16;
     hipStream_t stream = nullptr; // rounds and admissions
-    hipStream_t copy = nullptr;   // input copies, fill-holes epilogue, result copies
+    hipStream_t up = nullptr;     // input copies
+    hipStream_t down = nullptr;   // fill-holes epilogue, result copies
     int64_t n_tiles = 0;          // tile-id space
     // arena head
     Ctrl *ctrl = nullptr;
@@ -159,7 +161,8 @@ int check_job(const mr_server *s, const mr_job *j) {
     if (j->op != MR_OP_RECON && j->op != MR_OP_FILL) return sfail(MR_EINVAL, "unknown op %d", j->op);
     if (j->reserved) return sfail(MR_EINVAL, "reserved must be 0");
     if (j->H < 1 || j->W < 1) return sfail(MR_EINVAL, "empty image");
-    if (j->ld != 0 && j->ld < j->W) return sfail(MR_EINVAL, "host row pitch below the width");
+    if ((j->ld != 0 && j->ld < j->W) || (j->ld_result != 0 && j->ld_result < j->W))
+        return sfail(MR_EINVAL, "host row pitch below the width");
     if (!j->data || !j->result || (j->op == MR_OP_RECON && !j->mask))
         return sfail(MR_EINVAL, "null host buffer");
     int64_t pitch;
@@ -178,13 +181,9 @@ int hip_err(hipError_t e, const char *what) {
     return sfail(MR_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-void release_space(mr_server *s, const Job &j) {
-    s->mem.release(j.mem_off, j.mem_len);
-    s->tiles.release((size_t)j.tile_base, (size_t)j.n_tiles);
-}
-
 // Moves returning jobs whose result copies have completed to `done`, in
-// order (the copy stream completes them in order); with `wait`, all of them.
+// order (the download stream completes them in order), and gives their
+// arena space, tile ids and slots back; with `wait`, all of them.
 int collect(mr_server *s, bool wait) {
     while (!s->returning.empty()) {
         const Returning r = s->returning.front();
@@ -192,6 +191,8 @@ int collect(mr_server *s, bool wait) {
         if (e == hipErrorNotReady) return MR_OK;
         if (e != hipSuccess) return hip_err(e, "result copy");
         s->done.push_back(r.id);
+        s->mem.release(r.mem_off, r.mem_len);
+        s->tiles.release((size_t)r.tile_base, (size_t)r.n_tiles);
         s->free_slots.push_back(r.slot);
         s->returning.pop_front();
     }
@@ -205,7 +206,8 @@ void destroy_handles(mr_server *s) {
         if (e) hipEventDestroy(e);
     for (hipEvent_t e : s->ev_round)
         if (e) hipEventDestroy(e);
-    if (s->copy) hipStreamDestroy(s->copy);
+    if (s->up) hipStreamDestroy(s->up);
+    if (s->down) hipStreamDestroy(s->down);
     if (s->h_busy) hipHostFree(s->h_busy);
 }
 
@@ -266,7 +268,8 @@ int mr_server_create(void *arena, size_t arena_bytes, int32_t max_jobs, mr_dtype
     s->ev_out.assign(max_jobs, nullptr);
     hipError_t e = hipHostMalloc((void **)&s->h_busy, sizeof(uint32_t) * 2 * max_jobs,
                                  hipHostMallocDefault);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->up, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->down, hipStreamNonBlocking);
     for (int i = 0; i < 2 && e == hipSuccess; ++i)
         e = hipEventCreateWithFlags(&s->ev_round[i], hipEventDisableTiming);
     for (int32_t i = 0; i < max_jobs && e == hipSuccess; ++i) {
@@ -292,7 +295,7 @@ int mr_server_submit(mr_server *s, const mr_job *job, uint64_t *id) {
     if (!s || !id) return sfail(MR_EINVAL, "null pointer");
     int rc;
     if ((rc = check_job(s, job)) != MR_OK) return rc;
-    if (s->free_slots.empty() && (rc = collect(s, false)) != MR_OK) return rc;
+    if ((rc = collect(s, false)) != MR_OK) return rc;
     if (s->free_slots.empty()) return sfail(MR_EAGAIN, "all job slots are busy");
     Job j{};
     j.spec = *job;
@@ -315,11 +318,11 @@ int mr_server_submit(mr_server *s, const mr_job *job, uint64_t *id) {
     const size_t row = (size_t)job->W * s->t, dp = (size_t)j.pitch * s->t;
     const size_t hp = (size_t)(job->ld ? job->ld : job->W) * s->t;
     hipError_t e = hipMemcpy2DAsync(p0, dp, job->data, hp, row, (size_t)job->H,
-                                    hipMemcpyHostToDevice, s->copy);
+                                    hipMemcpyHostToDevice, s->up);
     if (e == hipSuccess && job->op == MR_OP_RECON)
         e = hipMemcpy2DAsync(p1, dp, job->mask, hp, row, (size_t)job->H, hipMemcpyHostToDevice,
-                             s->copy);
-    if (e == hipSuccess) e = hipEventRecord(s->ev_in[j.slot], s->copy);
+                             s->up);
+    if (e == hipSuccess) e = hipEventRecord(s->ev_in[j.slot], s->up);
     if (e == hipSuccess) e = hipStreamWaitEvent(s->stream, s->ev_in[j.slot], 0);
     ImgDesc &d = j.d;
     d = ImgDesc{};
@@ -349,7 +352,8 @@ int mr_server_submit(mr_server *s, const mr_job *job, uint64_t *id) {
     if (e != hipSuccess) {
         // the slot is not handed out: a failed enqueue leaves the streams in
         // an unknown state, and the error is reported
-        release_space(s, j);
+        s->mem.release(mo, need);
+        s->tiles.release(to, (size_t)j.n_tiles);
         return hip_err(e, "admit");
     }
     s->free_slots.pop_back();
@@ -405,23 +409,23 @@ int mr_server_step(mr_server *s) {
             if (j.first_round <= p && hb[j.slot] != p + 1) finished.push_back(kv.first);
         }
         if (!finished.empty() &&
-            (e = hipStreamWaitEvent(s->copy, s->ev_round[p & 1], 0)) != hipSuccess)
+            (e = hipStreamWaitEvent(s->down, s->ev_round[p & 1], 0)) != hipSuccess)
             return hip_err(e, "event wait");
         for (int32_t slot : finished) {
             Job &j = s->resident[slot];
             if (j.spec.op == MR_OP_FILL &&
-                (e = launch_fill_output(s->t, imgs, j.n_tiles, s->copy, j.tile_base)) !=
+                (e = launch_fill_output(s->t, imgs, j.n_tiles, s->down, j.tile_base)) !=
                     hipSuccess)
                 return hip_err(e, "fill output");
             const char *src = (const char *)(j.spec.op == MR_OP_RECON ? j.d.J : j.d.out);
             const size_t row = (size_t)j.spec.W * s->t, dp = (size_t)j.pitch * s->t;
-            const size_t hp = (size_t)(j.spec.ld ? j.spec.ld : j.spec.W) * s->t;
+            const size_t hp = (size_t)(j.spec.ld_result ? j.spec.ld_result : j.spec.W) * s->t;
             if ((e = hipMemcpy2DAsync(j.spec.result, hp, src, dp, row, (size_t)j.spec.H,
-                                      hipMemcpyDeviceToHost, s->copy)) != hipSuccess ||
-                (e = hipEventRecord(s->ev_out[slot], s->copy)) != hipSuccess)
+                                      hipMemcpyDeviceToHost, s->down)) != hipSuccess ||
+                (e = hipEventRecord(s->ev_out[slot], s->down)) != hipSuccess)
                 return hip_err(e, "result copy");
-            s->returning.push_back(Returning{j.id, slot});
-            release_space(s, j);
+            s->returning.push_back(
+                Returning{j.id, slot, j.mem_off, j.mem_len, j.tile_base, j.n_tiles});
             s->resident.erase(slot);
         }
     }
@@ -467,7 +471,8 @@ int mr_server_stats(const mr_server *s, int32_t *resident, uint64_t *rounds, siz
 void mr_server_destroy(mr_server *s) {
     if (!s) return;
     hipStreamSynchronize(s->stream);
-    if (s->copy) hipStreamSynchronize(s->copy);
+    if (s->up) hipStreamSynchronize(s->up);
+    if (s->down) hipStreamSynchronize(s->down);
     destroy_handles(s);
     delete s;
 }

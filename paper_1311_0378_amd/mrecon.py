@@ -44,7 +44,8 @@ class Tile(ctypes.Structure):
 class Job(ctypes.Structure):
     _fields_ = [("data", ctypes.c_void_p), ("mask", ctypes.c_void_p), ("result", ctypes.c_void_p),
                 ("H", ctypes.c_int64), ("W", ctypes.c_int64), ("ld", ctypes.c_int64),
-                ("op", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("ld_result", ctypes.c_int64), ("op", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class LaunchTime(ctypes.Structure):
@@ -343,10 +344,9 @@ class Server:
 
     def submit(self, data, mask=None, op=None, out=None):
         """Admit ``data`` (the marker, or for fill-holes the image when
-        ``mask`` is None). ``out`` (same shape, pinned host memory, rows
-        unit-stride and with the same row pitch as ``data``) receives the
-        result; by default a pinned buffer is allocated. Returns the job id,
-        or None if there is no room right now."""
+        ``mask`` is None). ``out`` (pinned host memory of the job's shape,
+        unit-stride rows) receives the result; by default a pinned buffer is
+        allocated. Returns the job id, or None if there is no room right now."""
         if op is None:
             op = MR_OP_RECON if mask is not None else MR_OP_FILL
         d = _host_rows(data, self.dtype)
@@ -357,12 +357,12 @@ class Server:
             d, m = (_host_rows(x.contiguous(), self.dtype) for x in (d, m))
         H, W = d.shape
         if out is None:
-            out = torch.empty((H, d.stride(0)), dtype=self.dtype, pin_memory=True)[:, :W]
-        elif (tuple(out.shape) != (H, W) or out.stride(0) != d.stride(0) or out.stride(1) != 1
-              or not out.is_pinned()):
-            raise ValueError("out must be pinned, of the job's shape and row pitch")
+            out = torch.empty((H, W), dtype=self.dtype, pin_memory=True)
+        elif (tuple(out.shape) != (H, W) or out.dtype != self.dtype or out.stride(1) != 1
+              or out.stride(0) < W or not out.is_pinned()):
+            raise ValueError("out must be pinned, of the job's shape and type, rows unit-stride")
         job = Job(d.data_ptr(), m.data_ptr() if m is not None else None, out.data_ptr(),
-                  H, W, d.stride(0), int(op), 0)
+                  H, W, d.stride(0), out.stride(0), int(op), 0)
         jid = ctypes.c_uint64()
         rc = lib().mr_server_submit(self._h, ctypes.byref(job), ctypes.byref(jid))
         if rc == MR_EAGAIN:

@@ -189,13 +189,24 @@ def serving_jobs(n: int = 2000, lo: int = 512, hi: int = 8192, seed: int = 1,
             for k, (a, b) in zip(kinds, u)]
 
 
-def serving_job_input(i: int, kind: str, H: int, W: int, n: int = 2000, root_seed: int = 1):
-    """Inputs for serving job ``i``: ``(marker, mask)`` or ``(binary, None)``."""
-    ss = np.random.SeedSequence(root_seed).spawn(n)[i]
-    if kind == "recon":
-        return make_tile(H, W, density_disks(H, W), ss, "u8", 0.0)
-    mask = quantize(make_field(H, W, density_disks(H, W), ss, 0.05), "u8")
-    return binary_from_mask(mask), None
+def serving_banks(side: int = 8192, root_seed: int = 1):
+    """The two images serving jobs are windows of, at the batch density:
+    ``(marker, mask)`` of a solid-disk field for reconstruction, and the
+    binary image of a field with 5 % hollow disks for fill-holes."""
+    ss = np.random.SeedSequence(root_seed).spawn(2)
+    marker, mask = make_tile(side, side, density_disks(side, side), ss[0], "u8", 0.0)
+    fmask = quantize(make_field(side, side, density_disks(side, side), ss[1], 0.05), "u8")
+    return marker, mask, binary_from_mask(fmask)
+
+
+def serving_windows(jobs, side: int = 8192, seed: int = 3, align: int = 64):
+    """Top-left corner of each job's window in its bank: the row uniform over
+    the rows where the H x W window fits, the column likewise but rounded
+    down to a multiple of ``align`` (tile buffers handed over at aligned
+    addresses, as an image reader would)."""
+    rng = np.random.default_rng(seed)
+    return [(int(rng.integers(0, side - H + 1)),
+             int(rng.integers(0, side - W + 1)) // align * align) for _, H, W in jobs]
 
 
 def poisson_arrivals(n: int, rate_per_s: float, seed: int = 2) -> np.ndarray:
