@@ -520,12 +520,13 @@ def main():
             if kind == "tile_round":
                 if rnd == 1 and step_tiles:
                     break  # next step's first round
+                # every launch counts, also the few that find an empty list
+                # after convergence, as in a profiler's per-kernel average
                 visits = rt[rnd - 1] if rnd - 1 < len(rt) else 0
                 step_tiles += visits
-                if visits:
-                    tile_ms += ms
-                    tile_bytes += visits * bytes_per_visit
-                    tile_launches += 1
+                tile_ms += ms
+                tile_bytes += visits * bytes_per_visit
+                tile_launches += 1
             elif kind == "seed":
                 seed_ms += ms
             elif kind == "queue":

@@ -153,3 +153,12 @@ def test_server_create_rejects(L, kw):
                             args["t"], args["conn"], None, ctypes.byref(h))
     assert rc == mrecon.MR_EINVAL and not h.value
     assert L.mr_last_error()
+
+
+def test_plane_limit(L):
+    # H * pitch must stay below 2^32 elements: 65535 x 65535 is accepted,
+    # 65536 x 65536 is refused
+    n = L.mr_workspace_bytes(mrecon.MR_OP_RECON, 65535, 65535, mrecon.MR_U8, 8, None)
+    assert n > 0
+    assert L.mr_workspace_bytes(mrecon.MR_OP_RECON, 65536, 65536, mrecon.MR_U8, 8, None) == 0
+    assert b"2^32" in L.mr_last_error()

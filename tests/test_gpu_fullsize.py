@@ -1,0 +1,101 @@
+"""Parity at full workload sizes, in the launch configuration the benchmark
+times (library defaults), and at the largest plane the interface accepts.
+
+* 16384 x 16384 reconstruction, u8 and i32 (values scaled to 0..65535),
+  8-connectivity: every pixel against the oracle.
+* 65535 x 65535 u8 (H * pitch just below 2^32): the mask carries walls of
+  zeros every 4096 rows and columns. Under 4- or 8-connectivity nothing can
+  propagate through a zero-mask wall one pixel thick (the wall pixels stay at
+  0, and pixels on either side are not neighbours), so every walled block is
+  an independent reconstruction: sampled blocks, corners and the ragged last
+  row and column of blocks included, are checked exactly against the oracle
+  run on the block alone. The whole image is checked for marker <= R <= mask
+  and for being a fixed point of one geodesic dilation step.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1311_0378_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from gpu_util import DEV, first_mismatch, gpu_recon  # noqa: E402
+from paper_1311_0378_amd import mrecon  # noqa: E402
+
+
+@pytest.mark.parametrize("dt", ["u8", "i32"])
+def test_16384_full_image(dt):
+    marker, mask = synth.single_16384(dt)
+    print(f"[gpu] 16384x16384 {dt} conn8", flush=True)
+    got = gpu_recon(marker, mask, 8)
+    want, _ = oracle.recon_dilate(marker, mask, 8)
+    assert np.array_equal(got, want), first_mismatch(got, want)
+
+
+def _walled_inputs(H, W, step, seed):
+    g = torch.Generator(device=DEV)
+    g.manual_seed(seed)
+    noise = torch.randint(0, 256, (H, W), generator=g, device=DEV, dtype=torch.uint8)
+    mask = torch.empty_like(noise)
+    # spatially correlated values: 5 x 5 box mean in row bands (fp16 holds
+    # every sum of 25 u8 values / 25 closely enough for test data)
+    band = 4096
+    for y0 in range(0, H, band):
+        y1 = min(H, y0 + band)
+        a, b = max(0, y0 - 2), min(H, y1 + 2)
+        blk = noise[a:b].to(torch.float16)[None, None]
+        m = torch.nn.functional.avg_pool2d(blk, 5, stride=1, padding=2, count_include_pad=False)
+        mask[y0:y1] = m[0, 0, y0 - a:y0 - a + (y1 - y0)].round().clamp(0, 255).to(torch.uint8)
+        del blk, m
+    del noise
+    mask[::step, :] = 0
+    mask[:, ::step] = 0
+    marker = (mask.to(torch.int16) - 30).clamp(min=0).to(torch.uint8)
+    return marker, mask
+
+
+@pytest.mark.parametrize("conn", [8])
+def test_max_plane_walled_blocks(conn):
+    H = W = 65535
+    step = 4096
+    print(f"[gpu] {H}x{W} u8 walled every {step}, conn{conn}", flush=True)
+    marker, mask = _walled_inputs(H, W, step, seed=7)
+    R = marker.clone()
+    ws = mrecon.alloc_workspace(mrecon.workspace_bytes(mrecon.MR_OP_RECON, H, W, torch.uint8,
+                                                       conn), R.device)
+    mrecon.recon_dilate(R, mask, conn, workspace=ws)
+    torch.cuda.synchronize()
+    del ws
+    # exact check of sampled blocks (row / column block indices; 15 is the
+    # ragged last one, 4095 pixels wide)
+    last = (H - 1) // step
+    for by, bx in [(0, 0), (0, last), (last, 0), (last, last), (7, 8), (3, 12)]:
+        y0, x0 = by * step, bx * step
+        y1, x1 = min(H, y0 + step + 1), min(W, x0 + step + 1)
+        mk = marker[y0:y1, x0:x1].cpu().numpy()
+        ms = mask[y0:y1, x0:x1].cpu().numpy()
+        want, _ = oracle.recon_dilate(mk, ms, conn)
+        got = R[y0:y1, x0:x1].cpu().numpy()
+        assert np.array_equal(got, want), f"block ({by},{bx}): " + first_mismatch(got, want)
+    # whole image: bounds, and a fixed point of one geodesic dilation step
+    band = 2048
+    for y0 in range(0, H, band):
+        y1 = min(H, y0 + band)
+        a, b = max(0, y0 - 1), min(H, y1 + 1)
+        r = R[y0:y1]
+        assert bool((r <= mask[y0:y1]).all()) and bool((r >= marker[y0:y1]).all()), y0
+        blk = R[a:b].to(torch.float16)[None, None]
+        if conn == 8:
+            d = torch.nn.functional.max_pool2d(blk, 3, stride=1, padding=1)[0, 0]
+        else:
+            p = torch.nn.functional.pad(blk, (1, 1, 1, 1))[0, 0]
+            d = torch.stack([p[1:-1, 1:-1], p[:-2, 1:-1], p[2:, 1:-1], p[1:-1, :-2],
+                             p[1:-1, 2:]]).amax(0)
+        d = d[y0 - a:y0 - a + (y1 - y0)]
+        step_once = torch.minimum(d, mask[y0:y1].to(torch.float16))
+        assert bool((step_once == r.to(torch.float16)).all()), f"not a fixed point near row {y0}"
