@@ -193,7 +193,7 @@ uint64_t round_total(const Ctrl &h, size_t r) {
 
 // The whole propagation over the images of one launch.
 int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *ws,
-                 const mr_tune &tn, hipStream_t s, bool any_fill) {
+                 const mr_tune &tn, hipStream_t s, bool any_fill, int op_all) {
     char *base = (char *)ws;
     Ctrl *ctrl = (Ctrl *)base;
     uint32_t *flags = (uint32_t *)(base + L.off_flags);
@@ -212,7 +212,7 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
     {
         LaunchTimer lt(s, MR_K_TILE_ROUND, (int32_t)round);
         e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl, round,
-                              tn.max_sweeps, grid, s);
+                              tn.max_sweeps, grid, s, op_all);
     }
     if (e != hipSuccess) return hip_fail(e, "tile round");
     if (tn.sweep_rounds > 0) {
@@ -220,7 +220,7 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
             {
                 LaunchTimer lt(s, MR_K_TILE_ROUND, (int32_t)round);
                 e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl, round,
-                                      tn.max_sweeps, grid, s);
+                                      tn.max_sweeps, grid, s, op_all);
             }
             if (e != hipSuccess) return hip_fail(e, "tile round");
         }
@@ -259,7 +259,7 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
                 {
                     LaunchTimer lt(s, MR_K_TILE_ROUND, (int32_t)round);
                     e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl,
-                                          round, tn.max_sweeps, grid, s);
+                                          round, tn.max_sweeps, grid, s, op_all);
                 }
                 if (e != hipSuccess) return hip_fail(e, "tile round");
             }
@@ -325,7 +325,7 @@ int run_single(int op, void *J_io, const void *I, int64_t H, int64_t W, int64_t 
     imgs.d = (const ImgDesc *)((char *)ws + L.off_desc);
     hipError_t e = launch_put_desc((ImgDesc *)imgs.d, d, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "descriptor");
-    return run_sequence(t, conn, imgs, L, ws, tn, (hipStream_t)stream, op == MR_OP_FILL);
+    return run_sequence(t, conn, imgs, L, ws, tn, (hipStream_t)stream, op == MR_OP_FILL, op);
 }
 
 // ---------------------------------------------------------------- batches
@@ -337,7 +337,7 @@ size_t plane_bytes(int64_t H, int64_t W, int t) {
 struct BatchPlan {
     Layout L;
     std::vector<ImgDesc> descs;
-    bool any_fill = false;
+    bool any_fill = false, any_recon = false;
     size_t data_bytes = 0; // sum of H * W * t (autotune backup)
 };
 
@@ -370,6 +370,7 @@ int plan_batch(const mr_tile *tiles, int32_t n, int t, int conn, void *ws, Batch
             d.J = tl.data_inout;
             d.I = tl.mask;
             d.pJ = d.pI = pitch;
+            bp.any_recon = true;
         } else {
             d.J = (void *)(uintptr_t)fill_bytes; // offset for now, based below
             d.I = tl.data_inout;
@@ -406,7 +407,8 @@ int run_batch(const mr_tile *tiles, int32_t n, int t, int conn, void *ws, size_t
     hipError_t e = launch_put_descs(dd, bp.descs.data(), n, s);
     if (e != hipSuccess) return hip_fail(e, "descriptors");
     Imgs imgs{dd, n, nullptr};
-    return run_sequence(t, conn, imgs, bp.L, ws, effective_tune(tune), s, bp.any_fill);
+    const int op_all = bp.any_fill ? (bp.any_recon ? -1 : MR_OP_FILL) : MR_OP_RECON;
+    return run_sequence(t, conn, imgs, bp.L, ws, effective_tune(tune), s, bp.any_fill, op_all);
 }
 
 } // namespace

@@ -90,10 +90,12 @@ hipError_t launch_clear_ctrl(Ctrl *c, int64_t n_tiles, hipStream_t s);
 // Round r visits every tile (r == 1) or the dirty lists of round r -- band
 // b's at lists[(r & 1) * n_tiles + band start], ctrl->round_tiles[r][b] long
 // -- and lists each tile it dirties for round r + 1 in the other half
-// (flags[t] = the latest round t is listed for).
+// (flags[t] = the latest round t is listed for). Every image's first round
+// is 1; op_all is the op of all images (MR_OP_RECON / MR_OP_FILL), or -1 if
+// they differ.
 hipError_t launch_tile_round(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
                              uint32_t *flags, uint32_t *lists, Ctrl *ctrl, uint32_t round,
-                             int max_iters, int grid, hipStream_t s);
+                             int max_iters, int grid, hipStream_t s, int op_all);
 // The same round with explicit list-length counters (NBANDS each) for this
 // round and the next; all_tiles visits every tile instead of a list.
 hipError_t launch_tile_round_ex(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,

@@ -118,7 +118,7 @@ template <> struct Atom<uint8_t> {
 // the end, or at the huge offsets used for rows outside the image, return 0.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *p, uint64_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0,
-                                             (int)(uint32_t)min<uint64_t>(bytes, 0xFFFFFFF0ull),
+                                             (int)(bytes < 0xFFFFFFF0ull ? (uint32_t)bytes : 0xFFFFFFF0u),
                                              0x00020000);
 }
 
@@ -138,16 +138,27 @@ static_assert(2 * STAGE_BYTES <= TS * (TS + 1) * 4, "the stage must fit in the t
 __device__ __forceinline__ void stage_u8(__amdgpu_buffer_rsrc_t rs, int64_t gy0, int64_t H,
                                          uint32_t pitch, int64_t a, int lane, uint8_t *st) {
     typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+    // Staged planes have a pitch of at least 16 and H * pitch < 2^32, so rows
+    // and offsets fit 32 bits. The lane id goes through an empty asm so that
+    // nothing derived from it is hoisted out of the caller's tile loop: held
+    // across the sweeps, such values would be spilled, and every reload would
+    // wait for all memory operations in flight.
+    uint32_t ln = (uint32_t)lane;
+    asm volatile("" : "+v"(ln));
+    const int32_t gy0s = (int32_t)gy0, Hs = (int32_t)H, as = (int32_t)a;
     v4u v[5];
     int base[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-        const int q = k * 64 + lane;
+        const int q = k * 64 + (int)ln;
         const int row = q / 5, ch = q - row * 5;
-        const int64_t gy = gy0 + row;
-        const int64_t off = gy * (int64_t)pitch + a + ch * 16;
-        const bool in = gy >= 0 && gy < H && off >= 0;
-        v[k] = __builtin_amdgcn_raw_buffer_load_b128(rs, in ? (uint32_t)off : 0xFFFFFFF0u, 0, 0);
+        const int32_t gy = gy0s + row, col = as + ch * 16;
+        // col < 0 only in the first chunk of a tile at the left image edge;
+        // below row 0 it reads the end of the previous row (outside pixels,
+        // masked out later), in row 0 it is out of range
+        const bool in = gy >= 0 && gy < Hs && (gy > 0 || col >= 0);
+        const uint32_t off = (uint32_t)gy * pitch + (uint32_t)col;
+        v[k] = __builtin_amdgcn_raw_buffer_load_b128(rs, in ? off : 0xFFFFFFF0u, 0, 0);
         base[k] = row * SROW + ch * 16;
     }
 #pragma unroll
@@ -170,15 +181,20 @@ __device__ __forceinline__ void stage_u8(__amdgpu_buffer_rsrc_t rs, int64_t gy0,
 // are already 256-byte coalesced loads) go straight to registers from
 // clamped, in-bounds addresses.
 template <typename T, bool FILL, bool INITIAL>
-__device__ __forceinline__ void load_tile(const ImgDesc &d, int64_t gy0, int64_t gx, int lane,
+__device__ __forceinline__ void load_tile(const ImgDesc &d, int64_t gy0, int64_t gx0, int lane,
                                           uint32_t (&J)[TS], uint32_t (&I)[TS], uint8_t *stage) {
     using P = Pix<T>;
     const int64_t H = d.H, W = d.W;
+    const int64_t gx = gx0 + lane;
     const bool xin = gx >= 0 && gx < W;
     const bool halo_lane = lane == 0 || lane == TS - 1;
     const bool xedge = gx == 0 || gx == W - 1;
+    // The whole tile, halo included, lies inside the image (wave-uniform):
+    // no pixel needs the outside rule. A fill-holes image's first visit also
+    // needs to know the image border, so it always takes the general path.
+    const bool inside =
+        !(FILL && INITIAL) && gy0 >= 0 && gy0 + TS <= H && gx0 >= 0 && gx0 + TS <= W;
     if (sizeof(T) == 1 && stage_ok(d.I, d.pI) && stage_ok(d.J, d.pJ)) {
-        const int64_t gx0 = gx - lane;
         const int64_t a = gx0 & ~(int64_t)15;
         const int sh = (int)(gx0 - a) + lane;
         uint8_t *stI = stage, *stJ = stage + STAGE_BYTES;
@@ -187,35 +203,63 @@ __device__ __forceinline__ void load_tile(const ImgDesc &d, int64_t gy0, int64_t
         if (needJ)
             stage_u8(plane_rsrc(d.J, (uint64_t)(H * d.pJ)), gy0, H, (uint32_t)d.pJ, a, lane, stJ);
         __syncthreads();
+        if (inside) {
 #pragma unroll
-        for (int r = 0; r < TS; ++r) {
-            const int64_t gy = gy0 + r;
-            const bool ok = xin && gy >= 0 && gy < H;
-            uint32_t iv = stI[r * SROW + sh];
-            if (FILL) iv = P::KMAX - iv;
-            uint32_t jv;
-            if (FILL && INITIAL)
-                jv = (xedge || gy == 0 || gy == H - 1) ? iv : 0u;
-            else if (INITIAL)
-                jv = min((uint32_t)stJ[r * SROW + sh], iv);
-            else
-                jv = stJ[r * SROW + sh];
-            jv = ok ? jv : 0u;
-            iv = ok ? iv : 0u;
-            J[r] = jv;
-            I[r] = (halo_lane || r == 0 || r == TS - 1) ? jv : iv;
+            for (int r = 0; r < TS; ++r) {
+                uint32_t iv = stI[r * SROW + sh];
+                if (FILL) iv = P::KMAX - iv;
+                uint32_t jv = stJ[r * SROW + sh];
+                if (INITIAL) jv = min(jv, iv);
+                J[r] = jv;
+                I[r] = (halo_lane || r == 0 || r == TS - 1) ? jv : iv;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < TS; ++r) {
+                const int64_t gy = gy0 + r;
+                const bool ok = xin && gy >= 0 && gy < H;
+                uint32_t iv = stI[r * SROW + sh];
+                if (FILL) iv = P::KMAX - iv;
+                uint32_t jv;
+                if (FILL && INITIAL)
+                    jv = (xedge || gy == 0 || gy == H - 1) ? iv : 0u;
+                else if (INITIAL)
+                    jv = min((uint32_t)stJ[r * SROW + sh], iv);
+                else
+                    jv = stJ[r * SROW + sh];
+                jv = ok ? jv : 0u;
+                iv = ok ? iv : 0u;
+                J[r] = jv;
+                I[r] = (halo_lane || r == 0 || r == TS - 1) ? jv : iv;
+            }
         }
         __syncthreads();
         return;
     }
     cgptr<T> Jp = (cgptr<T>)d.J;
     cgptr<T> Ip = (cgptr<T>)d.I;
-    const uint32_t xc = (uint32_t)min(max(gx, (int64_t)0), W - 1);
+    if (inside) {
+        uint32_t oI = (uint32_t)gy0 * (uint32_t)d.pI + (uint32_t)gx;
+        uint32_t oJ = (uint32_t)gy0 * (uint32_t)d.pJ + (uint32_t)gx;
+#pragma unroll
+        for (int r = 0; r < TS; ++r) {
+            uint32_t iv = P::key(Ip[oI]);
+            if (FILL) iv = P::KMAX - iv;
+            uint32_t jv = P::key(Jp[oJ]);
+            if (INITIAL) jv = min(jv, iv);
+            J[r] = jv;
+            I[r] = (halo_lane || r == 0 || r == TS - 1) ? jv : iv;
+            oI += (uint32_t)d.pI;
+            oJ += (uint32_t)d.pJ;
+        }
+        return;
+    }
+    const uint32_t xc = (uint32_t)(gx < 0 ? 0 : (gx > W - 1 ? W - 1 : gx));
 #pragma unroll
     for (int r = 0; r < TS; ++r) {
         const int64_t gy = gy0 + r;
         const bool ok = xin && gy >= 0 && gy < H;
-        const uint32_t yc = (uint32_t)min(max(gy, (int64_t)0), H - 1);
+        const uint32_t yc = (uint32_t)(gy < 0 ? 0 : (gy > H - 1 ? H - 1 : gy));
         uint32_t iv = P::key(Ip[yc * (uint32_t)d.pI + xc]);
         if (FILL) iv = P::KMAX - iv;
         uint32_t jv;
@@ -362,7 +406,7 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
     const int64_t gy0 = (int64_t)ty * TI - 1, gx = (int64_t)tx * TI - 1 + lane;
 
     uint32_t J[TS], I[TS], IT[TS];
-    load_tile<T, FILL, INITIAL>(d, gy0, gx, lane, J, I, (uint8_t *)tb);
+    load_tile<T, FILL, INITIAL>(d, gy0, (int64_t)tx * TI - 1, lane, J, I, (uint8_t *)tb);
 #pragma unroll
     for (int r = 0; r < TS; ++r) IT[r] = I[r];
     transpose(IT, tb, lane);
@@ -403,13 +447,23 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
         if (in_lane && gx < d.W) {
             // rows gy0+1 .. gy0+62 are all >= 0; only the last tile row may
             // run past the image
-            const int rows = (int)min<int64_t>(TS - 2, d.H - gy0 - 1);
+            const int64_t left = d.H - gy0 - 1;
+            const int rows = left < TS - 2 ? (int)left : TS - 2;
             uint32_t off = (uint32_t)(gy0 + 1) * (uint32_t)d.pJ + (uint32_t)gx;
+            if (rows == TS - 2) {
 #pragma unroll
-            for (int r = 1; r < TS - 1; ++r) {
-                asm volatile("" : "+v"(off));
-                if (r <= rows) Jw[off] = P::val(J[r]);
-                off += (uint32_t)d.pJ;
+                for (int r = 1; r < TS - 1; ++r) {
+                    asm volatile("" : "+v"(off));
+                    Jw[off] = P::val(J[r]);
+                    off += (uint32_t)d.pJ;
+                }
+            } else {
+#pragma unroll
+                for (int r = 1; r < TS - 1; ++r) {
+                    asm volatile("" : "+v"(off));
+                    if (r <= rows) Jw[off] = P::val(J[r]);
+                    off += (uint32_t)d.pJ;
+                }
             }
         }
     }
@@ -456,7 +510,11 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
 // band's dirty list. Tiles are dealt to the band's blocks by static
 // interleave, so no block gets more than one tile above another. A tile
 // builds its image's initial working values in the image's first round.
-template <typename T, int CONN>
+// V selects the visit: -1 dispatches per tile on the image's op and first
+// round (mixed batches, the server); otherwise (FILL << 1) | INITIAL for
+// launches whose tiles all take the same visit, which keeps the other three
+// variants' code, and their registers, out of the kernel.
+template <typename T, int CONN, int V>
 __global__ __launch_bounds__(64, 2) void k_tile_round(Imgs imgs, int64_t n_tiles,
                                                       uint32_t *__restrict__ flags,
                                                       uint32_t *__restrict__ lists,
@@ -476,7 +534,11 @@ __global__ __launch_bounds__(64, 2) void k_tile_round(Imgs imgs, int64_t n_tiles
     for (int64_t i = local; i < n; i += per) {
         const int64_t t = all_tiles ? lo + i : (int64_t)list_in[i];
         const ImgDesc d = load_desc(imgs, t);
-        if (!d.done) {
+        if (V >= 0) {
+            if (!d.done)
+                visit_tile<T, CONN, (V >> 1) & 1, V & 1>(d, t, lane, flags, app, ctrl, round,
+                                                         max_iters, tb);
+        } else if (!d.done) {
             if (d.first_round == (int64_t)round) {
                 if (d.op == MR_OP_FILL)
                     visit_tile<T, CONN, true, true>(d, t, lane, flags, app, ctrl, round, max_iters, tb);
@@ -560,7 +622,7 @@ __device__ __forceinline__ void seed_tile(const ImgDesc &d, int64_t t, int lane,
     const int ty = (int)(lt / d.ntx), tx = (int)(lt - (int64_t)ty * d.ntx);
     const int64_t gy0 = (int64_t)ty * TI - 1, gx = (int64_t)tx * TI - 1 + lane;
     uint32_t J[TS], I[TS];
-    load_tile<T, FILL, false>(d, gy0, gx, lane, J, I, stage);
+    load_tile<T, FILL, false>(d, gy0, (int64_t)tx * TI - 1, lane, J, I, stage);
     uint64_t myrow = 0; // lane r ends up holding row r's bits
     uint32_t nseed = 0;
     gptr<T> Jw = (gptr<T>)d.J;
@@ -906,36 +968,61 @@ hipError_t launch_clear_ctrl(Ctrl *c, int64_t n_tiles, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <typename T, int CONN>
-static hipError_t tile_round_t(const Imgs &imgs, int64_t n_tiles, uint32_t *flags,
+template <typename T, int CONN, int V>
+static hipError_t tile_round_v(const Imgs &imgs, int64_t n_tiles, uint32_t *flags,
                                uint32_t *lists, const uint32_t *cin, uint32_t *cout, int all,
                                Ctrl *ctrl, uint32_t round, int max_iters, int grid,
                                hipStream_t s) {
     const int64_t want = std::max<int64_t>(NBANDS, (n_tiles + NBANDS - 1) / NBANDS * NBANDS);
     const unsigned g = (unsigned)(std::min<int64_t>(grid, want) / NBANDS * NBANDS);
-    hipLaunchKernelGGL((k_tile_round<T, CONN>), dim3(g), dim3(64), 0, s, imgs, n_tiles, flags,
+    hipLaunchKernelGGL((k_tile_round<T, CONN, V>), dim3(g), dim3(64), 0, s, imgs, n_tiles, flags,
                        lists, cin, cout, all, ctrl, round, max_iters);
     return hipGetLastError();
+}
+
+template <typename T, int CONN>
+static hipError_t tile_round_t(const Imgs &imgs, int64_t n_tiles, uint32_t *flags,
+                               uint32_t *lists, const uint32_t *cin, uint32_t *cout, int all,
+                               Ctrl *ctrl, uint32_t round, int max_iters, int grid,
+                               hipStream_t s, int variant) {
+    switch (variant) {
+    case 0: return tile_round_v<T, CONN, 0>(imgs, n_tiles, flags, lists, cin, cout, all, ctrl, round, max_iters, grid, s);
+    case 1: return tile_round_v<T, CONN, 1>(imgs, n_tiles, flags, lists, cin, cout, all, ctrl, round, max_iters, grid, s);
+    case 2: return tile_round_v<T, CONN, 2>(imgs, n_tiles, flags, lists, cin, cout, all, ctrl, round, max_iters, grid, s);
+    case 3: return tile_round_v<T, CONN, 3>(imgs, n_tiles, flags, lists, cin, cout, all, ctrl, round, max_iters, grid, s);
+    default: return tile_round_v<T, CONN, -1>(imgs, n_tiles, flags, lists, cin, cout, all, ctrl, round, max_iters, grid, s);
+    }
+}
+
+static hipError_t tile_round_any(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
+                                 uint32_t *flags, uint32_t *lists, const uint32_t *cin,
+                                 uint32_t *cout, int all, Ctrl *ctrl, uint32_t round,
+                                 int max_iters, int grid, hipStream_t s, int variant) {
+    if (!ctrl) return hipErrorInvalidValue;
+    if (tbytes == 1)
+        return conn == 8 ? tile_round_t<uint8_t, 8>(imgs, n_tiles, flags, lists, cin, cout, all, ctrl, round, max_iters, grid, s, variant)
+                         : tile_round_t<uint8_t, 4>(imgs, n_tiles, flags, lists, cin, cout, all, ctrl, round, max_iters, grid, s, variant);
+    return conn == 8 ? tile_round_t<int32_t, 8>(imgs, n_tiles, flags, lists, cin, cout, all, ctrl, round, max_iters, grid, s, variant)
+                     : tile_round_t<int32_t, 4>(imgs, n_tiles, flags, lists, cin, cout, all, ctrl, round, max_iters, grid, s, variant);
 }
 
 hipError_t launch_tile_round_ex(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
                                 uint32_t *flags, uint32_t *lists, const uint32_t *cin,
                                 uint32_t *cout, int all, Ctrl *ctrl, uint32_t round,
                                 int max_iters, int grid, hipStream_t s) {
-    if (!ctrl) return hipErrorInvalidValue;
-    if (tbytes == 1)
-        return conn == 8 ? tile_round_t<uint8_t, 8>(imgs, n_tiles, flags, lists, cin, cout, all, ctrl, round, max_iters, grid, s)
-                         : tile_round_t<uint8_t, 4>(imgs, n_tiles, flags, lists, cin, cout, all, ctrl, round, max_iters, grid, s);
-    return conn == 8 ? tile_round_t<int32_t, 8>(imgs, n_tiles, flags, lists, cin, cout, all, ctrl, round, max_iters, grid, s)
-                     : tile_round_t<int32_t, 4>(imgs, n_tiles, flags, lists, cin, cout, all, ctrl, round, max_iters, grid, s);
+    return tile_round_any(tbytes, conn, imgs, n_tiles, flags, lists, cin, cout, all, ctrl, round,
+                          max_iters, grid, s, -1);
 }
 
 hipError_t launch_tile_round(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
                              uint32_t *flags, uint32_t *lists, Ctrl *ctrl, uint32_t round,
-                             int max_iters, int grid, hipStream_t s) {
-    return launch_tile_round_ex(tbytes, conn, imgs, n_tiles, flags, lists,
-                                ctrl->round_tiles[round], ctrl->round_tiles[round + 1],
-                                round == 1, ctrl, round, max_iters, grid, s);
+                             int max_iters, int grid, hipStream_t s, int op_all) {
+    // every image starts in round 1 here, so with one op for all of them the
+    // visit is known for the whole launch
+    const int variant = op_all < 0 ? -1 : ((op_all == MR_OP_FILL ? 2 : 0) | (round == 1 ? 1 : 0));
+    return tile_round_any(tbytes, conn, imgs, n_tiles, flags, lists, ctrl->round_tiles[round],
+                          ctrl->round_tiles[round + 1], round == 1, ctrl, round, max_iters, grid,
+                          s, variant);
 }
 
 template <typename T, int CONN>
