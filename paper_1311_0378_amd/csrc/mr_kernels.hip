@@ -128,9 +128,9 @@ __device__ __forceinline__ bool stage_ok(const void *p, int64_t pitch) {
 
 // uint8 staging: row r of a tile (image row gy0 + r) is fetched as five
 // 16-byte chunks covering image columns a .. a+79, a = gx0 rounded down to 16,
-// and kept in LDS at r * SROW. SROW is an odd number of dwords, so column
-// reads (lane = column) and row reads (lane = row) are both free of bank
-// conflicts.
+// and kept in LDS at r * SROW. SROW is an odd number of dwords, so the row
+// writes (lane = row) and the column reads (lane = column) are both free of
+// bank conflicts.
 constexpr int SROW = 84;
 constexpr int STAGE_BYTES = TS * SROW;
 static_assert(2 * STAGE_BYTES <= TS * (TS + 1) * 4, "the stage must fit in the transpose buffer");
@@ -138,36 +138,34 @@ static_assert(2 * STAGE_BYTES <= TS * (TS + 1) * 4, "the stage must fit in the t
 __device__ __forceinline__ void stage_u8(__amdgpu_buffer_rsrc_t rs, int64_t gy0, int64_t H,
                                          uint32_t pitch, int64_t a, int lane, uint8_t *st) {
     typedef uint32_t v4u __attribute__((ext_vector_type(4)));
-    // Staged planes have a pitch of at least 16 and H * pitch < 2^32, so rows
-    // and offsets fit 32 bits. The lane id goes through an empty asm so that
-    // nothing derived from it is hoisted out of the caller's tile loop: held
-    // across the sweeps, such values would be spilled, and every reload would
-    // wait for all memory operations in flight.
+    // Lane r fetches tile row r, chunk k per load. Staged planes have a pitch
+    // of at least 16 and H * pitch < 2^32, so rows and offsets fit 32 bits.
+    // The lane id goes through an empty asm so that nothing derived from it
+    // is hoisted out of the caller's tile loop: held across the sweeps, such
+    // values would be spilled, and every reload would wait for all memory
+    // operations in flight.
     uint32_t ln = (uint32_t)lane;
     asm volatile("" : "+v"(ln));
-    const int32_t gy0s = (int32_t)gy0, Hs = (int32_t)H, as = (int32_t)a;
+    const int32_t gy = (int32_t)gy0 + (int32_t)ln;
+    const bool rowok = gy >= 0 && gy < (int32_t)H;
+    uint32_t off = (uint32_t)gy * pitch + (uint32_t)(int32_t)a;
     v4u v[5];
-    int base[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-        const int q = k * 64 + (int)ln;
-        const int row = q / 5, ch = q - row * 5;
-        const int32_t gy = gy0s + row, col = as + ch * 16;
-        // col < 0 only in the first chunk of a tile at the left image edge;
+        // a + 16 k < 0 only for chunk 0 of a tile at the left image edge;
         // below row 0 it reads the end of the previous row (outside pixels,
         // masked out later), in row 0 it is out of range
-        const bool in = gy >= 0 && gy < Hs && (gy > 0 || col >= 0);
-        const uint32_t off = (uint32_t)gy * pitch + (uint32_t)col;
+        const bool in = rowok && (gy > 0 || a + 16 * k >= 0);
         v[k] = __builtin_amdgcn_raw_buffer_load_b128(rs, in ? off : 0xFFFFFFF0u, 0, 0);
-        base[k] = row * SROW + ch * 16;
+        off += 16;
     }
+    uint32_t *w = (uint32_t *)(st + ln * SROW);
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-        uint32_t *w = (uint32_t *)(st + base[k]);
-        w[0] = v[k].x;
-        w[1] = v[k].y;
-        w[2] = v[k].z;
-        w[3] = v[k].w;
+        w[4 * k + 0] = v[k].x;
+        w[4 * k + 1] = v[k].y;
+        w[4 * k + 2] = v[k].z;
+        w[4 * k + 3] = v[k].w;
     }
 }
 
