@@ -332,7 +332,7 @@ def leg_served(args, dev) -> dict:
         hasher = ThreadPoolExecutor(4)
         consume = digest if hashing else recycle
         srv = mrecon.Server(arena, max_jobs=max_jobs, dtype=u8, conn=8, device=dev,
-                            stream=stream)
+                            stream=stream, rounds_per_step=args.serve_rounds)
         hashes, lat, futs = [None] * n, [0.0] * n, []
         owned = {}
         i = done = 0
@@ -408,6 +408,7 @@ def leg_served(args, dev) -> dict:
         "workload": f"{n} jobs, sides log-uniform 512-8192, 70% recon / 30% fill-holes, u8 "
                     f"conn8, {npx / 1e9:.2f} Gpx, host memory in and out",
         "arena_gib": arena >> 30, "max_jobs": max_jobs,
+        "rounds_per_step": args.serve_rounds or "library default",
         "back_to_back": {"sequential": summary(lat_sb, span_sb),
                          "served": summary(lat_vb, span_vb), "served_rounds": rounds_vb},
         "trace": {"rate_jobs_s": round(rate, 2), "load_vs_sequential_capacity": args.serve_load,
@@ -433,6 +434,8 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--serve-n", type=int, default=2000)
     ap.add_argument("--serve-load", type=float, default=0.8)
+    ap.add_argument("--serve-rounds", type=int, default=None,
+                    help="tile rounds per server step (library default when omitted)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",

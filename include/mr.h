@@ -212,10 +212,15 @@ int mr_server_create(void *arena, size_t arena_bytes, int32_t max_jobs, mr_dtype
  * MR_EAGAIN: no slot, arena space or tile ids free now -- retry after steps.
  * MR_EINVAL: the job is malformed or could never fit this arena. */
 int mr_server_submit(mr_server *s, const mr_job *job, uint64_t *id);
-/* Launches the next tile round (if any job is still working) and retires
- * the jobs the previous round finished: their result copies are started.
- * Blocks until the previous round has completed. */
+/* Launches the next tile rounds (if any job is still working) and retires
+ * the jobs the previous step finished: their result copies are started.
+ * Blocks until the previous step's rounds have completed. */
 int mr_server_step(mr_server *s);
+/* Tile rounds each step launches before its one status read-back (1..64,
+ * default 2): more rounds per step mean fewer host round trips, at the cost
+ * of noticing a finished job up to that many rounds later. Takes effect at
+ * the next step. Errors: MR_EINVAL. */
+int mr_server_set_rounds_per_step(mr_server *s, int32_t k);
 /* Ids of jobs whose results have fully arrived in their host buffers since
  * the last poll (up to cap), in the order they finished. Does not block. */
 int mr_server_poll(mr_server *s, uint64_t *done_ids, int32_t cap, int32_t *n_done);

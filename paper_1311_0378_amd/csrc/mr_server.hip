@@ -139,9 +139,12 @@ struct mr_server {
     std::deque<uint64_t> done;        // result copy complete, not yet polled
     std::vector<hipEvent_t> ev_in, ev_out; // per slot
     hipEvent_t ev_round[2] = {nullptr, nullptr};
-    uint32_t *h_busy = nullptr; // pinned, [2][max_jobs]: busy after rounds of each parity
-    uint32_t round = 1;         // the round the next step launches
-    uint32_t inflight = 0;      // launched, not yet retired (0: none)
+    uint32_t *h_busy = nullptr; // pinned, [2][max_jobs]: busy after the last step of each parity
+    uint32_t round = 1;         // the round the next step launches first
+    int32_t rounds_per_step = 2;
+    uint64_t steps = 0;         // steps that launched rounds
+    uint32_t inflight = 0;      // last round of the step launched, not yet retired (0: none)
+    int inflight_buf = 0;       // its status buffer and event
     uint64_t next_id = 1;
     uint64_t rounds_run = 0;
 };
@@ -368,48 +371,57 @@ int mr_server_step(mr_server *s) {
     if (!s) return sfail(MR_EINVAL, "null server");
     hipError_t e;
     Imgs imgs{s->descs, s->max_jobs, s->owner};
-    // 1. launch round r over every resident job (including those admitted
-    //    since the last step); the host does not wait for it here
+    // 1. launch the step's rounds over every resident job (including those
+    //    admitted since the last step); the host does not wait for them here
     uint32_t launched = 0;
+    int buf = 0;
     if (!s->resident.empty()) {
-        const uint32_t r = s->round;
-        uint32_t *cin = s->counts + (r % RING) * NBANDS;
-        uint32_t *cout = s->counts + ((r + 1) % RING) * NBANDS;
-        if ((e = launch_clear_u32(cout, NBANDS, 0u, s->stream)) != hipSuccess)
-            return hip_err(e, "clear");
-        if ((e = launch_tile_round_ex(s->t, s->conn, imgs, s->n_tiles, s->flags, s->lists, cin,
-                                      cout, 0, s->ctrl, r, s->max_sweeps, persistent_grid(),
-                                      s->stream)) != hipSuccess)
-            return hip_err(e, "tile round");
-        if ((e = launch_server_status(s->lists + (size_t)((r + 1) & 1) * s->n_tiles, cout,
-                                      s->owner, s->busy, s->n_tiles, r + 1, s->stream)) !=
+        buf = (int)(s->steps++ & 1);
+        uint32_t *cout = nullptr;
+        for (int32_t k = 0; k < s->rounds_per_step; ++k) {
+            const uint32_t r = s->round;
+            uint32_t *cin = s->counts + (r % RING) * NBANDS;
+            cout = s->counts + ((r + 1) % RING) * NBANDS;
+            if ((e = launch_clear_u32(cout, NBANDS, 0u, s->stream)) != hipSuccess)
+                return hip_err(e, "clear");
+            if ((e = launch_tile_round_ex(s->t, s->conn, imgs, s->n_tiles, s->flags, s->lists,
+                                          cin, cout, 0, s->ctrl, r, s->max_sweeps,
+                                          persistent_grid(), s->stream)) != hipSuccess)
+                return hip_err(e, "tile round");
+            s->round = r + 1;
+            ++s->rounds_run;
+        }
+        const uint32_t last = s->round - 1;
+        if ((e = launch_server_status(s->lists + (size_t)((last + 1) & 1) * s->n_tiles, cout,
+                                      s->owner, s->busy, s->n_tiles, last + 1, s->stream)) !=
             hipSuccess)
             return hip_err(e, "status");
-        if ((e = hipMemcpyAsync(s->h_busy + (size_t)(r & 1) * s->max_jobs, s->busy,
+        if ((e = hipMemcpyAsync(s->h_busy + (size_t)buf * s->max_jobs, s->busy,
                                 sizeof(uint32_t) * s->max_jobs, hipMemcpyDeviceToHost,
                                 s->stream)) != hipSuccess)
             return hip_err(e, "status copy");
-        if ((e = hipEventRecord(s->ev_round[r & 1], s->stream)) != hipSuccess)
+        if ((e = hipEventRecord(s->ev_round[buf], s->stream)) != hipSuccess)
             return hip_err(e, "event");
-        s->round = r + 1;
-        ++s->rounds_run;
-        launched = r;
+        launched = last;
     }
-    // 2. retire what the previous round finished: jobs that had joined by
-    //    then and have no tile on the list it left for the next round
+    // 2. retire what the previous step finished: jobs that had joined by its
+    //    last round p and have no tile on the list p left for the next round
+    //    (a job that finished earlier in that step has none on it either)
     const uint32_t p = s->inflight;
+    const int pb = s->inflight_buf;
     s->inflight = launched;
+    s->inflight_buf = buf;
     if (p) {
-        if ((e = hipEventSynchronize(s->ev_round[p & 1])) != hipSuccess)
+        if ((e = hipEventSynchronize(s->ev_round[pb])) != hipSuccess)
             return hip_err(e, "round");
-        const uint32_t *hb = s->h_busy + (size_t)(p & 1) * s->max_jobs;
+        const uint32_t *hb = s->h_busy + (size_t)pb * s->max_jobs;
         std::vector<int32_t> finished;
         for (auto &kv : s->resident) {
             const Job &j = kv.second;
             if (j.first_round <= p && hb[j.slot] != p + 1) finished.push_back(kv.first);
         }
         if (!finished.empty() &&
-            (e = hipStreamWaitEvent(s->down, s->ev_round[p & 1], 0)) != hipSuccess)
+            (e = hipStreamWaitEvent(s->down, s->ev_round[pb], 0)) != hipSuccess)
             return hip_err(e, "event wait");
         for (int32_t slot : finished) {
             Job &j = s->resident[slot];
@@ -430,6 +442,14 @@ int mr_server_step(mr_server *s) {
         }
     }
     return collect(s, false);
+}
+
+int mr_server_set_rounds_per_step(mr_server *s, int32_t k) {
+    clear_error();
+    if (!s) return sfail(MR_EINVAL, "null server");
+    if (k < 1 || k > 64) return sfail(MR_EINVAL, "rounds per step must be in 1..64");
+    s->rounds_per_step = k;
+    return MR_OK;
 }
 
 int mr_server_poll(mr_server *s, uint64_t *done_ids, int32_t cap, int32_t *n_done) {

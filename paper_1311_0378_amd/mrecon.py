@@ -114,6 +114,8 @@ def lib():
         L.mr_server_submit.restype = c_int
         L.mr_server_step.argtypes = [vp]
         L.mr_server_step.restype = c_int
+        L.mr_server_set_rounds_per_step.argtypes = [vp, i32]
+        L.mr_server_set_rounds_per_step.restype = c_int
         L.mr_server_poll.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), i32, ctypes.POINTER(i32)]
         L.mr_server_poll.restype = c_int
         L.mr_server_drain.argtypes = [vp]
@@ -332,7 +334,7 @@ class Server:
     whose results have arrived in host memory."""
 
     def __init__(self, arena_bytes: int, max_jobs: int = 64, dtype=torch.uint8, conn: int = 8,
-                 device="cuda:0", stream=None):
+                 device="cuda:0", stream=None, rounds_per_step: int | None = None):
         self.dtype = dtype
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
         h = ctypes.c_void_p()
@@ -341,6 +343,8 @@ class Server:
                                       ctypes.byref(h)))
         self._h = h
         self.jobs = {}  # id -> (buffers kept alive until done, result)
+        if rounds_per_step is not None:
+            _check(lib().mr_server_set_rounds_per_step(self._h, int(rounds_per_step)))
 
     def submit(self, data, mask=None, op=None, out=None):
         """Admit ``data`` (the marker, or for fill-holes the image when

@@ -162,3 +162,7 @@ def test_plane_limit(L):
     assert n > 0
     assert L.mr_workspace_bytes(mrecon.MR_OP_RECON, 65536, 65536, mrecon.MR_U8, 8, None) == 0
     assert b"2^32" in L.mr_last_error()
+
+
+def test_server_rounds_per_step_validation(L):
+    assert L.mr_server_set_rounds_per_step(None, 4) == mrecon.MR_EINVAL

@@ -29,8 +29,8 @@ def alone(job, conn):
     return d.cpu().numpy()
 
 
-def run_server(jobs, arena, conn=8, per_step=3, dtype=torch.uint8, max_jobs=16):
-    srv = mrecon.Server(arena, max_jobs=max_jobs, dtype=dtype, conn=conn)
+def run_server(jobs, arena, conn=8, per_step=3, dtype=torch.uint8, max_jobs=16, rounds=None):
+    srv = mrecon.Server(arena, max_jobs=max_jobs, dtype=dtype, conn=conn, rounds_per_step=rounds)
     pending = list(enumerate(jobs))
     ids, results, eagain = {}, {}, 0
     steps = 0
@@ -55,11 +55,12 @@ def run_server(jobs, arena, conn=8, per_step=3, dtype=torch.uint8, max_jobs=16):
     return results, eagain
 
 
+@pytest.mark.parametrize("rounds", [1, 2, 3, None], ids=lambda r: f"rounds{r}")
 @pytest.mark.parametrize("conn", [4, 8])
-def test_server_results_equal_alone_and_oracle(conn):
+def test_server_results_equal_alone_and_oracle(conn, rounds):
     jobs = make_batch(30, "u8", seed=11 + conn, lo=20, hi=600)
-    print(f"[gpu] server 30 jobs conn{conn}", flush=True)
-    results, _ = run_server(jobs, 256 << 20, conn=conn)
+    print(f"[gpu] server 30 jobs conn{conn} rounds/step {rounds}", flush=True)
+    results, _ = run_server(jobs, 256 << 20, conn=conn, rounds=rounds)
     assert len(results) == len(jobs)
     for i, job in enumerate(jobs):
         want = oracle_of(job, conn)
