@@ -70,9 +70,10 @@ def cpu_model() -> str:
 
 
 def kernel_source_hash() -> str:
+    """Hash of the sources that define the tile-round kernel."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1311_0378_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in ("mr_internal.h", "mr_kernels.hip"):
         h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
