@@ -172,20 +172,27 @@ __device__ __forceinline__ void stage_u8(__amdgpu_buffer_rsrc_t rs, int64_t gy0,
 // Load one 64 x 64 register tile. INITIAL builds the starting working image
 // (reconstruction: min(marker, mask); fill-holes: the complement on the image
 // border and the minimum inside) instead of reading it; FILL reads the input
-// image and complements it into the mask. Outside pixels become key 0. The
-// halo ring gets I = J, which freezes it: min(max(J, n), J) = J.
+// image and complements it into the mask. Outside pixels become key 0 in
+// both, which keeps them at 0.
+// The halo is not frozen: a sweep may raise a halo pixel from its in-tile
+// neighbours. That is a true geodesic dilation step on real values, so every
+// value stays at or below the reconstruction; halo values are never stored,
+// and a tile at a fixed point against a raised halo is one against the stored
+// halo as well (the dilation step is monotone).
 // uint8 tiles whose planes are 16-byte aligned are staged through LDS
 // (`stage`, at least 2 * STAGE_BYTES); other uint8 planes and int32 rows (which
 // are already 256-byte coalesced loads) go straight to registers from
-// clamped, in-bounds addresses.
+// clamped, in-bounds addresses. For staged tiles inside the image the
+// transposed mask IT (lane = row, register = column) is read straight from
+// the stage, and `it_done` says so.
 template <typename T, bool FILL, bool INITIAL>
 __device__ __forceinline__ void load_tile(const ImgDesc &d, int64_t gy0, int64_t gx0, int lane,
-                                          uint32_t (&J)[TS], uint32_t (&I)[TS], uint8_t *stage) {
+                                          uint32_t (&J)[TS], uint32_t (&I)[TS],
+                                          uint32_t (&IT)[TS], uint8_t *stage, bool &it_done) {
     using P = Pix<T>;
     const int64_t H = d.H, W = d.W;
     const int64_t gx = gx0 + lane;
     const bool xin = gx >= 0 && gx < W;
-    const bool halo_lane = lane == 0 || lane == TS - 1;
     const bool xedge = gx == 0 || gx == W - 1;
     // The whole tile, halo included, lies inside the image (wave-uniform):
     // no pixel needs the outside rule. A fill-holes image's first visit also
@@ -209,8 +216,19 @@ __device__ __forceinline__ void load_tile(const ImgDesc &d, int64_t gy0, int64_t
                 uint32_t jv = stJ[r * SROW + sh];
                 if (INITIAL) jv = min(jv, iv);
                 J[r] = jv;
-                I[r] = (halo_lane || r == 0 || r == TS - 1) ? jv : iv;
+                I[r] = iv;
             }
+            // lane = row: this lane's row of the mask, interior columns only
+            // (the horizontal sweeps never clamp the halo columns)
+            const uint8_t *row = stI + lane * SROW + (int)(gx0 - a);
+#pragma unroll
+            for (int c = 1; c < TS - 1; ++c) {
+                uint32_t v = row[c];
+                if (FILL) v = P::KMAX - v;
+                IT[c] = v;
+            }
+            IT[0] = IT[TS - 1] = 0u;
+            it_done = true;
         } else {
 #pragma unroll
             for (int r = 0; r < TS; ++r) {
@@ -228,7 +246,7 @@ __device__ __forceinline__ void load_tile(const ImgDesc &d, int64_t gy0, int64_t
                 jv = ok ? jv : 0u;
                 iv = ok ? iv : 0u;
                 J[r] = jv;
-                I[r] = (halo_lane || r == 0 || r == TS - 1) ? jv : iv;
+                I[r] = iv;
             }
         }
         __syncthreads();
@@ -246,7 +264,7 @@ __device__ __forceinline__ void load_tile(const ImgDesc &d, int64_t gy0, int64_t
             uint32_t jv = P::key(Jp[oJ]);
             if (INITIAL) jv = min(jv, iv);
             J[r] = jv;
-            I[r] = (halo_lane || r == 0 || r == TS - 1) ? jv : iv;
+            I[r] = iv;
             oI += (uint32_t)d.pI;
             oJ += (uint32_t)d.pJ;
         }
@@ -272,7 +290,7 @@ __device__ __forceinline__ void load_tile(const ImgDesc &d, int64_t gy0, int64_t
         jv = ok ? jv : 0u;
         iv = ok ? iv : 0u;
         J[r] = jv;
-        I[r] = (halo_lane || r == 0 || r == TS - 1) ? jv : iv;
+        I[r] = iv;
     }
 }
 
@@ -404,11 +422,16 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
     const int64_t gy0 = (int64_t)ty * TI - 1, gx = (int64_t)tx * TI - 1 + lane;
 
     uint32_t J[TS], I[TS], IT[TS];
-    load_tile<T, FILL, INITIAL>(d, gy0, (int64_t)tx * TI - 1, lane, J, I, (uint8_t *)tb);
+    bool it_done = false;
+    load_tile<T, FILL, INITIAL>(d, gy0, (int64_t)tx * TI - 1, lane, J, I, IT, (uint8_t *)tb,
+                                it_done);
+    if (!it_done) {
 #pragma unroll
-    for (int r = 0; r < TS; ++r) IT[r] = I[r];
-    transpose(IT, tb, lane);
+        for (int r = 0; r < TS; ++r) IT[r] = I[r];
+        transpose(IT, tb, lane);
+    }
 
+    const bool in_lane = lane >= 1 && lane <= TS - 2;
     const uint32_t top_in = J[1], bot_in = J[TS - 2];
     const uint64_t col_in = col_sum<T>(J);
     uint64_t col_prev = col_in;
@@ -428,7 +451,8 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
         sweep_bwd<false>(J, IT);
         transpose(J, tb, lane);
         const uint64_t col_now = col_sum<T>(J);
-        const bool ch = col_now != col_prev;
+        // halo columns may rise too, but only the interior must settle
+        const bool ch = in_lane && col_now != col_prev;
         col_prev = col_now;
         if (__ballot(ch) == 0) {
             stable = true;
@@ -439,7 +463,6 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
     if (lane == 0)
         atomicAdd(&ctrl->iters[t & (NCNT - 1)], (unsigned long long)(it + (stable ? 1 : 0)));
 
-    const bool in_lane = lane >= 1 && lane <= TS - 2;
     if (changed || first) {
         gptr<T> Jw = (gptr<T>)d.J;
         if (in_lane && gx < d.W) {
@@ -619,8 +642,9 @@ __device__ __forceinline__ void seed_tile(const ImgDesc &d, int64_t t, int lane,
     const int64_t lt = t - d.tile_base;
     const int ty = (int)(lt / d.ntx), tx = (int)(lt - (int64_t)ty * d.ntx);
     const int64_t gy0 = (int64_t)ty * TI - 1, gx = (int64_t)tx * TI - 1 + lane;
-    uint32_t J[TS], I[TS];
-    load_tile<T, FILL, false>(d, gy0, (int64_t)tx * TI - 1, lane, J, I, stage);
+    uint32_t J[TS], I[TS], IT[TS];
+    bool it_done = false;
+    load_tile<T, FILL, false>(d, gy0, (int64_t)tx * TI - 1, lane, J, I, IT, stage, it_done);
     uint64_t myrow = 0; // lane r ends up holding row r's bits
     uint32_t nseed = 0;
     gptr<T> Jw = (gptr<T>)d.J;
@@ -635,7 +659,9 @@ __device__ __forceinline__ void seed_tile(const ImgDesc &d, int64_t t, int lane,
             n = max(n, max(from_lower_lane(J[r + 1]), from_upper_lane(J[r + 1])));
         }
         const uint32_t v = min(max(J[r], n), I[r]);
-        const bool raised = v > J[r]; // frozen halo and outside pixels have I == J
+        // only this tile's own pixels: the halo columns belong to the
+        // neighbours (outside pixels have I == J == 0 and never rise)
+        const bool raised = lane >= 1 && lane <= TS - 2 && v > J[r];
         const uint64_t bits = __ballot(raised);
         if (raised) Jw[off] = P::val(v);
         if (lane == r) myrow = bits;
