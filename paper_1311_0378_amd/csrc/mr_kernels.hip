@@ -552,8 +552,14 @@ __global__ __launch_bounds__(64, 2) void k_tile_round(Imgs imgs, int64_t n_tiles
     Appender app{abuf, 0, lists + ((round + 1) & 1) * n_tiles, counts_out, n_tiles};
     const uint32_t *list_in = lists + (round & 1) * n_tiles + lo;
     const int64_t n = all_tiles ? band_lo(n_tiles, band + 1) - lo : (int64_t)counts_in[band];
+    // Odd rounds walk the band forward, even rounds backward: a tile stored
+    // early in a round is read by tiles visited later in it, so information
+    // travels down the image within odd rounds and up it within even ones,
+    // as in a raster / anti-raster pair of scans.
+    const bool fwd = (round & 1) != 0;
     for (int64_t i = local; i < n; i += per) {
-        const int64_t t = all_tiles ? lo + i : (int64_t)list_in[i];
+        const int64_t k = fwd ? i : n - 1 - i;
+        const int64_t t = all_tiles ? lo + k : (int64_t)list_in[k];
         const ImgDesc d = load_desc(imgs, t);
         if (V >= 0) {
             if (!d.done)
