@@ -11,6 +11,9 @@ times (library defaults), and at the largest plane the interface accepts.
   row and column of blocks included, are checked exactly against the oracle
   run on the block alone. The whole image is checked for marker <= R <= mask
   and for being a fixed point of one geodesic dilation step.
+* The 512-tile batch at full size, autotuned and replayed as the benchmark
+  times it, and the first 100 serving jobs through the server: every image
+  against the oracle.
 """
 import numpy as np
 import pytest
@@ -99,3 +102,77 @@ def test_max_plane_walled_blocks(conn):
         d = d[y0 - a:y0 - a + (y1 - y0)]
         step_once = torch.minimum(d, mask[y0:y1].to(torch.float16))
         assert bool((step_once == r.to(torch.float16)).all()), f"not a fixed point near row {y0}"
+
+
+def _oracle_all(jobs, conn):
+    """Oracle results of (marker-or-image, mask-or-None) jobs, on threads."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(job):
+        a, m = job
+        return (oracle.recon_dilate(a, m, conn) if m is not None else oracle.fill_holes(a, conn))[0]
+
+    with ThreadPoolExecutor(16) as ex:
+        return list(ex.map(one, jobs))
+
+
+def test_batch_512_tiles_full():
+    # the batched workload at its full size (sides log-uniform 256-4096,
+    # about 1.0 Gpx), autotuned and replayed the way the benchmark times it
+    from concurrent.futures import ThreadPoolExecutor
+    n = 512
+    shapes = synth.batch_shapes(n)
+    with ThreadPoolExecutor(8) as ex:
+        tiles = list(ex.map(lambda i: synth.batch_tile(i, *shapes[i], n=n), range(n)))
+    print(f"[gpu] batch of {n} tiles, {sum(h * w for h, w in shapes) / 1e9:.2f} Gpx", flush=True)
+    src = [torch.from_numpy(m).to(DEV) for m, _ in tiles]
+    msk = [torch.from_numpy(k).to(DEV) for _, k in tiles]
+    work = [x.clone() for x in src]
+    items = [(w, k, mrecon.MR_OP_RECON) for w, k in zip(work, msk)]
+    tune = mrecon.autotune(items, 8)
+    ws = mrecon.alloc_workspace(mrecon.batch_workspace_bytes(items, 8, tune), DEV)
+    if tune.sweep_rounds > 0:
+        g = mrecon.BatchGraph(items, 8, tune, ws)
+        g.launch()
+        torch.cuda.synchronize()
+        g.close()
+    else:
+        mrecon.batch(items, 8, tune, ws)
+    want = _oracle_all(tiles, 8)
+    for i in range(n):
+        got = work[i].cpu().numpy()
+        assert np.array_equal(got, want[i]), f"tile {i} {shapes[i]}: " + first_mismatch(got, want[i])
+
+
+def test_serving_jobs_full_sizes():
+    # the first 100 jobs of the serving workload (windows of the two serving
+    # images, sides 512-8192, recon and fill-holes mixed) through the server
+    # with its default settings
+    n = 100
+    jobs = synth.serving_jobs(2000)[:n]
+    wins = synth.serving_windows(synth.serving_jobs(2000))[:n]
+    bm, bk, bf = synth.serving_banks()
+    inputs = []
+    for (kind, H, W), (y, x) in zip(jobs, wins):
+        if kind == "recon":
+            inputs.append((np.ascontiguousarray(bm[y:y + H, x:x + W]),
+                           np.ascontiguousarray(bk[y:y + H, x:x + W])))
+        else:
+            inputs.append((np.ascontiguousarray(bf[y:y + H, x:x + W]), None))
+    print(f"[gpu] server, {n} serving jobs", flush=True)
+    srv = mrecon.Server(8 << 30, max_jobs=32)
+    pending, owned, got = list(range(n)), {}, {}
+    while pending or owned:
+        while pending:
+            a, m = inputs[pending[0]]
+            jid = srv.submit(a, m)
+            if jid is None:
+                break
+            owned[jid] = pending.pop(0)
+        srv.step()
+        for jid, res in srv.poll():
+            got[owned.pop(jid)] = res.numpy()
+    srv.close()
+    want = _oracle_all(inputs, 8)
+    for i in range(n):
+        assert np.array_equal(got[i], want[i]), f"job {i} {jobs[i]}: " + first_mismatch(got[i], want[i])
