@@ -78,7 +78,10 @@ typedef struct {
                                   (1..1024); a capped tile is revisited */
     int32_t persistent_blocks; /* queue-phase workgroups; 0 = as many as can
                                   be co-resident on the GPU */
-    int32_t reserved;          /* must be 0 */
+    int32_t converge_rounds;   /* with a negative sweep_rounds: tile rounds
+                                  after which work still left goes to the seed
+                                  pass and the queue phase, which finish any
+                                  input (1..1000; 0 = 1000) */
 } mr_tune;
 
 /* Work counters of the last call that used a workspace. */

@@ -88,7 +88,8 @@ int check_tune(const mr_tune *tn) {
         return fail(MR_EINVAL, "tune.max_sweeps must be in 1..1024 (got %d)", tn->max_sweeps);
     if (tn->persistent_blocks < 0)
         return fail(MR_EINVAL, "tune.persistent_blocks must be >= 0");
-    if (tn->reserved != 0) return fail(MR_EINVAL, "tune.reserved must be 0");
+    if (tn->converge_rounds < 0 || tn->converge_rounds > MAX_ROUNDS)
+        return fail(MR_EINVAL, "tune.converge_rounds must be in 0..%d", MAX_ROUNDS);
     return MR_OK;
 }
 
@@ -215,26 +216,17 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
                               tn.max_sweeps, grid, s, op_all);
     }
     if (e != hipSuccess) return hip_fail(e, "tile round");
-    if (tn.sweep_rounds > 0) {
-        for (round = 2; round <= (uint32_t)tn.sweep_rounds; ++round) {
-            {
-                LaunchTimer lt(s, MR_K_TILE_ROUND, (int32_t)round);
-                e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl, round,
-                                      tn.max_sweeps, grid, s, op_all);
-            }
-            if (e != hipSuccess) return hip_fail(e, "tile round");
-        }
-        if ((e = launch_store_u64(&ctrl->rounds, (unsigned long long)tn.sweep_rounds, s)) !=
-            hipSuccess)
-            return hip_fail(e, "store");
+    // Seed pass and queue phase over the tiles listed for round `seed_round`
+    // (the round after the last one run).
+    auto queue_phase = [&](uint32_t seed_round) -> int {
         if ((e = launch_clear_u32(qflag, L.n_tiles, 0u, s)) != hipSuccess ||
             (e = launch_clear_u64(bitmap, L.n_tiles * TS, s)) != hipSuccess ||
             (e = launch_clear_u32(ring, (int64_t)L.ring_cap, Q_EMPTY, s)) != hipSuccess)
             return hip_fail(e, "clear");
         {
             LaunchTimer lt(s, MR_K_SEED, 0);
-            e = launch_seed(tbytes, conn, imgs, L.n_tiles, lists, round, ctrl, bitmap, qflag, ring,
-                            L.ring_cap, grid, s);
+            e = launch_seed(tbytes, conn, imgs, L.n_tiles, lists, seed_round, ctrl, bitmap, qflag,
+                            ring, L.ring_cap, grid, s);
         }
         if (e != hipSuccess) return hip_fail(e, "seed");
         int blocks = tn.persistent_blocks;
@@ -247,14 +239,32 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
                              SPIN_CAP, s);
         }
         if (e != hipSuccess) return hip_fail(e, "queue");
+        return MR_OK;
+    };
+    if (tn.sweep_rounds > 0) {
+        for (round = 2; round <= (uint32_t)tn.sweep_rounds; ++round) {
+            {
+                LaunchTimer lt(s, MR_K_TILE_ROUND, (int32_t)round);
+                e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl, round,
+                                      tn.max_sweeps, grid, s, op_all);
+            }
+            if (e != hipSuccess) return hip_fail(e, "tile round");
+        }
+        if ((e = launch_store_u64(&ctrl->rounds, (unsigned long long)tn.sweep_rounds, s)) !=
+            hipSuccess)
+            return hip_fail(e, "store");
+        const int rc = queue_phase(round);
+        if (rc != MR_OK) return rc;
     } else {
         // converge mode: rounds until a round leaves no dirty tile, polling
         // every few rounds
         unsigned long long *hw = host_word();
         if (!hw) return fail(MR_EHIP, "cannot allocate a pinned host word");
         const uint32_t poll = 8;
+        const uint32_t cap = tn.converge_rounds > 0 ? (uint32_t)tn.converge_rounds : MAX_ROUNDS;
+        bool left = false; // work still listed after `cap` rounds
         while (true) {
-            for (uint32_t k = 0; k < poll && round < MAX_ROUNDS; ++k) {
+            for (uint32_t k = 0; k < poll && round < cap; ++k) {
                 ++round;
                 {
                     LaunchTimer lt(s, MR_K_TILE_ROUND, (int32_t)round);
@@ -270,10 +280,18 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
             uint64_t next = 0;
             for (int b = 0; b < NBANDS; ++b) next += ((const uint32_t *)hw)[b];
             if (next == 0) break;
-            if (round >= MAX_ROUNDS) return fail(MR_EHIP, "tile rounds did not converge");
+            if (round >= cap) {
+                left = true;
+                break;
+            }
         }
         if ((e = launch_store_u64(&ctrl->rounds, (unsigned long long)round, s)) != hipSuccess)
             return hip_fail(e, "store");
+        // a propagation path too long for the rounds: the queue finishes it
+        if (left) {
+            const int rc = queue_phase(round + 1);
+            if (rc != MR_OK) return rc;
+        }
     }
     if (any_fill && (e = launch_fill_output(tbytes, imgs, L.n_tiles, s)) != hipSuccess)
         return hip_fail(e, "fill output");
@@ -433,7 +451,7 @@ void mr_default_tune(mr_tune *out) {
     out->sweep_rounds = -1;
     out->max_sweeps = 16;
     out->persistent_blocks = 0;
-    out->reserved = 0;
+    out->converge_rounds = 0;
 }
 
 size_t mr_workspace_bytes(int op, int64_t H, int64_t W, mr_dtype t, int conn, const mr_tune *tune) {

@@ -32,7 +32,7 @@ class MrError(RuntimeError):
 
 class Tune(ctypes.Structure):
     _fields_ = [("sweep_rounds", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
-                ("persistent_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("persistent_blocks", ctypes.c_int32), ("converge_rounds", ctypes.c_int32)]
 
 
 class Tile(ctypes.Structure):

@@ -25,7 +25,7 @@ def test_abi_version(L):
 
 def test_default_tune():
     t = mrecon.default_tune()
-    assert t.sweep_rounds != 0 and 1 <= t.max_sweeps <= 1024 and t.reserved == 0
+    assert t.sweep_rounds != 0 and 1 <= t.max_sweeps <= 1024 and t.converge_rounds == 0
 
 
 def test_workspace_bytes_grows_with_size():
@@ -77,7 +77,8 @@ def test_recon_rejects(L, kw, code):
 
 @pytest.mark.parametrize("field,value", [("sweep_rounds", 0), ("max_sweeps", 0),
                                          ("max_sweeps", 5000), ("persistent_blocks", -1),
-                                         ("reserved", 1)])
+                                         ("converge_rounds", -1),
+                                         ("converge_rounds", 1001)])
 def test_recon_rejects_bad_tune(L, field, value):
     t = mrecon.default_tune()
     setattr(t, field, value)

@@ -25,7 +25,8 @@ from gpu_util import first_mismatch, gpu_fill, gpu_recon  # noqa: E402
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 TUNES = [None, dict(sweep_rounds=1, max_sweeps=1), dict(sweep_rounds=2, max_sweeps=3),
-         dict(sweep_rounds=-1), dict(sweep_rounds=8, persistent_blocks=3)]
+         dict(sweep_rounds=-1), dict(sweep_rounds=8, persistent_blocks=3),
+         dict(sweep_rounds=-1, converge_rounds=2)]
 
 
 def check(got, want):
@@ -92,7 +93,10 @@ def test_serpentine_queue_heavy(conn):
     from test_oracle_pins import serpentine
     marker, mask = serpentine(127, 129, 7)
     want, _ = oracle.recon_dilate(marker, mask, conn)
-    for tune in (None, dict(sweep_rounds=1, max_sweeps=1)):
+    # the last tunes stop the tile rounds early and leave the long corridor to
+    # the seed pass and the queue phase
+    for tune in (None, dict(sweep_rounds=1, max_sweeps=1), dict(sweep_rounds=-1, converge_rounds=1),
+                 dict(sweep_rounds=-1, converge_rounds=5)):
         got, c = gpu_recon(marker, mask, conn, tune=tune, counters=True)
         check(got, want)
 
