@@ -546,7 +546,7 @@ def main():
     workload_key = f"recon {S}x{S} {dt} conn{conn}"
     traffic = load_traffic(workload_key)
     result = {
-        "metric": "reconstructed Mpixel/s (bit-exact)",
+        "metric": "reconstructed Mpixel/s (bit-exact) + %HBM roofline; batched vs per-tile; p50/p99",
         "value": round(value, 1),
         "unit": "Mpixel/s",
         "n_gpus": 1,
@@ -559,7 +559,7 @@ def main():
         "dtype": dt,
         "data": "synthetic",
         "config": {"workload": f"recon_dilate {S}x{S} {dt} conn{conn}, {n_disks} disks, seed 0",
-                   "global_batch": 1, "parallelism": "single-gpu"},
+                   "image": f"{S}x{S}", "pixel": dt, "conn": conn},
         "roofline": {
             "bound": "hbm",
             "kernel": "k_tile_round",
