@@ -183,12 +183,14 @@ __device__ __forceinline__ void stage_u8(__amdgpu_buffer_rsrc_t rs, int64_t gy0,
 // (`stage`, at least 2 * STAGE_BYTES); other uint8 planes and int32 rows (which
 // are already 256-byte coalesced loads) go straight to registers from
 // clamped, in-bounds addresses. For staged tiles inside the image the
-// transposed mask IT (lane = row, register = column) is read straight from
-// the stage, and `it_done` says so.
+// transposed mask IT (lane = row, register = column) and the loaded halo
+// columns JL, JR (lane = row) are read straight from the stage, and `it_done`
+// says so.
 template <typename T, bool FILL, bool INITIAL>
 __device__ __forceinline__ void load_tile(const ImgDesc &d, int64_t gy0, int64_t gx0, int lane,
                                           uint32_t (&J)[TS], uint32_t (&I)[TS],
-                                          uint32_t (&IT)[TS], uint8_t *stage, bool &it_done) {
+                                          uint32_t (&IT)[TS], uint32_t &JL, uint32_t &JR,
+                                          uint8_t *stage, bool &it_done) {
     using P = Pix<T>;
     const int64_t H = d.H, W = d.W;
     const int64_t gx = gx0 + lane;
@@ -218,16 +220,22 @@ __device__ __forceinline__ void load_tile(const ImgDesc &d, int64_t gy0, int64_t
                 J[r] = jv;
                 I[r] = iv;
             }
-            // lane = row: this lane's row of the mask, interior columns only
-            // (the horizontal sweeps never clamp the halo columns)
+            // lane = row: this lane's row of the mask, and the working
+            // image's two halo pixels of that row
             const uint8_t *row = stI + lane * SROW + (int)(gx0 - a);
 #pragma unroll
-            for (int c = 1; c < TS - 1; ++c) {
+            for (int c = 0; c < TS; ++c) {
                 uint32_t v = row[c];
                 if (FILL) v = P::KMAX - v;
                 IT[c] = v;
             }
-            IT[0] = IT[TS - 1] = 0u;
+            const uint8_t *rowJ = stJ + lane * SROW + (int)(gx0 - a);
+            JL = rowJ[0];
+            JR = rowJ[TS - 1];
+            if (INITIAL) {
+                JL = min(JL, IT[0]);
+                JR = min(JR, IT[TS - 1]);
+            }
             it_done = true;
         } else {
 #pragma unroll
@@ -329,6 +337,33 @@ __device__ __forceinline__ uint32_t step3(uint32_t j, uint32_t u, uint32_t i) {
     return r;
 }
 
+// Max over lanes l-1, l, l+1 (0 beyond the wave's ends).
+__device__ __forceinline__ uint32_t max3_lanes(uint32_t u) {
+    uint32_t t;
+    asm("s_nop 1\n\t"
+        "v_max_u32_dpp %0, %1, %1 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_max_u32_dpp %0, %1, %0 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+        : "=&v"(t)
+        : "v"(u));
+    return t;
+}
+
+// The halo columns 0 and TS-1 of a register tile, lane = row: lanes 0 and
+// TS-1 write their registers to LDS and every lane reads its row back.
+__device__ __forceinline__ void halo_cols(const uint32_t (&A)[TS], uint32_t (*tb)[TS + 1],
+                                          int lane, uint32_t &cl, uint32_t &cr) {
+    uint32_t *buf = &tb[0][0];
+    if (lane == 0 || lane == TS - 1) {
+        uint32_t *dst = buf + (lane == 0 ? 0 : TS);
+#pragma unroll
+        for (int r = 0; r < TS; ++r) dst[r] = A[r];
+    }
+    __syncthreads();
+    cl = buf[lane];
+    cr = buf[TS + lane];
+    __syncthreads();
+}
+
 // Sweeps along the registers. With DIAG, A[r] takes the max over the three
 // lanes of the previous register (the 3 neighbours in the previous row), else
 // only the same lane; the result is limited by B[r]. Values only rise, so
@@ -422,14 +457,18 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
     const int64_t gy0 = (int64_t)ty * TI - 1, gx = (int64_t)tx * TI - 1 + lane;
 
     uint32_t J[TS], I[TS], IT[TS];
+    uint32_t JL, JR; // loaded halo columns 0 and TS-1, lane = row
     bool it_done = false;
-    load_tile<T, FILL, INITIAL>(d, gy0, (int64_t)tx * TI - 1, lane, J, I, IT, (uint8_t *)tb,
-                                it_done);
+    load_tile<T, FILL, INITIAL>(d, gy0, (int64_t)tx * TI - 1, lane, J, I, IT, JL, JR,
+                                (uint8_t *)tb, it_done);
     if (!it_done) {
 #pragma unroll
         for (int r = 0; r < TS; ++r) IT[r] = I[r];
         transpose(IT, tb, lane);
+        halo_cols(J, tb, lane, JL, JR);
     }
+    // loaded halo rows 0 and TS-1 (the sweeps may raise them in registers)
+    const uint32_t JT = J[0], JB = J[TS - 1];
 
     const bool in_lane = lane >= 1 && lane <= TS - 2;
     const uint32_t top_in = J[1], bot_in = J[TS - 2];
@@ -494,23 +533,40 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
     const uint64_t bt = __ballot(in_lane && J[1] != top_in);
     const uint64_t bb = __ballot(in_lane && J[TS - 2] != bot_in);
     const uint64_t bc = __ballot(col_out != col_in);
+    // Can the final border still raise a halo pixel, i.e. is min(mask, max of
+    // its neighbours in this tile's interior) above the value the pixel held
+    // when this visit loaded it? Pixels only rise, so a halo pixel that passes
+    // against its loaded value passes against its current one too, and its
+    // tile need not be visited on this tile's account. Rows 0 and TS-1 in
+    // lanes 0..TS-1 (lane = column), then columns 0 and TS-1 in lanes 0..TS-1
+    // (lane = row), whose border columns 1 and TS-2 the last transpose left in
+    // LDS.
+    const uint32_t b1 = in_lane ? J[1] : 0u, b2 = in_lane ? J[TS - 2] : 0u;
+    const uint32_t c1 = in_lane ? tb[1][lane] : 0u, c2 = in_lane ? tb[TS - 2][lane] : 0u;
+    const uint32_t nbT = CONN == 8 ? max3_lanes(b1) : b1, nbB = CONN == 8 ? max3_lanes(b2) : b2;
+    const uint32_t nbL = CONN == 8 ? max3_lanes(c1) : c1, nbR = CONN == 8 ? max3_lanes(c2) : c2;
+    const uint64_t rt = __ballot(med3(JT, nbT, I[0]) > JT);
+    const uint64_t rb = __ballot(med3(JB, nbB, I[TS - 1]) > JB);
+    const uint64_t rl = __ballot(med3(JL, nbL, IT[0]) > JL);
+    const uint64_t rr = __ballot(med3(JR, nbR, IT[TS - 1]) > JR);
+    constexpr uint64_t EDGE = ~(1ull | (1ull << (TS - 1))); // lanes 1..TS-2
     // Lanes 0..8 each consider one tile to mark dirty for the next round:
-    // itself (if the sweep cap stopped it early) and the neighbours whose halo
-    // holds a changed border pixel. The atomic max on the flag lets exactly
-    // one marker put a tile on the next list.
+    // itself (if the sweep cap stopped it early) and the neighbours next to a
+    // changed border pixel that can raise one of their pixels. The atomic max
+    // on the flag lets exactly one marker put a tile on the next list.
     const uint32_t nxt = round + 1;
     bool want = false;
     int dy = 0, dx = 0;
     switch (lane) {
     case 0: want = !stable; break;
-    case 1: want = bt != 0; dy = -1; break;
-    case 2: want = bb != 0; dy = 1; break;
-    case 3: want = (bc >> 1) & 1; dx = -1; break;
-    case 4: want = (bc >> (TS - 2)) & 1; dx = 1; break;
-    case 5: want = CONN == 8 && ((bt >> 1) & 1); dy = -1; dx = -1; break;
-    case 6: want = CONN == 8 && ((bt >> (TS - 2)) & 1); dy = -1; dx = 1; break;
-    case 7: want = CONN == 8 && ((bb >> 1) & 1); dy = 1; dx = -1; break;
-    case 8: want = CONN == 8 && ((bb >> (TS - 2)) & 1); dy = 1; dx = 1; break;
+    case 1: want = bt != 0 && (rt & EDGE) != 0; dy = -1; break;
+    case 2: want = bb != 0 && (rb & EDGE) != 0; dy = 1; break;
+    case 3: want = ((bc >> 1) & 1) && (rl & EDGE) != 0; dx = -1; break;
+    case 4: want = ((bc >> (TS - 2)) & 1) && (rr & EDGE) != 0; dx = 1; break;
+    case 5: want = CONN == 8 && ((bt >> 1) & 1) && (rt & 1); dy = -1; dx = -1; break;
+    case 6: want = CONN == 8 && ((bt >> (TS - 2)) & 1) && (rt >> (TS - 1)); dy = -1; dx = 1; break;
+    case 7: want = CONN == 8 && ((bb >> 1) & 1) && (rb & 1); dy = 1; dx = -1; break;
+    case 8: want = CONN == 8 && ((bb >> (TS - 2)) & 1) && (rb >> (TS - 1)); dy = 1; dx = 1; break;
     default: break;
     }
     const int ny = ty + dy, nx = tx + dx;
@@ -648,9 +704,10 @@ __device__ __forceinline__ void seed_tile(const ImgDesc &d, int64_t t, int lane,
     const int64_t lt = t - d.tile_base;
     const int ty = (int)(lt / d.ntx), tx = (int)(lt - (int64_t)ty * d.ntx);
     const int64_t gy0 = (int64_t)ty * TI - 1, gx = (int64_t)tx * TI - 1 + lane;
-    uint32_t J[TS], I[TS], IT[TS];
+    uint32_t J[TS], I[TS], IT[TS], JL, JR;
     bool it_done = false;
-    load_tile<T, FILL, false>(d, gy0, (int64_t)tx * TI - 1, lane, J, I, IT, stage, it_done);
+    load_tile<T, FILL, false>(d, gy0, (int64_t)tx * TI - 1, lane, J, I, IT, JL, JR, stage,
+                              it_done);
     uint64_t myrow = 0; // lane r ends up holding row r's bits
     uint32_t nseed = 0;
     gptr<T> Jw = (gptr<T>)d.J;
