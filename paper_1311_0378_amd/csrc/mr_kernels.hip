@@ -382,6 +382,29 @@ __device__ __forceinline__ void sweep_bwd(uint32_t (&A)[TS], const uint32_t (&B)
         A[r] = DIAG ? step3(A[r], A[r + 1], B[r]) : med3(A[r], A[r + 1], B[r]);
 }
 
+// One relaxation step over the interior rows: every pixel against all its
+// neighbours. With 8-connectivity the step reads the values from before it;
+// with 4-connectivity the row above is already updated. Both are valid
+// steps, and a step that changes nothing means every pixel in rows 1..TS-2 is
+// stable against all its neighbours.
+template <int CONN>
+__device__ __forceinline__ void relax_once(uint32_t (&J)[TS], const uint32_t (&I)[TS]) {
+    if (CONN == 8) {
+        uint32_t hp = max3_lanes(J[0]), hc = max3_lanes(J[1]);
+#pragma unroll
+        for (int r = 1; r < TS - 1; ++r) {
+            const uint32_t hn = max3_lanes(J[r + 1]);
+            J[r] = med3(J[r], max(max(hp, hc), hn), I[r]);
+            hp = hc;
+            hc = hn;
+        }
+    } else {
+#pragma unroll
+        for (int r = 1; r < TS - 1; ++r)
+            J[r] = med3(J[r], max(max(J[r - 1], J[r + 1]), max3_lanes(J[r])), I[r]);
+    }
+}
+
 // Sum of the interior rows of a column. Keys only rise, so the sum rises iff
 // some key changed; 62 keys below 2^32 cannot overflow 64 bits, and 62 u8 keys
 // cannot overflow 32.
@@ -462,10 +485,11 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
     load_tile<T, FILL, INITIAL>(d, gy0, (int64_t)tx * TI - 1, lane, J, I, IT, JL, JR,
                                 (uint8_t *)tb, it_done);
     if (!it_done) {
+        // (before the mask transpose: fewer registers live)
+        halo_cols(J, tb, lane, JL, JR);
 #pragma unroll
         for (int r = 0; r < TS; ++r) IT[r] = I[r];
         transpose(IT, tb, lane);
-        halo_cols(J, tb, lane, JL, JR);
     }
     // loaded halo rows 0 and TS-1 (the sweeps may raise them in registers)
     const uint32_t JT = J[0], JB = J[TS - 1];
@@ -481,26 +505,38 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
     // left sweeps take only the in-row neighbour, because the vertical sweeps
     // already test the diagonal ones. A full iteration that changes nothing
     // therefore means every pixel is stable against all its neighbours.
+    // A full iteration that changes something mostly leaves the tile at its
+    // fixed point; one relaxation step against all neighbours confirms that
+    // at a fraction of an iteration's cost (no transposes), and otherwise
+    // the iterations go on.
     int it = 0;
-    for (; it < max_iters; ++it) {
+    while (it < max_iters) {
         sweep_fwd<CONN == 8>(J, I);
         sweep_bwd<CONN == 8>(J, I);
         transpose(J, tb, lane);
         sweep_fwd<false>(J, IT);
         sweep_bwd<false>(J, IT);
         transpose(J, tb, lane);
-        const uint64_t col_now = col_sum<T>(J);
+        ++it;
+        uint64_t col_now = col_sum<T>(J);
         // halo columns may rise too, but only the interior must settle
-        const bool ch = in_lane && col_now != col_prev;
+        bool ch = in_lane && col_now != col_prev;
         col_prev = col_now;
         if (__ballot(ch) == 0) {
             stable = true;
             break;
         }
         changed = true;
+        relax_once<CONN>(J, I);
+        col_now = col_sum<T>(J);
+        ch = in_lane && col_now != col_prev;
+        col_prev = col_now;
+        if (__ballot(ch) == 0) {
+            stable = true;
+            break;
+        }
     }
-    if (lane == 0)
-        atomicAdd(&ctrl->iters[t & (NCNT - 1)], (unsigned long long)(it + (stable ? 1 : 0)));
+    if (lane == 0) atomicAdd(&ctrl->iters[t & (NCNT - 1)], (unsigned long long)it);
 
     if (changed || first) {
         gptr<T> Jw = (gptr<T>)d.J;
@@ -547,8 +583,10 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
     const uint32_t nbL = CONN == 8 ? max3_lanes(c1) : c1, nbR = CONN == 8 ? max3_lanes(c2) : c2;
     const uint64_t rt = __ballot(med3(JT, nbT, I[0]) > JT);
     const uint64_t rb = __ballot(med3(JB, nbB, I[TS - 1]) > JB);
-    const uint64_t rl = __ballot(med3(JL, nbL, IT[0]) > JL);
-    const uint64_t rr = __ballot(med3(JR, nbR, IT[TS - 1]) > JR);
+    // (after a relaxation step that still changed pixels at the sweep cap,
+    // LDS holds the columns from before it: then every halo column counts)
+    const uint64_t rl = stable ? __ballot(med3(JL, nbL, IT[0]) > JL) : ~0ull;
+    const uint64_t rr = stable ? __ballot(med3(JR, nbR, IT[TS - 1]) > JR) : ~0ull;
     constexpr uint64_t EDGE = ~(1ull | (1ull << (TS - 1))); // lanes 1..TS-2
     // Lanes 0..8 each consider one tile to mark dirty for the next round:
     // itself (if the sweep cap stopped it early) and the neighbours next to a
