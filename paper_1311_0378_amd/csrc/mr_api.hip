@@ -149,7 +149,7 @@ struct Timing {
         if (!pool.empty()) {
             e = pool.back();
             pool.pop_back();
-        } else if (hipEventCreate(&e) != hipSuccess) {
+        } else if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
             e = nullptr;
         }
         return e;
@@ -157,22 +157,27 @@ struct Timing {
 };
 thread_local Timing g_timing;
 
-// Brackets one launch with events when timing is on.
+// Brackets one launch with events when timing is on. The events are created
+// without the system-scope fence, so recording them writes back and
+// invalidates no caches between the launches they time.
 struct LaunchTimer {
     hipStream_t s;
     int32_t kind, round;
     hipEvent_t a = nullptr;
     LaunchTimer(hipStream_t s_, int32_t kind_, int32_t round_) : s(s_), kind(kind_), round(round_) {
-        if (g_timing.on && (a = g_timing.get())) hipEventRecord(a, s);
+        if (g_timing.on && (a = g_timing.get()) && hipEventRecord(a, s) != hipSuccess) {
+            g_timing.pool.push_back(a);
+            a = nullptr;
+        }
     }
     ~LaunchTimer() {
         if (!a) return;
         hipEvent_t b = g_timing.get();
-        if (!b) {
+        if (!b || hipEventRecord(b, s) != hipSuccess) {
             g_timing.pool.push_back(a);
+            if (b) g_timing.pool.push_back(b);
             return;
         }
-        hipEventRecord(b, s);
         g_timing.recs.push_back({kind, round, a, b});
     }
 };

@@ -1,0 +1,41 @@
+"""Per-launch timing (mr_timing_*): one record per tile-round, seed and queue
+launch, in launch order, with positive device times."""
+import pytest
+
+from paper_1311_0378_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # collected on CPU-only hosts too
+    pytest.skip("no GPU", allow_module_level=True)
+
+from gpu_util import gpu_recon  # noqa: E402
+from paper_1311_0378_amd import mrecon  # noqa: E402
+
+
+@pytest.mark.parametrize("tune", [None, dict(sweep_rounds=2, max_sweeps=2)],
+                         ids=["converge", "rounds+queue"])
+def test_timing_records_every_launch(tune):
+    marker, mask = synth.make_tile(700, 900, 130, 5, "u8", 0.0)
+    mrecon.timing_enable(True)
+    try:
+        out, c = gpu_recon(marker, mask, 8, tune=tune, counters=True)
+    finally:
+        mrecon.timing_enable(False)
+    recs = mrecon.timing_collect()
+    tiles = [r for r in recs if r[0] == "tile_round"]
+    assert [r[1] for r in tiles] == list(range(1, c["rounds"] + 1))
+    kinds = [r[0] for r in recs]
+    if tune is None:
+        assert kinds == ["tile_round"] * c["rounds"]
+    else:
+        assert kinds == ["tile_round"] * 2 + ["seed", "queue"]
+    assert all(ms > 0.0 for _, _, ms in recs)
+    assert mrecon.timing_collect() == []
+
+
+def test_timing_off_records_nothing():
+    marker, mask = synth.make_tile(300, 300, 20, 6, "u8", 0.0)
+    gpu_recon(marker, mask, 8)
+    assert mrecon.timing_collect() == []
