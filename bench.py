@@ -187,10 +187,12 @@ def leg_batched(args, dev) -> dict:
     restore()
     t1 = time.time()
     tune = mrecon.autotune(items, 8, stream=stream)
-    tuned = {"sweep_rounds": tune.sweep_rounds, "max_sweeps": tune.max_sweeps}
+    tuned = {"sweep_rounds": tune.sweep_rounds, "max_sweeps": tune.max_sweeps,
+             "tail_rounds": tune.tail_rounds}
     log(f"batched: autotune {tuned} in {time.time() - t1:.1f}s")
     wsb = mrecon.alloc_workspace(mrecon.batch_workspace_bytes(items, 8, tune), dev)
-    graph = mrecon.BatchGraph(items, 8, tune, wsb) if tune.sweep_rounds > 0 else None
+    graph = (mrecon.BatchGraph(items, 8, tune, wsb)
+             if tune.sweep_rounds > 0 or tune.tail_rounds > 0 else None)
     batched_s = []
     for rep in range(warm + reps):
         restore()
@@ -536,7 +538,7 @@ def main():
             elif kind == "queue":
                 queue_ms += ms
             li += 1
-        per_step.append({"tiles": step_tiles, "counters": cnt})
+        per_step.append({"tiles": step_tiles, "counters": cnt, "round_tiles": rt})
 
     npx = S * S
     ms_per_step = elapsed * 1e3 / K
@@ -581,6 +583,7 @@ def main():
             "queue_ms_per_step": round(queue_ms / K, 4),
         },
         "counters_last_step": per_step[-1]["counters"],
+        "round_tiles_last_step": [int(x) for x in per_step[-1]["round_tiles"]],
         "tune": tune or "library default",
     }
 

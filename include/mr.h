@@ -16,9 +16,11 @@
  * How (Algorithm 1, Sec. III-B on the GPU queue and atomics, Sec. V-C.2 on the
  * regular-then-irregular hybrid): tile rounds propagate inside 64 x 64
  * register tiles until a local fixed point; tiles whose halo changed are
- * revisited; after `sweep_rounds` rounds the pixels that can still raise a
- * neighbour are compacted into a device frontier queue and finished by
- * persistent workgroups with atomic max updates.
+ * revisited. By default, after `tail_rounds` rounds a persistent tile queue
+ * revisits each tile as soon as a neighbour marks it until none is left.
+ * With a positive `sweep_rounds`, after that many rounds the pixels that can
+ * still raise a neighbour are compacted into a device frontier queue and
+ * finished by persistent workgroups with atomic max updates.
  *
  * Conventions for every entry point:
  *  - Images are row-major, element (y, x) at index y * pitch + x; pitch is in
@@ -70,10 +72,9 @@ enum { MR_OP_RECON = 0, MR_OP_FILL = 1 };
  * No knob changes the result, only the time it takes. */
 typedef struct {
     int32_t sweep_rounds;      /* tile rounds before the queue phase (1..1000);
-                                  a negative value runs tile rounds until no
-                                  tile is dirty and skips the queue phase (the
-                                  call then waits for the device between
-                                  rounds) */
+                                  a negative value (the default) runs tile
+                                  rounds, then the tile queue (tail_rounds),
+                                  and skips the queue phase */
     int32_t max_sweeps;        /* cap on sweep iterations per tile visit
                                   (1..1024); a capped tile is revisited */
     int32_t persistent_blocks; /* queue-phase workgroups; 0 = as many as can
@@ -82,12 +83,21 @@ typedef struct {
                                   after which work still left goes to the seed
                                   pass and the queue phase, which finish any
                                   input (1..1000; 0 = 1000) */
+    int32_t tail_rounds;       /* with a negative sweep_rounds: tile rounds
+                                  after which the tiles still listed go to
+                                  the tile queue, one persistent launch that
+                                  revisits a tile as soon as a neighbour marks
+                                  it, until none is left; the call then never
+                                  waits for the device (0..1000, default 8;
+                                  0 = rounds until no tile is dirty, polled
+                                  by the host, and converge_rounds applies) */
 } mr_tune;
 
 /* Work counters of the last call that used a workspace. */
 typedef struct {
     uint64_t rounds;      /* tile rounds launched */
-    uint64_t tiles;       /* tile visits (64 x 64 register tiles) */
+    uint64_t tiles;       /* tile visits (64 x 64 register tiles), in tile
+                             rounds and in the tile queue */
     uint64_t seeds;       /* frontier entries made by the seed pass */
     uint64_t pops;        /* frontier entries processed by the queue phase */
     uint64_t pushes;      /* frontier entries produced by the queue phase */
@@ -153,18 +163,19 @@ int mr_batch(const mr_tile *tiles, int32_t n, mr_dtype t, int conn, void *ws, si
              const mr_tune *tune, void *stream);
 
 /* A batch captured once into a HIP graph, for repeated launches over the same
- * buffers (new data copied into them between launches). Needs
- * tune->sweep_rounds > 0 (a fixed number of tile rounds, then the queue
- * phase), because the converge mode waits on the host. */
+ * buffers (new data copied into them between launches). Needs a tune whose
+ * call never waits for the device: tune->sweep_rounds > 0 (a fixed number of
+ * tile rounds, then the queue phase), or a negative sweep_rounds with
+ * tail_rounds > 0 (rounds, then the tile queue). */
 typedef struct mr_graph mr_graph;
 int mr_batch_graph_create(const mr_tile *tiles, int32_t n, mr_dtype t, int conn, void *ws,
                           size_t ws_bytes, const mr_tune *tune, mr_graph **out);
 int mr_graph_launch(mr_graph *g, void *stream);
 void mr_graph_destroy(mr_graph *g);
 
-/* Autotuner: times candidate tunings (sweep rounds before the queue phase,
- * sweep cap per tile visit) of mr_batch on this batch and writes the fastest
- * to *out. The tiles' data are restored afterwards. ws must hold
+/* Autotuner: times candidate tunings (sweep rounds before the queue phase or
+ * the tile queue, sweep cap per tile visit) of mr_batch on this batch and
+ * writes the fastest to *out. The tiles' data are restored afterwards. ws must hold
  * mr_autotune_workspace_bytes bytes (the batch workspace plus a backup of
  * the data). Waits for `stream`. */
 size_t mr_autotune_workspace_bytes(const mr_tile *tiles, int32_t n, mr_dtype t, int conn);
@@ -244,19 +255,20 @@ int mr_read_counters(const void *ws, mr_counters *out, void *stream);
 
 /* Tile visits per round of the last call that used a workspace: out[i] is
  * the number of 64 x 64 tiles visited in round i + 1, and out[rounds] the
- * number of tiles the seed pass started from (0 when the rounds converged).
+ * number of tiles handed on to the seed pass or the tile queue (0 when the
+ * rounds converged).
  * Writes min(cap, rounds + 1) entries, sets *n_rounds. Waits for `stream`.
  * Errors: MR_EINVAL (null pointer, negative cap), MR_EHIP. */
 int mr_read_round_tiles(const void *ws, uint32_t *out, int32_t cap, int32_t *n_rounds,
                         void *stream);
 
 /* Per-launch device timing (measurement support). While enabled, every
- * tile-round, seed and queue kernel that a call on this thread enqueues is
- * bracketed by two HIP events recorded on the call's stream; the records
- * accumulate until collected. The events carry no system-scope fence (no
+ * tile-round, seed, queue and tile-queue kernel that a call on this thread
+ * enqueues is bracketed by two HIP events recorded on the call's stream; the
+ * records accumulate until collected. The events carry no system-scope fence (no
  * cache writeback between launches); each still adds a marker to the
  * stream, about 2 us per event on MI355X. */
-enum { MR_K_TILE_ROUND = 0, MR_K_SEED = 1, MR_K_QUEUE = 2 };
+enum { MR_K_TILE_ROUND = 0, MR_K_SEED = 1, MR_K_QUEUE = 2, MR_K_TILE_QUEUE = 3 };
 typedef struct {
     int32_t kind;  /* MR_K_* */
     int32_t round; /* tile round number (MR_K_TILE_ROUND), else 0 */

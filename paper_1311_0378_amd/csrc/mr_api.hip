@@ -40,6 +40,10 @@ uint64_t next_pow2(uint64_t v) {
 // Spin budget of an idle queue wave before it gives up (a watchdog: the
 // queue always drains long before this on a working device).
 constexpr unsigned long long SPIN_CAP = 1ull << 16;
+// The tile queue's watchdog: microseconds without any new ring entry after
+// which a waiting wave gives up (on a working device entries come every few
+// microseconds until the queue drains).
+constexpr unsigned long long TILE_QUEUE_WAIT_US = 2000000ull;
 
 
 
@@ -90,6 +94,8 @@ int check_tune(const mr_tune *tn) {
         return fail(MR_EINVAL, "tune.persistent_blocks must be >= 0");
     if (tn->converge_rounds < 0 || tn->converge_rounds > MAX_ROUNDS)
         return fail(MR_EINVAL, "tune.converge_rounds must be in 0..%d", MAX_ROUNDS);
+    if (tn->tail_rounds < 0 || tn->tail_rounds > MAX_ROUNDS)
+        return fail(MR_EINVAL, "tune.tail_rounds must be in 0..%d", MAX_ROUNDS);
     return MR_OK;
 }
 
@@ -260,6 +266,30 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
             return hip_fail(e, "store");
         const int rc = queue_phase(round);
         if (rc != MR_OK) return rc;
+    } else if (tn.tail_rounds > 0) {
+        // converge mode with the tile queue: a fixed number of rounds, then
+        // the queue takes every tile still listed and runs to the fixed point
+        for (round = 2; round <= (uint32_t)tn.tail_rounds; ++round) {
+            {
+                LaunchTimer lt(s, MR_K_TILE_ROUND, (int32_t)round);
+                e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl, round,
+                                      tn.max_sweeps, grid, s, op_all);
+            }
+            if (e != hipSuccess) return hip_fail(e, "tile round");
+        }
+        if ((e = launch_store_u64(&ctrl->rounds, (unsigned long long)tn.tail_rounds, s)) !=
+            hipSuccess)
+            return hip_fail(e, "store");
+        if ((e = launch_clear_u32(qflag, L.n_tiles, 0u, s)) != hipSuccess ||
+            (e = launch_clear_u32(ring, (int64_t)L.ring_cap, Q_EMPTY, s)) != hipSuccess)
+            return hip_fail(e, "clear");
+        {
+            LaunchTimer lt(s, MR_K_TILE_QUEUE, 0);
+            e = launch_tile_queue(tbytes, conn, imgs, L.n_tiles, lists, (uint32_t)tn.tail_rounds + 1,
+                                  ctrl, qflag, ring, L.ring_cap, tn.max_sweeps, grid,
+                                  TILE_QUEUE_WAIT_US, s, op_all);
+        }
+        if (e != hipSuccess) return hip_fail(e, "tile queue");
     } else {
         // converge mode: rounds until a round leaves no dirty tile, polling
         // every few rounds
@@ -457,6 +487,7 @@ void mr_default_tune(mr_tune *out) {
     out->max_sweeps = 16;
     out->persistent_blocks = 0;
     out->converge_rounds = 0;
+    out->tail_rounds = 8;
 }
 
 size_t mr_workspace_bytes(int op, int64_t H, int64_t W, mr_dtype t, int conn, const mr_tune *tune) {
@@ -499,9 +530,10 @@ int mr_batch_graph_create(const mr_tile *tiles, int32_t n, mr_dtype t, int conn,
     g_err.clear();
     if (!out) return fail(MR_EINVAL, "null output handle");
     *out = nullptr;
-    if (!tune || tune->sweep_rounds <= 0)
-        return fail(MR_EINVAL, "a graph needs tune->sweep_rounds > 0 (the converge mode waits "
-                               "on the host)");
+    if (!tune || (tune->sweep_rounds <= 0 && tune->tail_rounds <= 0))
+        return fail(MR_EINVAL, "a graph needs tune->sweep_rounds > 0 or tune->tail_rounds > 0 "
+                               "(the converge mode without the tile queue waits on the host)");
+    if (check_tune(tune) != MR_OK) return MR_EINVAL;
     hipStream_t s = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(e, "stream");
@@ -584,8 +616,11 @@ int mr_autotune(const mr_tile *tiles, int32_t n, mr_dtype t, int conn, void *ws,
     };
     hipError_t e = copy_all(true);
     if (e != hipSuccess) return hip_fail(e, "backup");
-    static const int cand[][2] = {{-1, 16}, {-1, 3}, {4, 16}, {8, 16}, {12, 16}, {16, 16},
-                                  {24, 16}, {32, 16}, {48, 16}, {16, 3}};
+    // {sweep_rounds, max_sweeps, tail_rounds}
+    static const int cand[][3] = {{-1, 16, 0}, {-1, 3, 0}, {-1, 16, 4}, {-1, 16, 6},
+                                  {-1, 16, 8}, {-1, 16, 12}, {4, 16, 0}, {8, 16, 0},
+                                  {12, 16, 0}, {16, 16, 0}, {24, 16, 0}, {32, 16, 0},
+                                  {48, 16, 0}, {16, 3, 0}};
     hipEvent_t a = nullptr, b = nullptr;
     if ((e = hipEventCreate(&a)) != hipSuccess || (e = hipEventCreate(&b)) != hipSuccess)
         return hip_fail(e, "event");
@@ -599,6 +634,7 @@ int mr_autotune(const mr_tile *tiles, int32_t n, mr_dtype t, int conn, void *ws,
         mr_default_tune(&tn);
         tn.sweep_rounds = c[0];
         tn.max_sweeps = c[1];
+        tn.tail_rounds = c[2];
         float t_best = 1e30f;
         for (int rep = 0; rep < 2 && rc == MR_OK; ++rep) {
             if ((e = copy_all(false)) != hipSuccess) { rc = hip_fail(e, "restore"); break; }
@@ -644,9 +680,10 @@ int mr_read_counters(const void *ws, mr_counters *out, void *stream) {
         c.cas_retries += h.cas[i];
         c.overflows += h.ovf[i];
         c.sweeps += h.iters[i];
+        c.tiles += h.tiles[i]; // tile-queue visits
     }
     *out = c;
-    if (h.watchdog) return fail(MR_EHIP, "a queue workgroup hit its spin cap");
+    if (h.watchdog) return fail(MR_EHIP, "a queue or tile-queue workgroup hit its spin cap");
     return MR_OK;
 }
 

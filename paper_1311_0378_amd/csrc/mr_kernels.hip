@@ -132,9 +132,13 @@ __device__ __forceinline__ bool stage_ok(const void *p, int64_t pitch) {
 // writes (lane = row) and the column reads (lane = column) are both free of
 // bank conflicts.
 constexpr int SROW = 84;
+// Cache policy of loads that must see other compute units' stores at device
+// scope (sc1: not served from a compute unit's or a die's non-coherent cache).
+constexpr int CPOL_DEVICE = 16;
 constexpr int STAGE_BYTES = TS * SROW;
 static_assert(2 * STAGE_BYTES <= TS * (TS + 1) * 4, "the stage must fit in the transpose buffer");
 
+template <int CPOL = 0>
 __device__ __forceinline__ void stage_u8(__amdgpu_buffer_rsrc_t rs, int64_t gy0, int64_t H,
                                          uint32_t pitch, int64_t a, int lane, uint8_t *st) {
     typedef uint32_t v4u __attribute__((ext_vector_type(4)));
@@ -156,7 +160,7 @@ __device__ __forceinline__ void stage_u8(__amdgpu_buffer_rsrc_t rs, int64_t gy0,
         // below row 0 it reads the end of the previous row (outside pixels,
         // masked out later), in row 0 it is out of range
         const bool in = rowok && (gy > 0 || a + 16 * k >= 0);
-        v[k] = __builtin_amdgcn_raw_buffer_load_b128(rs, in ? off : 0xFFFFFFF0u, 0, 0);
+        v[k] = __builtin_amdgcn_raw_buffer_load_b128(rs, in ? off : 0xFFFFFFF0u, 0, CPOL);
         off += 16;
     }
     uint32_t *w = (uint32_t *)(st + ln * SROW);
@@ -167,6 +171,18 @@ __device__ __forceinline__ void stage_u8(__amdgpu_buffer_rsrc_t rs, int64_t gy0,
         w[4 * k + 2] = v[k].z;
         w[4 * k + 3] = v[k].w;
     }
+}
+
+// A working-image element; COH reads it device-coherent.
+template <typename T, bool COH>
+__device__ __forceinline__ T load_j(cgptr<T> p, uint32_t off) {
+    if (COH) return __hip_atomic_load((T *)(p + off), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return p[off];
+}
+template <typename T, bool COH>
+__device__ __forceinline__ void store_j(gptr<T> p, uint32_t off, T v) {
+    if (COH) __hip_atomic_store((T *)(p + off), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else p[off] = v;
 }
 
 // Load one 64 x 64 register tile. INITIAL builds the starting working image
@@ -186,7 +202,7 @@ __device__ __forceinline__ void stage_u8(__amdgpu_buffer_rsrc_t rs, int64_t gy0,
 // transposed mask IT (lane = row, register = column) and the loaded halo
 // columns JL, JR (lane = row) are read straight from the stage, and `it_done`
 // says so.
-template <typename T, bool FILL, bool INITIAL>
+template <typename T, bool FILL, bool INITIAL, bool COH = false>
 __device__ __forceinline__ void load_tile(const ImgDesc &d, int64_t gy0, int64_t gx0, int lane,
                                           uint32_t (&J)[TS], uint32_t (&I)[TS],
                                           uint32_t (&IT)[TS], uint32_t &JL, uint32_t &JR,
@@ -208,7 +224,8 @@ __device__ __forceinline__ void load_tile(const ImgDesc &d, int64_t gy0, int64_t
         stage_u8(plane_rsrc(d.I, (uint64_t)(H * d.pI)), gy0, H, (uint32_t)d.pI, a, lane, stI);
         const bool needJ = !(FILL && INITIAL);
         if (needJ)
-            stage_u8(plane_rsrc(d.J, (uint64_t)(H * d.pJ)), gy0, H, (uint32_t)d.pJ, a, lane, stJ);
+            stage_u8<COH ? CPOL_DEVICE : 0>(plane_rsrc(d.J, (uint64_t)(H * d.pJ)), gy0, H,
+                                            (uint32_t)d.pJ, a, lane, stJ);
         __syncthreads();
         if (inside) {
 #pragma unroll
@@ -269,7 +286,7 @@ __device__ __forceinline__ void load_tile(const ImgDesc &d, int64_t gy0, int64_t
         for (int r = 0; r < TS; ++r) {
             uint32_t iv = P::key(Ip[oI]);
             if (FILL) iv = P::KMAX - iv;
-            uint32_t jv = P::key(Jp[oJ]);
+            uint32_t jv = P::key(load_j<T, COH>(Jp, oJ));
             if (INITIAL) jv = min(jv, iv);
             J[r] = jv;
             I[r] = iv;
@@ -291,9 +308,9 @@ __device__ __forceinline__ void load_tile(const ImgDesc &d, int64_t gy0, int64_t
             if (FILL)
                 jv = (xedge || yc == 0 || yc == (uint32_t)(H - 1)) ? iv : 0u;
             else
-                jv = min(P::key(Jp[yc * (uint32_t)d.pJ + xc]), iv);
+                jv = min(P::key(load_j<T, COH>(Jp, yc * (uint32_t)d.pJ + xc)), iv);
         } else {
-            jv = P::key(Jp[yc * (uint32_t)d.pJ + xc]);
+            jv = P::key(load_j<T, COH>(Jp, yc * (uint32_t)d.pJ + xc));
         }
         jv = ok ? jv : 0u;
         iv = ok ? iv : 0u;
@@ -466,13 +483,98 @@ __device__ __forceinline__ void app_flush(Appender &a, int lane) {
     a.cnt = 0;
 }
 
+// ------------------------------------------------------------ frontier ring
+
+// The ring holds tile ids; a tile is in it at most once (its qflag is 1 from
+// enqueue until a wave finishes with it), so it never holds more than the
+// launch's tile count, and the capacity exceeds that plus the waves in flight.
+// FENCED: the entry is published with a device-scope release (data written
+// before it becomes visible with it); without, the caller has made its data
+// device-visible itself (device-coherent stores, waited for).
+template <bool FENCED = true>
+__device__ __forceinline__ void ring_push(Ctrl *ctrl, uint32_t *ring, uint64_t cap, uint32_t t) {
+    __hip_atomic_fetch_add(&ctrl->pending.v, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long pos =
+        __hip_atomic_fetch_add(&ctrl->q_tail.v, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t *slot = ring + (pos & (cap - 1));
+    // The capacity bound means the slot is already free; the wait is a guard,
+    // capped so that a broken bound cannot hang the device.
+    for (uint32_t spin = 0;
+         __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != Q_EMPTY; ++spin) {
+        if (spin > (1u << 22)) {
+            atomicAdd(&ctrl->watchdog, 1ull);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    if (FENCED)
+        __hip_atomic_store(slot, t, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        __hip_atomic_store(slot, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Claim the oldest ring entry; Q_EMPTY if the ring looks empty. FENCED
+// acquires at device scope what the pusher released.
+template <bool FENCED = true>
+__device__ __forceinline__ uint32_t ring_pop(Ctrl *ctrl, uint32_t *ring, uint64_t cap) {
+    unsigned long long h =
+        __hip_atomic_load(&ctrl->q_head.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (true) {
+        const unsigned long long tl =
+            __hip_atomic_load(&ctrl->q_tail.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (h >= tl) return Q_EMPTY;
+        if (__hip_atomic_compare_exchange_weak(&ctrl->q_head.v, &h, h + 1, __ATOMIC_RELAXED,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            break;
+    }
+    uint32_t *slot = ring + (h & (cap - 1));
+    uint32_t v;
+    // the producer that reserved this entry writes it right after reserving
+    for (uint32_t spin = 0;
+         (v = FENCED ? __hip_atomic_load(slot, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)
+                     : __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == Q_EMPTY;
+         ++spin) {
+        if (spin > (1u << 22)) {
+            atomicAdd(&ctrl->watchdog, 1ull);
+            return Q_EMPTY;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    __hip_atomic_store(slot, Q_EMPTY, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return v;
+}
+
+// Tile queue: a tile's state is 0 (idle), 1 (queued), 2 (a wave visits it)
+// or 3 (visited and marked again meanwhile: it goes back on the ring when the
+// visit ends). A mark sets bit 0; the one that finds the tile idle enqueues it.
+// Tile-queue visits read and write the working image device-coherent and
+// wait for their stores before any mark, so a visit that a mark leads to
+// sees the marking visit's pixels without cache-wide fences.
+
+// Wait until this wave's memory operations are done (its device-coherent
+// stores visible to every compute unit); also a compiler barrier.
+__device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+struct TailQ {
+    uint32_t *state;
+    uint32_t *ring;
+    uint64_t cap;
+    Ctrl *ctrl;
+};
+
+__device__ __forceinline__ void tail_mark(const TailQ &q, uint32_t t) {
+    const uint32_t prev =
+        __hip_atomic_fetch_or(q.state + t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev == 0u) ring_push<false>(q.ctrl, q.ring, q.cap, t);
+}
+
 // One visit of one tile: load, sweep to a local fixed point (or the cap),
-// store, and mark the neighbours whose halo changed.
-template <typename T, int CONN, bool FILL, bool INITIAL>
+// store, and mark the neighbours whose halo changed: onto the next round's
+// lists, or (TAIL) into the tile queue `tq`.
+template <typename T, int CONN, bool FILL, bool INITIAL, bool TAIL = false>
 __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane,
                                            uint32_t *__restrict__ flags, Appender &app,
                                            Ctrl *__restrict__ ctrl, uint32_t round, int max_iters,
-                                           uint32_t (*tb)[TS + 1]) {
+                                           uint32_t (*tb)[TS + 1], const TailQ *tq = nullptr) {
     using P = Pix<T>;
     constexpr bool first = INITIAL;
     const int64_t lt = t - d.tile_base;
@@ -482,7 +584,7 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
     uint32_t J[TS], I[TS], IT[TS];
     uint32_t JL, JR; // loaded halo columns 0 and TS-1, lane = row
     bool it_done = false;
-    load_tile<T, FILL, INITIAL>(d, gy0, (int64_t)tx * TI - 1, lane, J, I, IT, JL, JR,
+    load_tile<T, FILL, INITIAL, TAIL>(d, gy0, (int64_t)tx * TI - 1, lane, J, I, IT, JL, JR,
                                 (uint8_t *)tb, it_done);
     if (!it_done) {
         // (before the mask transpose: fewer registers live)
@@ -553,14 +655,14 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
 #pragma unroll
                 for (int r = 1; r < TS - 1; ++r) {
                     asm volatile("" : "+v"(off));
-                    Jw[off] = P::val(J[r]);
+                    store_j<T, TAIL>(Jw, off, P::val(J[r]));
                     off += (uint32_t)d.pJ;
                 }
             } else {
 #pragma unroll
                 for (int r = 1; r < TS - 1; ++r) {
                     asm volatile("" : "+v"(off));
-                    if (r <= rows) Jw[off] = P::val(J[r]);
+                    if (r <= rows) store_j<T, TAIL>(Jw, off, P::val(J[r]));
                     off += (uint32_t)d.pJ;
                 }
             }
@@ -612,6 +714,12 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
     }
     const int ny = ty + dy, nx = tx + dx;
     want = want && ny >= 0 && ny < d.nty && nx >= 0 && nx < d.ntx;
+    if (TAIL) {
+        // the visits these marks lead to must see this visit's stores
+        wait_vmem();
+        if (want) tail_mark(*tq, (uint32_t)(d.tile_base + (int64_t)ny * d.ntx + nx));
+        return;
+    }
     uint32_t nb = 0;
     bool fresh = false;
     if (want) {
@@ -680,55 +788,138 @@ __global__ __launch_bounds__(64, 2) void k_tile_round(Imgs imgs, int64_t n_tiles
     app_flush(app, lane);
 }
 
-// ------------------------------------------------------------ frontier ring
+// ------------------------------------------------------------- tile queue
 
-// The ring holds tile ids; a tile is in it at most once (its qflag is 1 from
-// enqueue until a wave finishes with it), so it never holds more than the
-// launch's tile count, and the capacity exceeds that plus the waves in flight.
-__device__ __forceinline__ void ring_push(Ctrl *ctrl, uint32_t *ring, uint64_t cap, uint32_t t) {
-    __hip_atomic_fetch_add(&ctrl->pending.v, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned long long pos =
-        __hip_atomic_fetch_add(&ctrl->q_tail.v, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t *slot = ring + (pos & (cap - 1));
-    // The capacity bound means the slot is already free; the wait is a guard,
-    // capped so that a broken bound cannot hang the device.
-    for (uint32_t spin = 0;
-         __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != Q_EMPTY; ++spin) {
-        if (spin > (1u << 22)) {
-            atomicAdd(&ctrl->watchdog, 1ull);
-            break;
-        }
-        __builtin_amdgcn_s_sleep(2);
+// Seeds the tile queue with band b's dirty list of `round` (block b).
+__global__ void k_tile_queue_seed(const uint32_t *__restrict__ lists,
+                                  const uint32_t *__restrict__ counts, int64_t n_tiles,
+                                  uint32_t round, uint32_t *__restrict__ state,
+                                  uint32_t *__restrict__ ring, uint64_t cap, Ctrl *ctrl) {
+    __shared__ unsigned long long base;
+    const int b = blockIdx.x;
+    const uint32_t n = counts[b];
+    if (n == 0) return;
+    const uint32_t *list = lists + (round & 1) * n_tiles + band_lo(n_tiles, b);
+    if (threadIdx.x == 0) {
+        base = atomicAdd(&ctrl->q_tail.v, (unsigned long long)n);
+        atomicAdd(&ctrl->pending.v, (unsigned long long)n);
     }
-    __hip_atomic_store(slot, t, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const uint32_t t = list[i];
+        state[t] = 1u;
+        ring[(base + i) & (cap - 1)] = t;
+    }
 }
 
-// Claim the oldest ring entry; Q_EMPTY if the ring looks empty.
-__device__ __forceinline__ uint32_t ring_pop(Ctrl *ctrl, uint32_t *ring, uint64_t cap) {
-    unsigned long long h =
-        __hip_atomic_load(&ctrl->q_head.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// The tile queue (the regular phase without rounds): each wave takes a tile
+// off the ring, visits it like a tile round does, and marks the neighbours
+// straight into the ring, so a chain of dependent tiles costs one visit per
+// link instead of one round. A wave takes a ticket (the next ring position)
+// and waits for that entry, so no two waves contend for an entry. The wave
+// that retires the last queued-or-running tile writes a stop entry for every
+// wave. A spin cap turns a stall into an error (watchdog) instead of a hang.
+constexpr uint32_t Q_STOP = 0xFFFFFFFEu;
+
+template <typename T, int CONN, int V>
+__global__ __launch_bounds__(64, 2) void k_tile_queue(Imgs imgs, Ctrl *__restrict__ ctrl,
+                                                      uint32_t *__restrict__ state,
+                                                      uint32_t *__restrict__ ring, uint64_t cap,
+                                                      int max_iters,
+                                                      unsigned long long spin_cap) {
+    __shared__ uint32_t tb[TS][TS + 1];
+    const int lane = threadIdx.x;
+    const TailQ tq{state, ring, cap, ctrl};
+    Appender app{nullptr, 0, nullptr, nullptr, 0}; // unused: marks go to the ring
+    unsigned long long visits = 0;
+    // nothing seeded: no wave will ever retire a tile and write the stops
+    if (__hip_atomic_load(&ctrl->pending.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+        return;
     while (true) {
-        const unsigned long long tl =
-            __hip_atomic_load(&ctrl->q_tail.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (h >= tl) return Q_EMPTY;
-        if (__hip_atomic_compare_exchange_weak(&ctrl->q_head.v, &h, h + 1, __ATOMIC_RELAXED,
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-            break;
-    }
-    uint32_t *slot = ring + (h & (cap - 1));
-    uint32_t v;
-    // the producer that reserved this entry writes it right after reserving
-    for (uint32_t spin = 0;
-         (v = __hip_atomic_load(slot, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) == Q_EMPTY;
-         ++spin) {
-        if (spin > (1u << 22)) {
-            atomicAdd(&ctrl->watchdog, 1ull);
-            return Q_EMPTY;
+        uint32_t t = Q_EMPTY;
+        if (lane == 0) {
+            const unsigned long long h = __hip_atomic_fetch_add(&ctrl->q_head.v, 1ull,
+                                                                __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_AGENT);
+            uint32_t *slot = ring + (h & (cap - 1));
+            // An entry can legitimately take as long as the whole queue run
+            // (a long chain of tiles), so the watchdog fires only when no
+            // entry at all was pushed for spin_cap microseconds (100 MHz
+            // constant clock).
+            unsigned long long t0 = wall_clock64(), seen = h;
+            for (unsigned long long spin = 0;; ++spin) {
+                t = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (t != Q_EMPTY) break;
+                if ((spin & 63) == 63 && wall_clock64() - t0 > spin_cap * 100ull) {
+                    const unsigned long long tail = __hip_atomic_load(
+                        &ctrl->q_tail.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (tail != seen) { // progress: wait on
+                        seen = tail;
+                        t0 = wall_clock64();
+                        continue;
+                    }
+                    atomicAdd(&ctrl->watchdog, 1ull);
+                    t = Q_STOP;
+                    break;
+                }
+                if (spin < 32)
+                    __builtin_amdgcn_s_sleep(1);
+                else
+                    __builtin_amdgcn_s_sleep(8);
+            }
+            if (t != Q_STOP)
+                __hip_atomic_store(slot, Q_EMPTY, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        __builtin_amdgcn_s_sleep(1);
+        t = __shfl(t, 0);
+        if (t == Q_STOP) break;
+        // queued -> visited, performed before any pixel is read: a mark that
+        // comes later finds state 2 and gets the tile visited again, one that
+        // came earlier had its stores done before it
+        if (lane == 0)
+            (void)__hip_atomic_exchange(state + t, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        wait_vmem();
+        const ImgDesc d = load_desc(imgs, t);
+        if (!d.done) {
+            ++visits;
+            if (V >= 0) {
+                visit_tile<T, CONN, (V >> 1) & 1, false, true>(d, t, lane, nullptr, app, ctrl, 0,
+                                                               max_iters, tb, &tq);
+            } else if (d.op == MR_OP_FILL) {
+                visit_tile<T, CONN, true, false, true>(d, t, lane, nullptr, app, ctrl, 0,
+                                                       max_iters, tb, &tq);
+            } else {
+                visit_tile<T, CONN, false, false, true>(d, t, lane, nullptr, app, ctrl, 0,
+                                                        max_iters, tb, &tq);
+            }
+        }
+        wait_vmem();
+        if (lane == 0) {
+            uint32_t expect = 2u;
+            if (!__hip_atomic_compare_exchange_strong(state + t, &expect, 0u, __ATOMIC_RELAXED,
+                                                      __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT)) {
+                // marked while it was visited (state 3): queue it again
+                __hip_atomic_store(state + t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ring_push<false>(ctrl, ring, cap, t);
+            }
+            wait_vmem();
+            const unsigned long long left = __hip_atomic_fetch_add(
+                &ctrl->pending.v, (unsigned long long)-1ll, __ATOMIC_RELAXED,
+                __HIP_MEMORY_SCOPE_AGENT);
+            if (left == 1) {
+                // the last one: every wave holds at most one ticket past the
+                // last entry, so gridDim.x stops reach them all
+                const unsigned long long base = __hip_atomic_fetch_add(
+                    &ctrl->q_tail.v, (unsigned long long)gridDim.x, __ATOMIC_RELAXED,
+                    __HIP_MEMORY_SCOPE_AGENT);
+                for (unsigned k = 0; k < gridDim.x; ++k)
+                    __hip_atomic_store(ring + ((base + k) & (cap - 1)), Q_STOP, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
     }
-    __hip_atomic_store(slot, Q_EMPTY, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return v;
+    if (lane == 0 && visits)
+        atomicAdd(&ctrl->tiles[(blockIdx.x) & (NCNT - 1)], visits);
 }
 
 // ------------------------------------------------------------------- seeds
@@ -1151,6 +1342,40 @@ hipError_t launch_tile_round(int tbytes, int conn, const Imgs &imgs, int64_t n_t
     return tile_round_any(tbytes, conn, imgs, n_tiles, flags, lists, ctrl->round_tiles[round],
                           ctrl->round_tiles[round + 1], round == 1, ctrl, round, max_iters, grid,
                           s, variant);
+}
+
+template <typename T, int CONN, int V>
+static hipError_t tile_queue_v(const Imgs &imgs, Ctrl *ctrl, uint32_t *state, uint32_t *ring,
+                               uint64_t cap, int max_iters, int grid, unsigned long long spin_cap,
+                               hipStream_t s) {
+    hipLaunchKernelGGL((k_tile_queue<T, CONN, V>), dim3((unsigned)grid), dim3(64), 0, s, imgs,
+                       ctrl, state, ring, cap, max_iters, spin_cap);
+    return hipGetLastError();
+}
+template <typename T, int CONN>
+static hipError_t tile_queue_t(const Imgs &imgs, Ctrl *ctrl, uint32_t *state, uint32_t *ring,
+                               uint64_t cap, int max_iters, int grid, unsigned long long spin_cap,
+                               hipStream_t s, int op_all) {
+    if (op_all == MR_OP_RECON)
+        return tile_queue_v<T, CONN, 0>(imgs, ctrl, state, ring, cap, max_iters, grid, spin_cap, s);
+    if (op_all == MR_OP_FILL)
+        return tile_queue_v<T, CONN, 2>(imgs, ctrl, state, ring, cap, max_iters, grid, spin_cap, s);
+    return tile_queue_v<T, CONN, -1>(imgs, ctrl, state, ring, cap, max_iters, grid, spin_cap, s);
+}
+hipError_t launch_tile_queue(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
+                             const uint32_t *lists, uint32_t round, Ctrl *ctrl, uint32_t *state,
+                             uint32_t *ring, uint64_t cap, int max_iters, int grid,
+                             unsigned long long spin_cap, hipStream_t s, int op_all) {
+    if (!ctrl || round > (uint32_t)MAX_ROUNDS + 1 || grid < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_tile_queue_seed, dim3(NBANDS), dim3(256), 0, s, lists,
+                       ctrl->round_tiles[round], n_tiles, round, state, ring, cap, ctrl);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (tbytes == 1)
+        return conn == 8 ? tile_queue_t<uint8_t, 8>(imgs, ctrl, state, ring, cap, max_iters, grid, spin_cap, s, op_all)
+                         : tile_queue_t<uint8_t, 4>(imgs, ctrl, state, ring, cap, max_iters, grid, spin_cap, s, op_all);
+    return conn == 8 ? tile_queue_t<int32_t, 8>(imgs, ctrl, state, ring, cap, max_iters, grid, spin_cap, s, op_all)
+                     : tile_queue_t<int32_t, 4>(imgs, ctrl, state, ring, cap, max_iters, grid, spin_cap, s, op_all);
 }
 
 template <typename T, int CONN>

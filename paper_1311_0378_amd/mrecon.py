@@ -32,7 +32,8 @@ class MrError(RuntimeError):
 
 class Tune(ctypes.Structure):
     _fields_ = [("sweep_rounds", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
-                ("persistent_blocks", ctypes.c_int32), ("converge_rounds", ctypes.c_int32)]
+                ("persistent_blocks", ctypes.c_int32), ("converge_rounds", ctypes.c_int32),
+                ("tail_rounds", ctypes.c_int32)]
 
 
 class Tile(ctypes.Structure):
@@ -52,7 +53,7 @@ class LaunchTime(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("round", ctypes.c_int32), ("ms", ctypes.c_float)]
 
 
-KIND_NAMES = {0: "tile_round", 1: "seed", 2: "queue"}
+KIND_NAMES = {0: "tile_round", 1: "seed", 2: "queue", 3: "tile_queue"}
 
 
 class Counters(ctypes.Structure):
@@ -269,7 +270,7 @@ def batch(items, conn: int = 8, tune=None, workspace: torch.Tensor | None = None
 
 class BatchGraph:
     """A batch captured into a HIP graph; ``launch()`` replays it on the same
-    buffers. Needs a tune with sweep_rounds > 0."""
+    buffers. Needs a tune with sweep_rounds > 0, or with tail_rounds > 0."""
 
     def __init__(self, items, conn: int = 8, tune=None, workspace: torch.Tensor | None = None):
         arr, n, t, _ = make_tiles(items)

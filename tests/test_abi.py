@@ -26,6 +26,7 @@ def test_abi_version(L):
 def test_default_tune():
     t = mrecon.default_tune()
     assert t.sweep_rounds != 0 and 1 <= t.max_sweeps <= 1024 and t.converge_rounds == 0
+    assert 0 <= t.tail_rounds <= 1000
 
 
 def test_workspace_bytes_grows_with_size():
@@ -78,7 +79,8 @@ def test_recon_rejects(L, kw, code):
 @pytest.mark.parametrize("field,value", [("sweep_rounds", 0), ("max_sweeps", 0),
                                          ("max_sweeps", 5000), ("persistent_blocks", -1),
                                          ("converge_rounds", -1),
-                                         ("converge_rounds", 1001)])
+                                         ("converge_rounds", 1001), ("tail_rounds", -1),
+                                         ("tail_rounds", 1001)])
 def test_recon_rejects_bad_tune(L, field, value):
     t = mrecon.default_tune()
     setattr(t, field, value)
@@ -139,6 +141,7 @@ def test_graph_needs_fixed_rounds(L):
     h = ctypes.c_void_p()
     t = mrecon.default_tune()
     t.sweep_rounds = -1
+    t.tail_rounds = 0
     rc = L.mr_batch_graph_create(one, 1, 1, 8, ctypes.c_void_p(FAKE), 1 << 30, ctypes.byref(t),
                                  ctypes.byref(h))
     assert rc == mrecon.MR_EINVAL and not h.value

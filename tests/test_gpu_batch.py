@@ -48,8 +48,8 @@ def to_items(jobs, pad=0):
 
 @pytest.mark.parametrize("dt", ["u8", "i32"])
 @pytest.mark.parametrize("conn", [4, 8])
-@pytest.mark.parametrize("tune", [None, dict(sweep_rounds=3), dict(sweep_rounds=1, max_sweeps=1)],
-                         ids=str)
+@pytest.mark.parametrize("tune", [None, dict(sweep_rounds=3), dict(sweep_rounds=1, max_sweeps=1),
+                                  dict(sweep_rounds=-1, tail_rounds=2)], ids=str)
 def test_batch_matches_oracle(dt, conn, tune):
     jobs = make_batch(24, dt, seed=conn)
     items = to_items(jobs)
@@ -74,12 +74,14 @@ def test_batch_equals_single_calls():
         assert torch.equal(s, d)
 
 
-def test_graph_replays():
+@pytest.mark.parametrize("tune", [dict(sweep_rounds=6), dict(sweep_rounds=-1, tail_rounds=3)],
+                         ids=["rounds+queue", "rounds+tile_queue"])
+def test_graph_replays(tune):
     jobs = make_batch(16, "u8", seed=3)
     wants = [oracle_of(j, 8) for j in jobs]
     items = to_items(jobs)
     src = [d.clone() for d, _, _ in items]
-    g = mrecon.BatchGraph(items, 8, tune=dict(sweep_rounds=6))
+    g = mrecon.BatchGraph(items, 8, tune=tune)
     for rep in range(3):
         for (d, _, _), s in zip(items, src):
             d.copy_(s)  # eager work between replays

@@ -131,7 +131,7 @@ def test_batch_512_tiles_full():
     items = [(w, k, mrecon.MR_OP_RECON) for w, k in zip(work, msk)]
     tune = mrecon.autotune(items, 8)
     ws = mrecon.alloc_workspace(mrecon.batch_workspace_bytes(items, 8, tune), DEV)
-    if tune.sweep_rounds > 0:
+    if tune.sweep_rounds > 0 or tune.tail_rounds > 0:
         g = mrecon.BatchGraph(items, 8, tune, ws)
         g.launch()
         torch.cuda.synchronize()

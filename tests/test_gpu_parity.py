@@ -26,7 +26,8 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 TUNES = [None, dict(sweep_rounds=1, max_sweeps=1), dict(sweep_rounds=2, max_sweeps=3),
          dict(sweep_rounds=-1), dict(sweep_rounds=8, persistent_blocks=3),
-         dict(sweep_rounds=-1, converge_rounds=2)]
+         dict(sweep_rounds=-1, converge_rounds=2), dict(sweep_rounds=-1, tail_rounds=1),
+         dict(sweep_rounds=-1, tail_rounds=2, max_sweeps=1)]
 
 
 def check(got, want):
@@ -96,9 +97,25 @@ def test_serpentine_queue_heavy(conn):
     # the last tunes stop the tile rounds early and leave the long corridor to
     # the seed pass and the queue phase
     for tune in (None, dict(sweep_rounds=1, max_sweeps=1), dict(sweep_rounds=-1, converge_rounds=1),
-                 dict(sweep_rounds=-1, converge_rounds=5)):
+                 dict(sweep_rounds=-1, converge_rounds=5), dict(sweep_rounds=-1, tail_rounds=1),
+                 dict(sweep_rounds=-1, tail_rounds=1, max_sweeps=1)):
         got, c = gpu_recon(marker, mask, conn, tune=tune, counters=True)
         check(got, want)
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+@pytest.mark.parametrize("tail", [1, 3])
+def test_serpentine_tile_queue(conn, tail):
+    """A corridor through 10 x 12 tiles: the tile queue carries the chain from
+    tile to tile, requeueing tiles that are marked while they are visited."""
+    from test_oracle_pins import serpentine
+    marker, mask = serpentine(600, 700, 11)
+    want, _ = oracle.recon_dilate(marker, mask, conn)
+    for ms in (16, 1):
+        got, c = gpu_recon(marker, mask, conn, tune=dict(sweep_rounds=-1, tail_rounds=tail,
+                                                          max_sweeps=ms), counters=True)
+        check(got, want)
+        assert c["rounds"] == tail and c["tiles"] > 0
 
 
 @pytest.mark.parametrize("W", [1, 5, 17, 62, 63, 77, 130])

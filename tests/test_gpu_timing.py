@@ -14,8 +14,10 @@ from gpu_util import gpu_recon  # noqa: E402
 from paper_1311_0378_amd import mrecon  # noqa: E402
 
 
-@pytest.mark.parametrize("tune", [None, dict(sweep_rounds=2, max_sweeps=2)],
-                         ids=["converge", "rounds+queue"])
+@pytest.mark.parametrize("tune", [dict(sweep_rounds=-1, tail_rounds=0),
+                                  dict(sweep_rounds=2, max_sweeps=2),
+                                  dict(sweep_rounds=-1, tail_rounds=2), None],
+                         ids=["converge", "rounds+queue", "rounds+tile_queue", "default"])
 def test_timing_records_every_launch(tune):
     marker, mask = synth.make_tile(700, 900, 130, 5, "u8", 0.0)
     mrecon.timing_enable(True)
@@ -27,7 +29,11 @@ def test_timing_records_every_launch(tune):
     tiles = [r for r in recs if r[0] == "tile_round"]
     assert [r[1] for r in tiles] == list(range(1, c["rounds"] + 1))
     kinds = [r[0] for r in recs]
-    if tune is None:
+    if tune is None or tune.get("tail_rounds", 0) > 0:
+        # rounds, then the tile queue (the default: 8 rounds)
+        assert c["rounds"] == (tune or {}).get("tail_rounds", 8)
+        assert kinds == ["tile_round"] * c["rounds"] + ["tile_queue"]
+    elif tune["sweep_rounds"] < 0:
         assert kinds == ["tile_round"] * c["rounds"]
     else:
         assert kinds == ["tile_round"] * 2 + ["seed", "queue"]
