@@ -70,11 +70,15 @@ def cpu_model() -> str:
 
 
 def kernel_source_hash() -> str:
-    """Hash of the sources that define the tile-round kernel."""
+    """Hash of the code (line comments and blank lines dropped) of the sources
+    that define the tile-round kernel."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1311_0378_amd", "csrc")
     for f in ("mr_internal.h", "mr_kernels.hip"):
-        h.update(open(os.path.join(csrc, f), "rb").read())
+        for line in open(os.path.join(csrc, f), encoding="utf-8"):
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

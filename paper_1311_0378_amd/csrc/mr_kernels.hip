@@ -5,15 +5,18 @@
 // is the identity of max and stands for "no pixel" outside the image. The
 // bitwise complement used by fill-holes is KMAX - key in key space.
 //
-// Three kernels carry the propagation (Algorithm 1 split into the regular and
+// Four kernels carry the propagation (Algorithm 1 split into the regular and
 // irregular phases of Sec. V-C.2):
 //  * k_tile_round -- the regular phase. One wave owns a 64 x 64 tile of keys
-//    held in registers (lane = column, register = row); the outer ring is a
-//    frozen halo. Down and up sweeps run along the registers with the
-//    diagonal neighbours taken from the adjacent lanes by DPP; the tile is
-//    transposed through LDS for the right and left sweeps. Sweeps repeat until
-//    the tile is stable, then the interior is stored and the tiles whose halo
-//    changed go on the next round's dirty list, which is all it visits.
+//    held in registers (lane = column, register = row); the outer ring is the
+//    halo. Down and up sweeps run along the registers with the diagonal
+//    neighbours taken from the adjacent lanes by DPP; the tile is transposed
+//    through LDS for the right and left sweeps. Sweeps repeat until the tile
+//    is stable, then the interior is stored and the neighbours whose halo the
+//    new border can still raise go on the next round's dirty list, which is
+//    all that round visits.
+//  * k_tile_queue -- the same visits without rounds: waves take tiles from a
+//    device ring and mark neighbours straight into it, until none is left.
 //  * k_seed -- one relaxation step over each tile still dirty after the last
 //    round; every raised pixel is compacted by wave ballot into the tile's row
 //    of the frontier bitmap, and the tile into the device frontier ring.
