@@ -37,13 +37,10 @@ uint64_t next_pow2(uint64_t v) {
     return p;
 }
 
-// Spin budget of an idle queue wave before it gives up (a watchdog: the
-// queue always drains long before this on a working device).
-constexpr unsigned long long SPIN_CAP = 1ull << 16;
-// The tile queue's watchdog: microseconds without any new ring entry after
-// which a waiting wave gives up (on a working device entries come every few
-// microseconds until the queue drains).
-constexpr unsigned long long TILE_QUEUE_WAIT_US = 2000000ull;
+// The watchdog of the queue phase and the tile queue: microseconds without
+// any new ring entry after which a waiting wave gives up (on a working device
+// entries come every few microseconds until the queue drains).
+constexpr unsigned long long QUEUE_WAIT_US = 2000000ull;
 
 
 
@@ -59,7 +56,7 @@ Layout layout_for(int64_t n_tiles, int64_t fill_plane_bytes, int64_t plane_pitch
                   int64_t n_imgs = 1) {
     Layout L;
     L.n_tiles = n_tiles;
-    L.ring_cap = next_pow2((uint64_t)n_tiles + 8192);
+    L.ring_cap = next_pow2((uint64_t)n_tiles + (uint64_t)RING_SLACK);
     size_t o = align_up(sizeof(Ctrl), 256);
     L.off_desc = o;
     o = align_up(o + sizeof(ImgDesc) * (size_t)n_imgs, 256);
@@ -247,7 +244,7 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
         {
             LaunchTimer lt(s, MR_K_QUEUE, 0);
             e = launch_queue(tbytes, conn, imgs, ctrl, bitmap, qflag, ring, L.ring_cap, blocks,
-                             SPIN_CAP, s);
+                             QUEUE_WAIT_US, s);
         }
         if (e != hipSuccess) return hip_fail(e, "queue");
         return MR_OK;
@@ -287,7 +284,7 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
             LaunchTimer lt(s, MR_K_TILE_QUEUE, 0);
             e = launch_tile_queue(tbytes, conn, imgs, L.n_tiles, lists, (uint32_t)tn.tail_rounds + 1,
                                   ctrl, qflag, ring, L.ring_cap, tn.max_sweeps, grid,
-                                  TILE_QUEUE_WAIT_US, s, op_all);
+                                  QUEUE_WAIT_US, s, op_all);
         }
         if (e != hipSuccess) return hip_fail(e, "tile queue");
     } else {

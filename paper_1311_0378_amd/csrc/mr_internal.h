@@ -78,6 +78,10 @@ struct Imgs {
 };
 
 constexpr uint32_t Q_EMPTY = 0xFFFFFFFFu;
+// Ring slots beyond the tile count: the ring's consumers (waves of the queue
+// phase or the tile queue) hold at most one ticket each past the last entry,
+// and their launches are capped to this many waves.
+constexpr int64_t RING_SLACK = 8192;
 
 // The calling thread's error message (mr_last_error), shared by all host
 // translation units.
@@ -108,14 +112,14 @@ hipError_t launch_seed(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
 hipError_t launch_clear_u64(uint64_t *p, int64_t n, hipStream_t s);
 hipError_t launch_queue(int tbytes, int conn, const Imgs &imgs, Ctrl *ctrl, uint64_t *bitmap,
                         uint32_t *qflag, uint32_t *ring, uint64_t cap, int blocks,
-                        unsigned long long spin_cap, hipStream_t s);
+                        unsigned long long wait_us, hipStream_t s);
 // Tile queue: seed it with every tile listed for `round` (state[t] = 1, ring
 // entries, pending), then visit tiles from it on a persistent grid until none
 // is queued or running. state[] and ring[] start cleared (0, Q_EMPTY).
 hipError_t launch_tile_queue(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
                              const uint32_t *lists, uint32_t round, Ctrl *ctrl, uint32_t *state,
                              uint32_t *ring, uint64_t cap, int max_iters, int grid,
-                             unsigned long long spin_cap, hipStream_t s, int op_all);
+                             unsigned long long wait_us, hipStream_t s, int op_all);
 hipError_t launch_fill_output(int tbytes, const Imgs &imgs, int64_t n_tiles, hipStream_t s,
                               int64_t t0 = 0);
 hipError_t launch_store_u64(unsigned long long *p, unsigned long long v, hipStream_t s);

@@ -23,7 +23,7 @@
 //  * k_queue -- persistent waves pop tiles from the ring, claim the set bits of
 //    the tile's bitmap and propagate each claimed pixel to its neighbours with
 //    atomic max updates; every raised neighbour is pushed back (bit set, its
-//    tile enqueued once). The waves leave when nothing is pending.
+//    tile enqueued once). The wave that retires the last entry stops them all.
 #include <algorithm>
 
 #include "mr_internal.h"
@@ -488,13 +488,13 @@ __device__ __forceinline__ void app_flush(Appender &a, int lane) {
 
 // ------------------------------------------------------------ frontier ring
 
-// The ring holds tile ids; a tile is in it at most once (its qflag is 1 from
-// enqueue until a wave finishes with it), so it never holds more than the
-// launch's tile count, and the capacity exceeds that plus the waves in flight.
-// FENCED: the entry is published with a device-scope release (data written
-// before it becomes visible with it); without, the caller has made its data
-// device-visible itself (device-coherent stores, waited for).
-template <bool FENCED = true>
+// The ring holds tile ids; a tile is in it at most once (the seed pass and
+// the queue phase: its qflag is 1 from enqueue until a wave finishes with
+// it; the tile queue: its state), so it never holds more than the launch's
+// tile count, and the capacity exceeds that plus one ticket per wave. The
+// pusher has made what the entry stands for visible first: device-scope
+// atomics it waited for, device-coherent stores it waited for, or stores of
+// an earlier launch.
 __device__ __forceinline__ void ring_push(Ctrl *ctrl, uint32_t *ring, uint64_t cap, uint32_t t) {
     __hip_atomic_fetch_add(&ctrl->pending.v, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned long long pos =
@@ -510,41 +510,7 @@ __device__ __forceinline__ void ring_push(Ctrl *ctrl, uint32_t *ring, uint64_t c
         }
         __builtin_amdgcn_s_sleep(2);
     }
-    if (FENCED)
-        __hip_atomic_store(slot, t, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    else
-        __hip_atomic_store(slot, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Claim the oldest ring entry; Q_EMPTY if the ring looks empty. FENCED
-// acquires at device scope what the pusher released.
-template <bool FENCED = true>
-__device__ __forceinline__ uint32_t ring_pop(Ctrl *ctrl, uint32_t *ring, uint64_t cap) {
-    unsigned long long h =
-        __hip_atomic_load(&ctrl->q_head.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    while (true) {
-        const unsigned long long tl =
-            __hip_atomic_load(&ctrl->q_tail.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (h >= tl) return Q_EMPTY;
-        if (__hip_atomic_compare_exchange_weak(&ctrl->q_head.v, &h, h + 1, __ATOMIC_RELAXED,
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-            break;
-    }
-    uint32_t *slot = ring + (h & (cap - 1));
-    uint32_t v;
-    // the producer that reserved this entry writes it right after reserving
-    for (uint32_t spin = 0;
-         (v = FENCED ? __hip_atomic_load(slot, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)
-                     : __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == Q_EMPTY;
-         ++spin) {
-        if (spin > (1u << 22)) {
-            atomicAdd(&ctrl->watchdog, 1ull);
-            return Q_EMPTY;
-        }
-        __builtin_amdgcn_s_sleep(1);
-    }
-    __hip_atomic_store(slot, Q_EMPTY, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return v;
+    __hip_atomic_store(slot, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Tile queue: a tile's state is 0 (idle), 1 (queued), 2 (a wave visits it)
@@ -557,6 +523,59 @@ __device__ __forceinline__ uint32_t ring_pop(Ctrl *ctrl, uint32_t *ring, uint64_
 // Wait until this wave's memory operations are done (its device-coherent
 // stores visible to every compute unit); also a compiler barrier.
 __device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Ring consumers take a ticket (the next position) and wait for that entry,
+// so no two waves contend for one. An entry can legitimately take as long as
+// the whole run (a long chain), so the watchdog fires only when no entry at
+// all was pushed for wait_us microseconds (100 MHz constant clock): then the
+// wave gives up with Q_STOP. One lane per wave calls it.
+constexpr uint32_t Q_STOP = 0xFFFFFFFEu;
+
+__device__ __forceinline__ uint32_t ring_take(Ctrl *ctrl, uint32_t *ring, uint64_t cap,
+                                              unsigned long long wait_us) {
+    const unsigned long long h =
+        __hip_atomic_fetch_add(&ctrl->q_head.v, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t *slot = ring + (h & (cap - 1));
+    unsigned long long t0 = wall_clock64(), seen = h;
+    uint32_t t;
+    for (unsigned long long spin = 0;; ++spin) {
+        t = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (t != Q_EMPTY) break;
+        if ((spin & 63) == 63 && wall_clock64() - t0 > wait_us * 100ull) {
+            const unsigned long long tail =
+                __hip_atomic_load(&ctrl->q_tail.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (tail != seen) { // progress: wait on
+                seen = tail;
+                t0 = wall_clock64();
+                continue;
+            }
+            atomicAdd(&ctrl->watchdog, 1ull);
+            return Q_STOP;
+        }
+        if (spin < 32)
+            __builtin_amdgcn_s_sleep(1);
+        else
+            __builtin_amdgcn_s_sleep(8);
+    }
+    if (t != Q_STOP)
+        __hip_atomic_store(slot, Q_EMPTY, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return t;
+}
+
+// Retire one processed entry; the wave that retires the last one writes a
+// stop entry for each of the launch's `waves` waves (each holds at most one
+// ticket past the last entry).
+__device__ __forceinline__ void ring_retire(Ctrl *ctrl, uint32_t *ring, uint64_t cap,
+                                            unsigned waves) {
+    const unsigned long long left = __hip_atomic_fetch_add(
+        &ctrl->pending.v, (unsigned long long)-1ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (left != 1) return;
+    const unsigned long long base = __hip_atomic_fetch_add(
+        &ctrl->q_tail.v, (unsigned long long)waves, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (unsigned k = 0; k < waves; ++k)
+        __hip_atomic_store(ring + ((base + k) & (cap - 1)), Q_STOP, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
 struct TailQ {
     uint32_t *state;
     uint32_t *ring;
@@ -567,7 +586,7 @@ struct TailQ {
 __device__ __forceinline__ void tail_mark(const TailQ &q, uint32_t t) {
     const uint32_t prev =
         __hip_atomic_fetch_or(q.state + t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (prev == 0u) ring_push<false>(q.ctrl, q.ring, q.cap, t);
+    if (prev == 0u) ring_push(q.ctrl, q.ring, q.cap, t);
 }
 
 // One visit of one tile: load, sweep to a local fixed point (or the cap),
@@ -821,15 +840,14 @@ __global__ void k_tile_queue_seed(const uint32_t *__restrict__ lists,
 // link instead of one round. A wave takes a ticket (the next ring position)
 // and waits for that entry, so no two waves contend for an entry. The wave
 // that retires the last queued-or-running tile writes a stop entry for every
-// wave. A spin cap turns a stall into an error (watchdog) instead of a hang.
-constexpr uint32_t Q_STOP = 0xFFFFFFFEu;
+// wave. The watchdog (ring_take) turns a stall into an error instead of a hang.
 
 template <typename T, int CONN, int V>
 __global__ __launch_bounds__(64, 2) void k_tile_queue(Imgs imgs, Ctrl *__restrict__ ctrl,
                                                       uint32_t *__restrict__ state,
                                                       uint32_t *__restrict__ ring, uint64_t cap,
                                                       int max_iters,
-                                                      unsigned long long spin_cap) {
+                                                      unsigned long long wait_us) {
     __shared__ uint32_t tb[TS][TS + 1];
     const int lane = threadIdx.x;
     const TailQ tq{state, ring, cap, ctrl};
@@ -840,39 +858,7 @@ __global__ __launch_bounds__(64, 2) void k_tile_queue(Imgs imgs, Ctrl *__restric
         return;
     while (true) {
         uint32_t t = Q_EMPTY;
-        if (lane == 0) {
-            const unsigned long long h = __hip_atomic_fetch_add(&ctrl->q_head.v, 1ull,
-                                                                __ATOMIC_RELAXED,
-                                                                __HIP_MEMORY_SCOPE_AGENT);
-            uint32_t *slot = ring + (h & (cap - 1));
-            // An entry can legitimately take as long as the whole queue run
-            // (a long chain of tiles), so the watchdog fires only when no
-            // entry at all was pushed for spin_cap microseconds (100 MHz
-            // constant clock).
-            unsigned long long t0 = wall_clock64(), seen = h;
-            for (unsigned long long spin = 0;; ++spin) {
-                t = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (t != Q_EMPTY) break;
-                if ((spin & 63) == 63 && wall_clock64() - t0 > spin_cap * 100ull) {
-                    const unsigned long long tail = __hip_atomic_load(
-                        &ctrl->q_tail.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if (tail != seen) { // progress: wait on
-                        seen = tail;
-                        t0 = wall_clock64();
-                        continue;
-                    }
-                    atomicAdd(&ctrl->watchdog, 1ull);
-                    t = Q_STOP;
-                    break;
-                }
-                if (spin < 32)
-                    __builtin_amdgcn_s_sleep(1);
-                else
-                    __builtin_amdgcn_s_sleep(8);
-            }
-            if (t != Q_STOP)
-                __hip_atomic_store(slot, Q_EMPTY, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        if (lane == 0) t = ring_take(ctrl, ring, cap, wait_us);
         t = __shfl(t, 0);
         if (t == Q_STOP) break;
         // queued -> visited, performed before any pixel is read: a mark that
@@ -903,22 +889,10 @@ __global__ __launch_bounds__(64, 2) void k_tile_queue(Imgs imgs, Ctrl *__restric
                                                       __HIP_MEMORY_SCOPE_AGENT)) {
                 // marked while it was visited (state 3): queue it again
                 __hip_atomic_store(state + t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ring_push<false>(ctrl, ring, cap, t);
+                ring_push(ctrl, ring, cap, t);
             }
             wait_vmem();
-            const unsigned long long left = __hip_atomic_fetch_add(
-                &ctrl->pending.v, (unsigned long long)-1ll, __ATOMIC_RELAXED,
-                __HIP_MEMORY_SCOPE_AGENT);
-            if (left == 1) {
-                // the last one: every wave holds at most one ticket past the
-                // last entry, so gridDim.x stops reach them all
-                const unsigned long long base = __hip_atomic_fetch_add(
-                    &ctrl->q_tail.v, (unsigned long long)gridDim.x, __ATOMIC_RELAXED,
-                    __HIP_MEMORY_SCOPE_AGENT);
-                for (unsigned k = 0; k < gridDim.x; ++k)
-                    __hip_atomic_store(ring + ((base + k) & (cap - 1)), Q_STOP, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-            }
+            ring_retire(ctrl, ring, cap, gridDim.x);
         }
     }
     if (lane == 0 && visits)
@@ -970,6 +944,7 @@ __device__ __forceinline__ void seed_tile(const ImgDesc &d, int64_t t, int lane,
         qflag[t] = 1;
         __hip_atomic_fetch_add(&ctrl->seeds_total.v, (unsigned long long)nseed,
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // the queue runs in a later launch, which sees this one's stores
         ring_push(ctrl, ring, cap, (uint32_t)t);
     }
 }
@@ -1040,11 +1015,12 @@ __device__ __forceinline__ void relax_pixel(const ImgDesc &d, int64_t y, int64_t
         const int rq = (int)(yy - (int64_t)tyq * TI) + 1, lq = (int)(xx - (int64_t)txq * TI) + 1;
         const int64_t tq = d.tile_base + (int64_t)tyq * d.ntx + txq;
         const uint64_t bit = 1ull << lq;
-        const uint64_t old = __hip_atomic_fetch_or(bitmap + tq * TS + rq, bit, __ATOMIC_RELEASE,
+        // the raise above returned, so it is done before the bit is set
+        const uint64_t old = __hip_atomic_fetch_or(bitmap + tq * TS + rq, bit, __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_AGENT);
         ++npush;
         if (old & bit) continue;
-        if (__hip_atomic_exchange(qflag + tq, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 0)
+        if (__hip_atomic_exchange(qflag + tq, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
             ring_push(ctrl, ring, cap, (uint32_t)tq);
     }
 }
@@ -1054,35 +1030,25 @@ __global__ __launch_bounds__(64 * QWAVES) void k_queue(Imgs imgs, Ctrl *__restri
                                                        uint64_t *__restrict__ bitmap,
                                                        uint32_t *__restrict__ qflag,
                                                        uint32_t *__restrict__ ring, uint64_t cap,
-                                                       unsigned long long spin_cap) {
+                                                       unsigned long long wait_us) {
     __shared__ uint16_t list[QWAVES][LIST_CAP];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     uint16_t *mylist = list[w];
     uint32_t npush = 0, npop = 0;
-    unsigned long long retries = 0, idle = 0;
+    unsigned long long retries = 0;
     const int cslot = (int)((blockIdx.x * QWAVES + w) & (NCNT - 1));
+    // Every access that other waves' work depends on is a device-scope
+    // atomic (pixels, bitmap rows, queue flags, ring), each waited for where
+    // a later one must see it: no cache-wide fences. Nothing seeded: no wave
+    // would ever retire an entry and write the stops.
+    if (__hip_atomic_load(&ctrl->pending.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+        return;
 
     while (true) {
         uint32_t t = Q_EMPTY;
-        if (lane == 0) t = ring_pop(ctrl, ring, cap);
+        if (lane == 0) t = ring_take(ctrl, ring, cap, wait_us);
         t = __shfl(t, 0);
-        if (t == Q_EMPTY) {
-            unsigned long long pend = 0;
-            if (lane == 0)
-                pend = __hip_atomic_load(&ctrl->pending.v, __ATOMIC_ACQUIRE,
-                                         __HIP_MEMORY_SCOPE_AGENT);
-            pend = __shfl(pend, 0);
-            if (pend == 0) break;
-            if (++idle > spin_cap) {
-                if (lane == 0) atomicAdd(&ctrl->watchdog, 1ull);
-                break;
-            }
-            // back off so idle waves do not crowd the ring counters
-            const unsigned long long nap = idle < 6 ? (1ull << idle) : 64;
-            for (unsigned long long k = 0; k < nap; ++k) __builtin_amdgcn_s_sleep(32);
-            continue;
-        }
-        idle = 0;
+        if (t == Q_STOP) break;
         const ImgDesc d = load_desc(imgs, t);
         const int64_t lt = (int64_t)t - d.tile_base;
         const int ty = (int)(lt / d.ntx), tx = (int)(lt - (int64_t)ty * d.ntx);
@@ -1090,13 +1056,15 @@ __global__ __launch_bounds__(64 * QWAVES) void k_queue(Imgs imgs, Ctrl *__restri
         uint64_t *rows = bitmap + (int64_t)t * TS;
         bool released = false;
         while (true) {
-            uint64_t bits = __hip_atomic_exchange(rows + lane, 0ull, __ATOMIC_ACQUIRE,
+            uint64_t bits = __hip_atomic_exchange(rows + lane, 0ull, __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_AGENT);
             if (__ballot(bits != 0) == 0) {
                 if (released) break;
-                // let pushes enqueue the tile again, then look once more
+                // let pushes enqueue the tile again, then look once more (the
+                // store is done before the rows are read again)
                 if (lane == 0)
-                    __hip_atomic_store(qflag + t, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(qflag + t, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                wait_vmem();
                 released = true;
                 continue;
             }
@@ -1133,18 +1101,16 @@ __global__ __launch_bounds__(64 * QWAVES) void k_queue(Imgs imgs, Ctrl *__restri
                 // re-enqueued it, else leave the rest to the new entry
                 uint32_t prev = 0;
                 if (lane == 0)
-                    prev = __hip_atomic_exchange(qflag + t, 1u, __ATOMIC_ACQ_REL,
+                    prev = __hip_atomic_exchange(qflag + t, 1u, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
                 prev = __shfl(prev, 0);
                 if (prev != 0) break;
                 released = false;
             }
         }
-        // everything this tile produced is counted; retire the ring entry
-        __threadfence();
-        if (lane == 0)
-            __hip_atomic_fetch_add(&ctrl->pending.v, (unsigned long long)-1ll, __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+        // everything this tile produced is pushed; retire the ring entry
+        wait_vmem();
+        if (lane == 0) ring_retire(ctrl, ring, cap, gridDim.x * QWAVES);
     }
     // fold the per-lane counters
     unsigned long long p = npush, r = retries;
@@ -1349,36 +1315,37 @@ hipError_t launch_tile_round(int tbytes, int conn, const Imgs &imgs, int64_t n_t
 
 template <typename T, int CONN, int V>
 static hipError_t tile_queue_v(const Imgs &imgs, Ctrl *ctrl, uint32_t *state, uint32_t *ring,
-                               uint64_t cap, int max_iters, int grid, unsigned long long spin_cap,
+                               uint64_t cap, int max_iters, int grid, unsigned long long wait_us,
                                hipStream_t s) {
     hipLaunchKernelGGL((k_tile_queue<T, CONN, V>), dim3((unsigned)grid), dim3(64), 0, s, imgs,
-                       ctrl, state, ring, cap, max_iters, spin_cap);
+                       ctrl, state, ring, cap, max_iters, wait_us);
     return hipGetLastError();
 }
 template <typename T, int CONN>
 static hipError_t tile_queue_t(const Imgs &imgs, Ctrl *ctrl, uint32_t *state, uint32_t *ring,
-                               uint64_t cap, int max_iters, int grid, unsigned long long spin_cap,
+                               uint64_t cap, int max_iters, int grid, unsigned long long wait_us,
                                hipStream_t s, int op_all) {
     if (op_all == MR_OP_RECON)
-        return tile_queue_v<T, CONN, 0>(imgs, ctrl, state, ring, cap, max_iters, grid, spin_cap, s);
+        return tile_queue_v<T, CONN, 0>(imgs, ctrl, state, ring, cap, max_iters, grid, wait_us, s);
     if (op_all == MR_OP_FILL)
-        return tile_queue_v<T, CONN, 2>(imgs, ctrl, state, ring, cap, max_iters, grid, spin_cap, s);
-    return tile_queue_v<T, CONN, -1>(imgs, ctrl, state, ring, cap, max_iters, grid, spin_cap, s);
+        return tile_queue_v<T, CONN, 2>(imgs, ctrl, state, ring, cap, max_iters, grid, wait_us, s);
+    return tile_queue_v<T, CONN, -1>(imgs, ctrl, state, ring, cap, max_iters, grid, wait_us, s);
 }
 hipError_t launch_tile_queue(int tbytes, int conn, const Imgs &imgs, int64_t n_tiles,
                              const uint32_t *lists, uint32_t round, Ctrl *ctrl, uint32_t *state,
                              uint32_t *ring, uint64_t cap, int max_iters, int grid,
-                             unsigned long long spin_cap, hipStream_t s, int op_all) {
+                             unsigned long long wait_us, hipStream_t s, int op_all) {
     if (!ctrl || round > (uint32_t)MAX_ROUNDS + 1 || grid < 1) return hipErrorInvalidValue;
+    grid = (int)std::min<int64_t>(grid, RING_SLACK);
     hipLaunchKernelGGL(k_tile_queue_seed, dim3(NBANDS), dim3(256), 0, s, lists,
                        ctrl->round_tiles[round], n_tiles, round, state, ring, cap, ctrl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (tbytes == 1)
-        return conn == 8 ? tile_queue_t<uint8_t, 8>(imgs, ctrl, state, ring, cap, max_iters, grid, spin_cap, s, op_all)
-                         : tile_queue_t<uint8_t, 4>(imgs, ctrl, state, ring, cap, max_iters, grid, spin_cap, s, op_all);
-    return conn == 8 ? tile_queue_t<int32_t, 8>(imgs, ctrl, state, ring, cap, max_iters, grid, spin_cap, s, op_all)
-                     : tile_queue_t<int32_t, 4>(imgs, ctrl, state, ring, cap, max_iters, grid, spin_cap, s, op_all);
+        return conn == 8 ? tile_queue_t<uint8_t, 8>(imgs, ctrl, state, ring, cap, max_iters, grid, wait_us, s, op_all)
+                         : tile_queue_t<uint8_t, 4>(imgs, ctrl, state, ring, cap, max_iters, grid, wait_us, s, op_all);
+    return conn == 8 ? tile_queue_t<int32_t, 8>(imgs, ctrl, state, ring, cap, max_iters, grid, wait_us, s, op_all)
+                     : tile_queue_t<int32_t, 4>(imgs, ctrl, state, ring, cap, max_iters, grid, wait_us, s, op_all);
 }
 
 template <typename T, int CONN>
@@ -1438,21 +1405,23 @@ int queue_max_blocks(int tbytes, int conn) {
 
 template <typename T, int CONN>
 static hipError_t queue_t(const Imgs &imgs, Ctrl *ctrl, uint64_t *bitmap, uint32_t *qflag,
-                          uint32_t *ring, uint64_t cap, int blocks, unsigned long long spin_cap,
+                          uint32_t *ring, uint64_t cap, int blocks, unsigned long long wait_us,
                           hipStream_t s) {
     hipLaunchKernelGGL((k_queue<T, CONN>), dim3((unsigned)blocks), dim3(64 * QWAVES), 0, s, imgs,
-                       ctrl, bitmap, qflag, ring, cap, spin_cap);
+                       ctrl, bitmap, qflag, ring, cap, wait_us);
     return hipGetLastError();
 }
 
 hipError_t launch_queue(int tbytes, int conn, const Imgs &imgs, Ctrl *ctrl, uint64_t *bitmap,
                         uint32_t *qflag, uint32_t *ring, uint64_t cap, int blocks,
-                        unsigned long long spin_cap, hipStream_t s) {
+                        unsigned long long wait_us, hipStream_t s) {
+    if (blocks < 1) return hipErrorInvalidValue;
+    blocks = (int)std::min<int64_t>(blocks, RING_SLACK / QWAVES);
     if (tbytes == 1)
-        return conn == 8 ? queue_t<uint8_t, 8>(imgs, ctrl, bitmap, qflag, ring, cap, blocks, spin_cap, s)
-                         : queue_t<uint8_t, 4>(imgs, ctrl, bitmap, qflag, ring, cap, blocks, spin_cap, s);
-    return conn == 8 ? queue_t<int32_t, 8>(imgs, ctrl, bitmap, qflag, ring, cap, blocks, spin_cap, s)
-                     : queue_t<int32_t, 4>(imgs, ctrl, bitmap, qflag, ring, cap, blocks, spin_cap, s);
+        return conn == 8 ? queue_t<uint8_t, 8>(imgs, ctrl, bitmap, qflag, ring, cap, blocks, wait_us, s)
+                         : queue_t<uint8_t, 4>(imgs, ctrl, bitmap, qflag, ring, cap, blocks, wait_us, s);
+    return conn == 8 ? queue_t<int32_t, 8>(imgs, ctrl, bitmap, qflag, ring, cap, blocks, wait_us, s)
+                     : queue_t<int32_t, 4>(imgs, ctrl, bitmap, qflag, ring, cap, blocks, wait_us, s);
 }
 
 hipError_t launch_fill_output(int tbytes, const Imgs &imgs, int64_t n_tiles, hipStream_t s,
