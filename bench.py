@@ -28,7 +28,7 @@ Two more legs are added to the same line (``--legs``):
   Each job is a window of one of two seeded 8192 x 8192 images, its first
   column on a 64-byte boundary. Compared: sequential per-job launches (copy
   in, one call, copy out, wait) versus the continuous-batching server with an
-  8 GiB arena, first back to back, then on one Poisson arrival trace at
+  8 GiB arena and 128 job slots (--serve-slots), first back to back, then on one Poisson arrival trace at
   0.8 x the sequential capacity (p50/p99 of completion - arrival). Untimed
   passes afterwards hash every result of the sequential path and of the
   server (back to back and on the trace), which must agree job by job; a
@@ -275,7 +275,7 @@ def leg_served(args, dev) -> dict:
             return pm[y:y + H, x:x + W], pk[y:y + H, x:x + W]
         return pf[y:y + H, x:x + W], None
 
-    max_jobs = 32
+    max_jobs = args.serve_slots
     # result buffers: H rows of W, 64-byte aligned row pitch, in pinned blocks
     pool = queue.SimpleQueue()
     for _ in range(max_jobs + 16):
@@ -441,6 +441,8 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--serve-n", type=int, default=2000)
     ap.add_argument("--serve-load", type=float, default=0.8)
+    ap.add_argument("--serve-slots", type=int, default=128,
+                    help="server job slots (jobs resident at once)")
     ap.add_argument("--serve-rounds", type=int, default=None,
                     help="tile rounds per server step (library default when omitted)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
