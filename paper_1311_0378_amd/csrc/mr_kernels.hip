@@ -513,13 +513,6 @@ __device__ __forceinline__ void ring_push(Ctrl *ctrl, uint32_t *ring, uint64_t c
     __hip_atomic_store(slot, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Tile queue: a tile's state is 0 (idle), 1 (queued), 2 (a wave visits it)
-// or 3 (visited and marked again meanwhile: it goes back on the ring when the
-// visit ends). A mark sets bit 0; the one that finds the tile idle enqueues it.
-// Tile-queue visits read and write the working image device-coherent and
-// wait for their stores before any mark, so a visit that a mark leads to
-// sees the marking visit's pixels without cache-wide fences.
-
 // Wait until this wave's memory operations are done (its device-coherent
 // stores visible to every compute unit); also a compiler barrier.
 __device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
@@ -576,6 +569,13 @@ __device__ __forceinline__ void ring_retire(Ctrl *ctrl, uint32_t *ring, uint64_t
         __hip_atomic_store(ring + ((base + k) & (cap - 1)), Q_STOP, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
 }
+
+// Tile queue: a tile's state is 0 (idle), 1 (queued), 2 (a wave visits it)
+// or 3 (visited and marked again meanwhile: it goes back on the ring when the
+// visit ends). A mark sets bit 0; the one that finds the tile idle enqueues it.
+// Tile-queue visits read and write the working image device-coherent and
+// wait for their stores before any mark, so a visit that a mark leads to
+// sees the marking visit's pixels without cache-wide fences.
 struct TailQ {
     uint32_t *state;
     uint32_t *ring;
