@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define MR_ABI_VERSION 1
+#define MR_ABI_VERSION 2 /* 2: mr_tune.tail_rounds */
 
 typedef enum { MR_U8 = 1, MR_I32 = 4 } mr_dtype; /* value = bytes per pixel */
 

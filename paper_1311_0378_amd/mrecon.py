@@ -15,6 +15,7 @@ import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmrecon.so")
+ABI_VERSION = 2  # the layout of the structs below (include/mr.h MR_ABI_VERSION)
 HEADER = os.path.join(HERE, "..", "include", "mr.h")
 
 MR_U8, MR_I32 = 1, 4
@@ -134,6 +135,10 @@ def lib():
         L.mr_last_error.restype = ctypes.c_char_p
         L.mr_abi_version.argtypes = []
         L.mr_abi_version.restype = c_int
+        if L.mr_abi_version() != ABI_VERSION:
+            raise RuntimeError(f"{LIB_PATH} has ABI version {L.mr_abi_version()}, this binding "
+                               f"needs {ABI_VERSION}: rebuild with python -m "
+                               "paper_1311_0378_amd.build")
         _lib = L
     return _lib
 

@@ -20,7 +20,7 @@ def test_exports_every_declared_function(L):
 
 
 def test_abi_version(L):
-    assert L.mr_abi_version() == 1
+    assert L.mr_abi_version() == mrecon.ABI_VERSION == 2
 
 
 def test_default_tune():
