@@ -14,7 +14,7 @@ Prints one JSON line. ``roofline`` is for the dominant kernel, the tile
 round: algorithmic bytes per launch = tiles visited x (interior pixels per
 tile) x 3 bytes per pixel (read J, read the mask, write J), over the launch's
 duration measured with HIP events on the call's stream during the timed
-steps. ``--gpus`` above 1 is refused: this build runs on one GPU.
+steps. ``--gpus`` above 1 is refused: the library runs on one GPU.
 
 Two more legs are added to the same line (``--legs``):
 
@@ -459,7 +459,7 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
