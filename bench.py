@@ -445,6 +445,8 @@ def main():
                     help="server job slots (jobs resident at once)")
     ap.add_argument("--serve-rounds", type=int, default=None,
                     help="tile rounds per server step (library default when omitted)")
+    ap.add_argument("--timing", default="spans", choices=["spans", "launches"],
+                    help="launch timing inside the timed steps (see mr_timing_enable)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -504,7 +506,10 @@ def main():
         c.copy_(d_src)
     torch.cuda.synchronize()
 
-    mrecon.timing_enable(True)
+    # span mode: one pair of events per run of consecutive tile rounds (its
+    # average launch duration includes the dispatch gaps between them);
+    # "launches" brackets every launch, at a few microseconds per event
+    mrecon.timing_enable(args.timing)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(K):
@@ -521,28 +526,31 @@ def main():
     per_step = []
     li = 0
     tile_ms, tile_bytes, tile_launches = 0.0, 0.0, 0
-    seed_ms = queue_ms = 0.0
+    seed_ms = queue_ms = tq_ms = 0.0
     for i in range(K):
         rt = mrecon.read_round_tiles(wss[i])
         cnt = mrecon.read_counters(wss[i])
         step_tiles = 0
         # launches of step i: tile rounds 1..R, then optionally seed and queue
         while li < len(launches):
-            kind, rnd, ms = launches[li]
+            kind, rnd, ms, nl = launches[li]
             if kind == "tile_round":
                 if rnd == 1 and step_tiles:
                     break  # next step's first round
                 # every launch counts, also the few that find an empty list
-                # after convergence, as in a profiler's per-kernel average
-                visits = rt[rnd - 1] if rnd - 1 < len(rt) else 0
+                # after convergence, as in a profiler's per-kernel average; a
+                # span record covers rounds rnd .. rnd + nl - 1
+                visits = sum(rt[r - 1] for r in range(rnd, rnd + nl) if r - 1 < len(rt))
                 step_tiles += visits
                 tile_ms += ms
                 tile_bytes += visits * bytes_per_visit
-                tile_launches += 1
+                tile_launches += nl
             elif kind == "seed":
                 seed_ms += ms
             elif kind == "queue":
                 queue_ms += ms
+            elif kind == "tile_queue":
+                tq_ms += ms
             li += 1
         per_step.append({"tiles": step_tiles, "counters": cnt, "round_tiles": rt})
 
@@ -579,6 +587,7 @@ def main():
             "launches": tile_launches,
             "avg_launch_ms": round(tile_ms / max(1, tile_launches), 4),
             "bytes_per_tile_visit": round(bytes_per_visit, 1),
+            "timing": args.timing,
         },
         "whole_call": {
             "b_alg_gb_per_step": round(b_alg_step / 1e9, 4),
@@ -587,6 +596,7 @@ def main():
             "tile_round_ms_per_step": round(tile_ms / K, 4),
             "seed_ms_per_step": round(seed_ms / K, 4),
             "queue_ms_per_step": round(queue_ms / K, 4),
+            "tile_queue_ms_per_step": round(tq_ms / K, 4),
         },
         "counters_last_step": per_step[-1]["counters"],
         "round_tiles_last_step": [int(x) for x in per_step[-1]["round_tiles"]],

@@ -265,18 +265,24 @@ int mr_read_round_tiles(const void *ws, uint32_t *out, int32_t cap, int32_t *n_r
 /* Per-launch device timing (measurement support). While enabled, every
  * tile-round, seed, queue and tile-queue kernel that a call on this thread
  * enqueues is bracketed by two HIP events recorded on the call's stream; the
- * records accumulate until collected. The events carry no system-scope fence (no
- * cache writeback between launches); each still adds a marker to the
- * stream, about 2 us per event on MI355X. */
+ * records accumulate until collected. The events carry no system-scope fence
+ * (no cache writeback between launches); each still adds a marker to the
+ * stream, a few microseconds of device time per event on MI355X.
+ * MR_TIMING_SPANS brackets instead each run of consecutive tile rounds that
+ * no host wait interrupts, with one pair of events: the record covers
+ * `launches` rounds and the dispatch gaps between them. */
 enum { MR_K_TILE_ROUND = 0, MR_K_SEED = 1, MR_K_QUEUE = 2, MR_K_TILE_QUEUE = 3 };
+enum { MR_TIMING_OFF = 0, MR_TIMING_LAUNCHES = 1, MR_TIMING_SPANS = 2 };
 typedef struct {
-    int32_t kind;  /* MR_K_* */
-    int32_t round; /* tile round number (MR_K_TILE_ROUND), else 0 */
-    float ms;      /* device time between the two events */
+    int32_t kind;     /* MR_K_* */
+    int32_t round;    /* first tile round covered (MR_K_TILE_ROUND), else 0 */
+    int32_t launches; /* launches covered: 1, or the rounds of a span */
+    float ms;         /* device time between the two events */
 } mr_launch_time;
 
-/* Turns per-launch timing on (on != 0) or off for the calling thread.
- * Returns MR_OK. */
+/* Sets the calling thread's timing mode: MR_TIMING_OFF, MR_TIMING_LAUNCHES
+ * (every launch bracketed) or MR_TIMING_SPANS. Any other nonzero value means
+ * MR_TIMING_LAUNCHES. Returns MR_OK. */
 int mr_timing_enable(int on);
 
 /* Waits for the recorded events, writes up to `cap` records in launch order

@@ -133,11 +133,11 @@ mr_tune effective_tune(const mr_tune *tn) {
 
 // Per-launch timing records of the calling thread (mr_timing_enable).
 struct TimedLaunch {
-    int32_t kind, round;
+    int32_t kind, round, launches;
     hipEvent_t a, b;
 };
 struct Timing {
-    bool on = false;
+    int on = MR_TIMING_OFF;
     std::vector<TimedLaunch> recs;
     std::vector<hipEvent_t> pool;
     ~Timing() {
@@ -168,7 +168,10 @@ struct LaunchTimer {
     int32_t kind, round;
     hipEvent_t a = nullptr;
     LaunchTimer(hipStream_t s_, int32_t kind_, int32_t round_) : s(s_), kind(kind_), round(round_) {
-        if (g_timing.on && (a = g_timing.get()) && hipEventRecord(a, s) != hipSuccess) {
+        // in span mode the tile rounds are timed by a RoundSpan instead
+        const bool on = g_timing.on == MR_TIMING_LAUNCHES ||
+                        (g_timing.on == MR_TIMING_SPANS && kind != MR_K_TILE_ROUND);
+        if (on && (a = g_timing.get()) && hipEventRecord(a, s) != hipSuccess) {
             g_timing.pool.push_back(a);
             a = nullptr;
         }
@@ -181,8 +184,42 @@ struct LaunchTimer {
             if (b) g_timing.pool.push_back(b);
             return;
         }
-        g_timing.recs.push_back({kind, round, a, b});
+        g_timing.recs.push_back({kind, round, 1, a, b});
     }
+};
+
+// Span mode: one pair of events around consecutive tile rounds. begin()
+// before a round's launch (opens a span if none is open), add() after it,
+// close() before anything else goes on the stream or the host waits.
+struct RoundSpan {
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    int32_t first = 0, n = 0;
+    explicit RoundSpan(hipStream_t s_) : s(s_) {}
+    void begin(uint32_t round) {
+        if (g_timing.on != MR_TIMING_SPANS || a) return;
+        if ((a = g_timing.get()) && hipEventRecord(a, s) != hipSuccess) {
+            g_timing.pool.push_back(a);
+            a = nullptr;
+        }
+        first = (int32_t)round;
+        n = 0;
+    }
+    void add() {
+        if (a) ++n;
+    }
+    void close() {
+        if (!a) return;
+        hipEvent_t b = g_timing.get();
+        if (!b || n == 0 || hipEventRecord(b, s) != hipSuccess) {
+            g_timing.pool.push_back(a);
+            if (b) g_timing.pool.push_back(b);
+        } else {
+            g_timing.recs.push_back({MR_K_TILE_ROUND, first, n, a, b});
+        }
+        a = nullptr;
+    }
+    ~RoundSpan() { close(); }
 };
 
 // Pinned words the converge mode polls through (one round's band counts).
@@ -218,15 +255,19 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
     if ((e = launch_clear_u32(flags, L.n_tiles, 0u, s)) != hipSuccess) return hip_fail(e, "clear");
 
     uint32_t round = 1;
+    RoundSpan span(s); // span-mode timing of consecutive rounds
+    span.begin(round);
     {
         LaunchTimer lt(s, MR_K_TILE_ROUND, (int32_t)round);
         e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl, round,
                               tn.max_sweeps, grid, s, op_all);
     }
     if (e != hipSuccess) return hip_fail(e, "tile round");
+    span.add();
     // Seed pass and queue phase over the tiles listed for round `seed_round`
     // (the round after the last one run).
     auto queue_phase = [&](uint32_t seed_round) -> int {
+        span.close();
         if ((e = launch_clear_u32(qflag, L.n_tiles, 0u, s)) != hipSuccess ||
             (e = launch_clear_u64(bitmap, L.n_tiles * TS, s)) != hipSuccess ||
             (e = launch_clear_u32(ring, (int64_t)L.ring_cap, Q_EMPTY, s)) != hipSuccess)
@@ -251,13 +292,16 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
     };
     if (tn.sweep_rounds > 0) {
         for (round = 2; round <= (uint32_t)tn.sweep_rounds; ++round) {
+            span.begin(round);
             {
                 LaunchTimer lt(s, MR_K_TILE_ROUND, (int32_t)round);
                 e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl, round,
                                       tn.max_sweeps, grid, s, op_all);
             }
             if (e != hipSuccess) return hip_fail(e, "tile round");
+            span.add();
         }
+        span.close();
         if ((e = launch_store_u64(&ctrl->rounds, (unsigned long long)tn.sweep_rounds, s)) !=
             hipSuccess)
             return hip_fail(e, "store");
@@ -267,13 +311,16 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
         // converge mode with the tile queue: a fixed number of rounds, then
         // the queue takes every tile still listed and runs to the fixed point
         for (round = 2; round <= (uint32_t)tn.tail_rounds; ++round) {
+            span.begin(round);
             {
                 LaunchTimer lt(s, MR_K_TILE_ROUND, (int32_t)round);
                 e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl, round,
                                       tn.max_sweeps, grid, s, op_all);
             }
             if (e != hipSuccess) return hip_fail(e, "tile round");
+            span.add();
         }
+        span.close();
         if ((e = launch_store_u64(&ctrl->rounds, (unsigned long long)tn.tail_rounds, s)) !=
             hipSuccess)
             return hip_fail(e, "store");
@@ -298,13 +345,16 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
         while (true) {
             for (uint32_t k = 0; k < poll && round < cap; ++k) {
                 ++round;
+                span.begin(round);
                 {
                     LaunchTimer lt(s, MR_K_TILE_ROUND, (int32_t)round);
                     e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl,
                                           round, tn.max_sweeps, grid, s, op_all);
                 }
                 if (e != hipSuccess) return hip_fail(e, "tile round");
+                span.add();
             }
+            span.close(); // the host waits below
             if ((e = hipMemcpyAsync(hw, ctrl->round_tiles[round + 1], sizeof(uint32_t) * NBANDS,
                                     hipMemcpyDeviceToHost, s)) != hipSuccess)
                 return hip_fail(e, "poll copy");
@@ -534,8 +584,8 @@ int mr_batch_graph_create(const mr_tile *tiles, int32_t n, mr_dtype t, int conn,
     hipStream_t s = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(e, "stream");
-    const bool timing = g_timing.on;
-    g_timing.on = false;
+    const int timing = g_timing.on;
+    g_timing.on = MR_TIMING_OFF;
     mr_graph *g = new mr_graph();
     int rc = MR_OK;
     if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
@@ -621,8 +671,8 @@ int mr_autotune(const mr_tile *tiles, int32_t n, mr_dtype t, int conn, void *ws,
     hipEvent_t a = nullptr, b = nullptr;
     if ((e = hipEventCreate(&a)) != hipSuccess || (e = hipEventCreate(&b)) != hipSuccess)
         return hip_fail(e, "event");
-    const bool timing = g_timing.on;
-    g_timing.on = false;
+    const int timing = g_timing.on;
+    g_timing.on = MR_TIMING_OFF;
     float best = 1e30f;
     mr_tune bt;
     mr_default_tune(&bt);
@@ -699,7 +749,8 @@ int mr_read_round_tiles(const void *ws, uint32_t *out, int32_t cap, int32_t *n_r
 }
 
 int mr_timing_enable(int on) {
-    g_timing.on = on != 0;
+    g_timing.on = on == MR_TIMING_OFF ? MR_TIMING_OFF
+                  : on == MR_TIMING_SPANS ? MR_TIMING_SPANS : MR_TIMING_LAUNCHES;
     return MR_OK;
 }
 
@@ -714,7 +765,7 @@ int mr_timing_collect(mr_launch_time *out, int32_t cap, int32_t *n) {
         hipError_t e = hipEventSynchronize(r.b);
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
         if (e != hipSuccess && rc == MR_OK) rc = hip_fail(e, "event");
-        if ((int32_t)i < cap) out[i] = mr_launch_time{r.kind, r.round, ms};
+        if ((int32_t)i < cap) out[i] = mr_launch_time{r.kind, r.round, r.launches, ms};
         g_timing.pool.push_back(r.a);
         g_timing.pool.push_back(r.b);
     }

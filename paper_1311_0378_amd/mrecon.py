@@ -51,7 +51,8 @@ class Job(ctypes.Structure):
 
 
 class LaunchTime(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32), ("round", ctypes.c_int32), ("ms", ctypes.c_float)]
+    _fields_ = [("kind", ctypes.c_int32), ("round", ctypes.c_int32), ("launches", ctypes.c_int32),
+                ("ms", ctypes.c_float)]
 
 
 KIND_NAMES = {0: "tile_round", 1: "seed", 2: "queue", 3: "tile_queue"}
@@ -427,20 +428,28 @@ def read_round_tiles(workspace: torch.Tensor, stream=None) -> list:
     return [int(buf[i]) for i in range(min(cap, n.value + 1))]
 
 
-def timing_enable(on: bool = True) -> None:
-    """Bracket every tile-round, seed and queue launch of this thread's calls
-    with HIP events on the call's stream."""
-    _check(lib().mr_timing_enable(1 if on else 0))
+TIMING_MODES = {False: 0, True: 1, "launches": 1, "spans": 2}
+
+
+def timing_enable(on=True) -> None:
+    """Time this thread's launches with HIP events on each call's stream:
+    ``True``/``"launches"`` brackets every tile-round, seed, queue and
+    tile-queue launch; ``"spans"`` brackets each run of consecutive tile rounds
+    (no host wait between them) with one pair of events instead; ``False``
+    turns timing off."""
+    _check(lib().mr_timing_enable(TIMING_MODES[on]))
 
 
 def timing_collect() -> list:
-    """Wait for and return the recorded launches as ``(kind, round, ms)``."""
+    """Wait for and return the records as ``(kind, round, ms, launches)``:
+    ``round`` is the first tile round a record covers (0 for other kinds) and
+    ``launches`` the number of launches it covers."""
     n = ctypes.c_int32()
     cap = 1 << 16
     buf = (LaunchTime * cap)()
     _check(lib().mr_timing_collect(buf, cap, ctypes.byref(n)))
-    return [(KIND_NAMES.get(buf[i].kind, str(buf[i].kind)), int(buf[i].round), float(buf[i].ms))
-            for i in range(min(cap, n.value))]
+    return [(KIND_NAMES.get(buf[i].kind, str(buf[i].kind)), int(buf[i].round), float(buf[i].ms),
+             int(buf[i].launches)) for i in range(min(cap, n.value))]
 
 
 def read_counters(workspace: torch.Tensor, stream=None) -> dict:
