@@ -250,9 +250,11 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
     const int grid = persistent_grid(); // two 64-thread blocks per SIMD
     hipError_t e;
 
-    if ((e = launch_clear_ctrl(ctrl, L.n_tiles, s)) != hipSuccess)
+    // control block, dirty flags, and the queue flags and ring (untouched by
+    // the rounds, so the tile queue can start from them as they are)
+    if ((e = launch_clear_start(ctrl, L.n_tiles, flags, qflag, ring, (int64_t)L.ring_cap, s)) !=
+        hipSuccess)
         return hip_fail(e, "clear");
-    if ((e = launch_clear_u32(flags, L.n_tiles, 0u, s)) != hipSuccess) return hip_fail(e, "clear");
 
     uint32_t round = 1;
     RoundSpan span(s); // span-mode timing of consecutive rounds
@@ -324,9 +326,6 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
         if ((e = launch_store_u64(&ctrl->rounds, (unsigned long long)tn.tail_rounds, s)) !=
             hipSuccess)
             return hip_fail(e, "store");
-        if ((e = launch_clear_u32(qflag, L.n_tiles, 0u, s)) != hipSuccess ||
-            (e = launch_clear_u32(ring, (int64_t)L.ring_cap, Q_EMPTY, s)) != hipSuccess)
-            return hip_fail(e, "clear");
         {
             LaunchTimer lt(s, MR_K_TILE_QUEUE, 0);
             e = launch_tile_queue(tbytes, conn, imgs, L.n_tiles, lists, (uint32_t)tn.tail_rounds + 1,

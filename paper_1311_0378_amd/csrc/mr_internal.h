@@ -91,6 +91,10 @@ int set_error(int code, const char *msg);
 // Host-side launchers (defined in mr_kernels.hip).
 hipError_t launch_clear_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_clear_ctrl(Ctrl *c, int64_t n_tiles, hipStream_t s);
+// Clears what a launch sequence starts from in one kernel: the control block,
+// flags[n_tiles], qflag[n_tiles] (0) and ring[ring_cap] (Q_EMPTY).
+hipError_t launch_clear_start(Ctrl *c, int64_t n_tiles, uint32_t *flags, uint32_t *qflag,
+                              uint32_t *ring, int64_t ring_cap, hipStream_t s);
 // Round r visits every tile (r == 1) or the dirty lists of round r -- band
 // b's at lists[(r & 1) * n_tiles + band start], ctrl->round_tiles[r][b] long
 // -- and lists each tile it dirties for round r + 1 in the other half

@@ -1144,6 +1144,29 @@ __global__ void k_clear_ctrl(Ctrl *c, int64_t n_tiles) {
             (uint32_t)(band_lo(n_tiles, threadIdx.x + 1) - band_lo(n_tiles, threadIdx.x));
 }
 
+// The start of a launch sequence in one kernel: the control block (block 0;
+// round 1 lists every tile of each band), the dirty flags, and the queue
+// flags and ring of the tile queue and the queue phase.
+__global__ void k_clear_start(Ctrl *c, int64_t n_tiles, uint32_t *flags, uint32_t *qflag,
+                              uint32_t *ring, int64_t ring_cap) {
+    if (blockIdx.x == 0) {
+        unsigned long long *p = (unsigned long long *)c;
+        const int n = (int)(sizeof(Ctrl) / sizeof(unsigned long long));
+        for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+        __syncthreads();
+        if (threadIdx.x < NBANDS)
+            c->round_tiles[1][threadIdx.x] =
+                (uint32_t)(band_lo(n_tiles, threadIdx.x + 1) - band_lo(n_tiles, threadIdx.x));
+    }
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_tiles; i += stride) {
+        flags[i] = 0u;
+        qflag[i] = 0u;
+    }
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ring_cap; i += stride)
+        ring[i] = Q_EMPTY;
+}
+
 // Fill-holes epilogue: out = NOT J over the interior of every tile of the
 // launch whose image is a fill-holes image.
 template <typename T>
@@ -1255,6 +1278,14 @@ hipError_t launch_clear_ctrl(Ctrl *c, int64_t n_tiles, hipStream_t s) {
     hipLaunchKernelGGL(k_clear_ctrl, dim3(1), dim3(256), 0, s, c, n_tiles);
     return hipGetLastError();
 }
+hipError_t launch_clear_start(Ctrl *c, int64_t n_tiles, uint32_t *flags, uint32_t *qflag,
+                              uint32_t *ring, int64_t ring_cap, hipStream_t s) {
+    const int64_t n = std::max<int64_t>(n_tiles, ring_cap);
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_clear_start, dim3((unsigned)blocks), dim3(256), 0, s, c, n_tiles, flags,
+                       qflag, ring, ring_cap);
+    return hipGetLastError();
+}
 
 template <typename T, int CONN, int V>
 static hipError_t tile_round_v(const Imgs &imgs, int64_t n_tiles, uint32_t *flags,
@@ -1335,8 +1366,10 @@ hipError_t launch_tile_queue(int tbytes, int conn, const Imgs &imgs, int64_t n_t
                              const uint32_t *lists, uint32_t round, Ctrl *ctrl, uint32_t *state,
                              uint32_t *ring, uint64_t cap, int max_iters, int grid,
                              unsigned long long wait_us, hipStream_t s, int op_all) {
-    if (!ctrl || round > (uint32_t)MAX_ROUNDS + 1 || grid < 1) return hipErrorInvalidValue;
-    grid = (int)std::min<int64_t>(grid, RING_SLACK);
+    if (!ctrl || round > (uint32_t)MAX_ROUNDS + 1 || grid < 1 || n_tiles < 1)
+        return hipErrorInvalidValue;
+    // no more waves than tiles: a wave visits one tile at a time
+    grid = (int)std::min<int64_t>(std::min<int64_t>(grid, RING_SLACK), n_tiles);
     hipLaunchKernelGGL(k_tile_queue_seed, dim3(NBANDS), dim3(256), 0, s, lists,
                        ctrl->round_tiles[round], n_tiles, round, state, ring, cap, ctrl);
     hipError_t e = hipGetLastError();
