@@ -250,7 +250,9 @@ int mr_server_stats(const mr_server *s, int32_t *resident, uint64_t *rounds,
 void mr_server_destroy(mr_server *s);
 
 /* Copies the work counters held in a workspace to *out. Waits for `stream`.
- * Errors: MR_EINVAL (null pointer), MR_EHIP. */
+ * Errors: MR_EINVAL (null pointer), MR_EHIP (a copy failed, or a wave of the
+ * queue phase or the tile queue saw no new ring entry for 2 s and gave up:
+ * the result of that call is then incomplete; *out is still written). */
 int mr_read_counters(const void *ws, mr_counters *out, void *stream);
 
 /* Tile visits per round of the last call that used a workspace: out[i] is

@@ -729,7 +729,7 @@ int mr_read_counters(const void *ws, mr_counters *out, void *stream) {
         c.tiles += h.tiles[i]; // tile-queue visits
     }
     *out = c;
-    if (h.watchdog) return fail(MR_EHIP, "a queue or tile-queue workgroup hit its spin cap");
+    if (h.watchdog) return fail(MR_EHIP, "a queue or tile-queue wave saw no progress for its watchdog time");
     return MR_OK;
 }
 
