@@ -33,6 +33,11 @@ Two more legs are added to the same line (``--legs``):
   passes afterwards hash every result of the sequential path and of the
   server (back to back and on the trace), which must agree job by job; a
   sample of jobs is checked against the oracle.
+
+``--atomic-probe`` instead times the device atomic-rate probe
+(``mr_probe_atomics``: relaxed device-scope add, and load + compare-and-swap,
+on pseudo-random words of a 256 MiB and a 4 GiB buffer, every wave slot busy)
+and prints its own JSON line: the ceiling for the queue phase's atomics.
 """
 from __future__ import annotations
 
@@ -426,6 +431,40 @@ def leg_served(args, dev) -> dict:
     }
 
 
+def atomic_probe(torch, mrecon, dev, reps: int = 5) -> dict:
+    """Relaxed device-scope atomics on pseudo-random words, every wave slot of
+    the GPU busy: the ceiling the queue phase's atomics are measured against."""
+    waves = 16384  # 256 CUs x 32 wave slots, twice over
+    cases = []
+    for log2_words in (26, 30):  # 256 MiB (the 16384^2 u8 image's size), 4 GiB
+        words = torch.zeros(1 << log2_words, dtype=torch.int32, device=dev)
+        for kind, name, per_lane in ((mrecon.MR_PROBE_ADD, "add", 256),
+                                     (mrecon.MR_PROBE_CAS, "load+cas", 64)):
+            ops = waves * 64 * per_lane
+            mrecon.probe_atomics(words, kind, per_lane, waves, seed=1)  # warm-up
+            times = []
+            for r in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                mrecon.probe_atomics(words, kind, per_lane, waves, seed=2 + r)
+                b.record()
+                b.synchronize()
+                times.append(a.elapsed_time(b))
+            ms = sorted(times)[len(times) // 2]
+            cases.append({"kind": name, "buffer_mib": (4 << log2_words) >> 20, "waves": waves,
+                          "per_lane": per_lane, "ops": ops, "ms_median": round(ms, 4),
+                          "g_ops_s": round(ops / ms / 1e6, 2)})
+            log(f"probe {name} {(4 << log2_words) >> 20} MiB: {ms:.3f} ms, "
+                f"{ops / ms / 1e6:.1f} G ops/s")
+        total = int(words.to(torch.int64).sum())
+        expect = (reps + 1) * waves * 64 * (256 + 64)
+        if total != expect:
+            raise RuntimeError(f"probe lost operations: {total} != {expect}")
+        del words
+    return {"probe": "device atomics, relaxed, device scope, pseudo-random words",
+            "cases": cases}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -451,6 +490,9 @@ def main():
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="copy 1 GiB on the device first (counter calibration)")
+    ap.add_argument("--atomic-probe", action="store_true",
+                    help="time the device atomic-rate probe (mr_probe_atomics) on a 256 MiB and "
+                         "a 4 GiB buffer, print one JSON line and exit")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE) of a "
                          "--calibrate-copy run into profiles/tile_round_traffic.json and exit")
@@ -472,6 +514,9 @@ def main():
     if not os.path.exists(libbuild.LIB):
         libbuild.build()
     dev = torch.device("cuda:0")
+    if args.atomic_probe:
+        print(json.dumps(atomic_probe(torch, mrecon, dev)), flush=True)
+        return
     S, dt, conn = args.size, args.dtype, args.conn
     tune = None
     if args.tune:

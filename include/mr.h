@@ -292,6 +292,25 @@ int mr_timing_enable(int on);
  * Errors: MR_EINVAL (null n, or out null with cap > 0), MR_EHIP. */
 int mr_timing_collect(mr_launch_time *out, int32_t cap, int32_t *n);
 
+/* Device atomic-rate probe (measurement support; cf. the atomic-throughput
+ * measurements of Table IV). Enqueues on `stream` one launch of `waves`
+ * 64-lane waves; each lane performs `per_lane` relaxed device-scope atomics
+ * on words of `words` (device memory, n_words uint32 values, caller-owned)
+ * chosen by a fixed hash of (seed, lane, step):
+ *   MR_PROBE_ADD  fetch-add of 1, result unused;
+ *   MR_PROBE_CAS  load, then compare-and-swap to the value read + 1, retried
+ *                 with the returned value until it lands (the queue phase's
+ *                 raise pattern).
+ * Either way the sum of the words grows by exactly waves * 64 * per_lane
+ * (mod 2^32 per word). Time it with events on the same stream.
+ * Errors: MR_EINVAL (words null or not 4-byte aligned; n_words not a power
+ * of two in [64, 2^32]; kind unknown; per_lane outside [1, 65536]; waves
+ * outside [1, 2^20]), MR_EHIP (launch failure). Nothing is enqueued on
+ * error. */
+enum { MR_PROBE_ADD = 0, MR_PROBE_CAS = 1 };
+int mr_probe_atomics(void *words, size_t n_words, int kind, int32_t per_lane, int32_t waves,
+                     uint32_t seed, void *stream);
+
 /* Message for the last error returned to the calling thread ("" if none). */
 const char *mr_last_error(void);
 

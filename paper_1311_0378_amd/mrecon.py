@@ -21,6 +21,7 @@ HEADER = os.path.join(HERE, "..", "include", "mr.h")
 MR_U8, MR_I32 = 1, 4
 MR_OK, MR_EINVAL, MR_ENOMEM, MR_EHIP, MR_EAGAIN = 0, -1, -2, -3, -4
 MR_OP_RECON, MR_OP_FILL = 0, 1
+MR_PROBE_ADD, MR_PROBE_CAS = 0, 1
 
 _DTYPES = {torch.uint8: MR_U8, torch.int32: MR_I32}
 
@@ -132,6 +133,8 @@ def lib():
         L.mr_timing_enable.restype = c_int
         L.mr_timing_collect.argtypes = [ctypes.POINTER(LaunchTime), i32, ctypes.POINTER(i32)]
         L.mr_timing_collect.restype = c_int
+        L.mr_probe_atomics.argtypes = [vp, sz, c_int, i32, i32, ctypes.c_uint32, vp]
+        L.mr_probe_atomics.restype = c_int
         L.mr_last_error.argtypes = []
         L.mr_last_error.restype = ctypes.c_char_p
         L.mr_abi_version.argtypes = []
@@ -457,3 +460,16 @@ def read_counters(workspace: torch.Tensor, stream=None) -> dict:
     c = Counters()
     _check(lib().mr_read_counters(workspace.data_ptr(), ctypes.byref(c), _stream_ptr(stream)))
     return c.as_dict()
+
+
+def probe_atomics(words: torch.Tensor, kind: int, per_lane: int, waves: int, seed: int = 0,
+                  stream=None) -> None:
+    """Enqueue the device atomic-rate probe on ``words`` (a contiguous 32-bit
+    device tensor whose length is a power of two): ``waves`` 64-lane waves,
+    ``per_lane`` atomics per lane of kind ``MR_PROBE_ADD`` or ``MR_PROBE_CAS``.
+    The sum of ``words`` grows by ``waves * 64 * per_lane``."""
+    if (words.dtype not in (torch.int32, torch.uint32) or not words.is_contiguous()
+            or not words.is_cuda):
+        raise TypeError("words must be a contiguous int32 or uint32 device tensor")
+    _check(lib().mr_probe_atomics(words.data_ptr(), words.numel(), int(kind), int(per_lane),
+                                  int(waves), int(seed) & 0xFFFFFFFF, _stream_ptr(stream)))

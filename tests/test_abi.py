@@ -170,3 +170,14 @@ def test_plane_limit(L):
 
 def test_server_rounds_per_step_validation(L):
     assert L.mr_server_set_rounds_per_step(None, 4) == mrecon.MR_EINVAL
+
+
+@pytest.mark.parametrize("words,n,kind,per_lane,waves", [
+    (0, 1 << 16, 0, 1, 1), (FAKE + 2, 1 << 16, 0, 1, 1), (FAKE, 1000, 0, 1, 1),
+    (FAKE, 32, 1, 1, 1), (FAKE, (1 << 32) * 2, 0, 1, 1), (FAKE, 1 << 16, 2, 1, 1),
+    (FAKE, 1 << 16, 0, 0, 1), (FAKE, 1 << 16, 1, 1 << 17, 1), (FAKE, 1 << 16, 0, 1, 0),
+    (FAKE, 1 << 16, 1, 1, (1 << 20) + 1)])
+def test_probe_atomics_rejects(L, words, n, kind, per_lane, waves):
+    assert L.mr_probe_atomics(ctypes.c_void_p(words), n, kind, per_lane, waves, 0, None) \
+        == mrecon.MR_EINVAL
+    assert L.mr_last_error().startswith(b"probe:")
