@@ -1,4 +1,5 @@
-"""CPU oracle for grayscale reconstruction by dilation and fill-holes.
+"""CPU oracle for grayscale reconstruction by dilation, its dual by erosion,
+and fill-holes.
 
 TEST INFRASTRUCTURE. Only ``tests/``, ``__graft_entry__.smoke()`` and the
 CPU-baseline leg of ``bench.py`` may import this package. The GPU product path
@@ -59,7 +60,8 @@ def _lib(plant: int = 0):
             path = build(plant, force=False)
             lib = ctypes.CDLL(path)
             i64, c_int, vp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
-            for name in ("mro_recon_dilate_u8", "mro_recon_dilate_i32"):
+            for name in ("mro_recon_dilate_u8", "mro_recon_dilate_i32", "mro_recon_erode_u8",
+                         "mro_recon_erode_i32"):
                 fn = getattr(lib, name)
                 fn.argtypes = [vp, vp, i64, i64, c_int, ctypes.POINTER(Counts)]
                 fn.restype = c_int
@@ -93,6 +95,24 @@ def recon_dilate(marker: np.ndarray, mask: np.ndarray, conn: int = 8, plant: int
     rc = fn(out.ctypes.data, m.ctypes.data, H, W, int(conn), ctypes.byref(c))
     if rc != 0:
         raise ValueError(f"oracle recon_dilate failed with status {rc}")
+    return out, c.as_dict()
+
+
+def recon_erode(marker: np.ndarray, mask: np.ndarray, conn: int = 8, plant: int = 0):
+    """Reconstruction by erosion of ``marker`` over ``mask`` (the dual of
+    Table II's reconstruction, after Vincent 1993): the greatest image below
+    max(marker, mask) stable under J <- max(mask, min of J over the
+    neighbourhood). Returns ``(E, counts)``; the inputs are not modified."""
+    if marker.shape != mask.shape or marker.dtype != mask.dtype or marker.ndim != 2:
+        raise ValueError("marker and mask must be 2-D arrays of one shape and dtype")
+    out = np.ascontiguousarray(marker).copy()
+    m = np.ascontiguousarray(mask)
+    H, W = out.shape
+    c = Counts()
+    fn = getattr(_lib(plant), f"mro_recon_erode_{_suffix(out)}")
+    rc = fn(out.ctypes.data, m.ctypes.data, H, W, int(conn), ctypes.byref(c))
+    if rc != 0:
+        raise ValueError(f"oracle recon_erode failed with status {rc}")
     return out, c.as_dict()
 
 

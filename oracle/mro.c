@@ -277,3 +277,58 @@ int mro_fill_holes_i32(int32_t *img_inout, int64_t H, int64_t W, int conn, mro_c
     if (check_args(img_inout, img_inout, H, W, conn)) return MRO_EINVAL;
     return fill_core(img_inout, H, W, conn, INT32_MIN, cmpl_i32, cnt);
 }
+
+/* Reconstruction by erosion, the dual of Table II's reconstruction (after
+ * Vincent 1993): E is the greatest image J <= max(marker, mask) that is stable
+ * under J(p) <- max(mask(p), min of J over p and its G-neighbours). NOT, the
+ * bitwise complement, reverses the order and maps min to max, so
+ * E = NOT R(NOT marker, NOT mask); that identity is the whole computation
+ * here, on top of the reconstruction by dilation above. */
+static int erode_core(int32_t *J, const int32_t *mask, int64_t H, int64_t W, int conn,
+                      int32_t (*cmpl)(int32_t), mro_counts *cnt) {
+    size_t n = (size_t)H * (size_t)W;
+    int32_t *I = (int32_t *)calloc(n, sizeof(int32_t));
+    if (!I) return MRO_ENOMEM;
+    for (size_t i = 0; i < n; i++) {
+#if MRO_PLANT == 9
+        I[i] = mask[i]; /* planted: mask not complemented */
+#else
+        I[i] = cmpl(mask[i]);
+#endif
+#if MRO_PLANT == 8
+        J[i] = imax(cmpl(J[i]), I[i]); /* planted: clipped with the wrong operator */
+#else
+        J[i] = imin(cmpl(J[i]), I[i]);
+#endif
+    }
+    int rc = recon_core(J, I, H, W, conn, cnt);
+    if (rc == MRO_OK)
+        for (size_t i = 0; i < n; i++) J[i] = cmpl(J[i]);
+    free(I);
+    return rc;
+}
+
+int mro_recon_erode_u8(uint8_t *marker_inout, const uint8_t *mask, int64_t H, int64_t W,
+                       int conn, mro_counts *cnt) {
+    if (check_args(marker_inout, mask, H, W, conn)) return MRO_EINVAL;
+    size_t n = (size_t)H * (size_t)W;
+    int32_t *J = (int32_t *)malloc(n * sizeof(int32_t));
+    int32_t *M = (int32_t *)malloc(n * sizeof(int32_t));
+    if (!J || !M) { free(J); free(M); return MRO_ENOMEM; }
+    for (size_t i = 0; i < n; i++) {
+        J[i] = marker_inout[i];
+        M[i] = mask[i];
+    }
+    int rc = erode_core(J, M, H, W, conn, cmpl_u8, cnt);
+    if (rc == MRO_OK)
+        for (size_t i = 0; i < n; i++) marker_inout[i] = (uint8_t)J[i];
+    free(J);
+    free(M);
+    return rc;
+}
+
+int mro_recon_erode_i32(int32_t *marker_inout, const int32_t *mask, int64_t H, int64_t W,
+                        int conn, mro_counts *cnt) {
+    if (check_args(marker_inout, mask, H, W, conn)) return MRO_EINVAL;
+    return erode_core(marker_inout, mask, H, W, conn, cmpl_i32, cnt);
+}

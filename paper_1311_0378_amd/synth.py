@@ -27,6 +27,9 @@ Recipe for ``make_tile(H, W, n_disks, seed, dtype, hollow_frac)``:
    (7710 = 30 * 257).
 8. Fill-holes input: ``255`` where the u8 mask is ``>= 128``, else ``0``
    (i32: ``65535`` / ``0``).
+9. Reconstruction by erosion (``make_erode_tile``): the same mask, and the
+   marker raised instead, ``min(mask + 30, 255)`` for u8 and
+   ``min(mask + 7710, 65535)`` for i32.
 """
 from __future__ import annotations
 
@@ -135,6 +138,20 @@ def make_tile(H: int, W: int, n_disks: int, seed, dtype: str = "u8",
     """Return ``(marker, mask)`` for one synthetic tile."""
     mask = quantize(make_field(H, W, n_disks, seed, hollow_frac), dtype)
     return marker_from_mask(mask), mask
+
+
+def erode_marker_from_mask(mask: np.ndarray) -> np.ndarray:
+    """Step 9: the erosion marker is the mask raised by the same offset,
+    capped at the value range's top."""
+    off, top = (30, 255) if mask.dtype == np.uint8 else (7710, 65535)
+    return np.minimum(mask.astype(np.int64) + off, top).astype(mask.dtype)
+
+
+def make_erode_tile(H: int, W: int, n_disks: int, seed, dtype: str = "u8",
+                    hollow_frac: float = 0.0):
+    """Return ``(marker, mask)`` for reconstruction by erosion."""
+    mask = quantize(make_field(H, W, n_disks, seed, hollow_frac), dtype)
+    return erode_marker_from_mask(mask), mask
 
 
 def density_disks(H: int, W: int) -> int:

@@ -16,6 +16,11 @@ GPU engine. Each route reaches the same unique result by a different road:
 * ``minmax_fill``      -- fill-holes closed form: the min over paths to the
                           border of the max along the path (Dijkstra).
 * ``binary_fill``      -- ``scipy.ndimage.binary_fill_holes``.
+* ``brute_erode``      -- reconstruction by erosion from its definition:
+                          iterate max(erode(J), mask) to a fixed point with
+                          ``scipy.ndimage.grey_erosion`` (no complement).
+* ``minimax_path``     -- its closed form: the min over paths of the max of
+                          the start value and the mask along the path.
 """
 from __future__ import annotations
 
@@ -183,3 +188,41 @@ def load_golden(path: str) -> dict:
     for k, rows in blocks.items():
         out[k] = np.array(rows, dtype=np.int64).astype(dt)
     return out
+
+
+def maxval(dtype) -> int:
+    return int(np.iinfo(dtype).max)
+
+
+def brute_erode(marker: np.ndarray, mask: np.ndarray, conn: int) -> np.ndarray:
+    J = np.maximum(marker, mask)
+    fp = footprint(conn)
+    while True:
+        E = ndi.grey_erosion(J, footprint=fp, mode="constant", cval=maxval(J.dtype))
+        Jn = np.maximum(E, mask)
+        if np.array_equal(Jn, J):
+            return J
+        J = Jn
+
+
+def minimax_path(marker: np.ndarray, mask: np.ndarray, conn: int) -> np.ndarray:
+    """E(p) = min over q and paths q->p of max(J0(q), max of mask on the path),
+    J0 = max(marker, mask)."""
+    H, W = mask.shape
+    I = mask.astype(np.int64)
+    best = np.maximum(marker, mask).astype(np.int64)
+    heap = [(int(best[y, x]), y, x) for y in range(H) for x in range(W)]
+    heapq.heapify(heap)
+    nb = _nbrs(conn)
+    while heap:
+        d, y, x = heapq.heappop(heap)
+        if d > best[y, x]:
+            continue
+        for dy, dx in nb:
+            yy, xx = y + dy, x + dx
+            if 0 <= yy < H and 0 <= xx < W:
+                c = max(d, int(I[yy, xx]))
+                if c < best[yy, xx]:
+                    best[yy, xx] = c
+                    heapq.heappush(heap, (c, yy, xx))
+    return best.astype(mask.dtype)

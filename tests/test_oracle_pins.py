@@ -301,17 +301,101 @@ def _battery(plant):
         got, _ = oracle.fill_holes(img, conn, plant=plant)
         if not np.array_equal(got, refs.binary_fill(img, conn)):
             fails.append(f"fill/conn{conn}")
+        for t in range(30):
+            H, W = rng.integers(2, 12, 2)
+            mask = rng.integers(0, 4, (H, W)).astype(np.uint8)
+            marker = rng.integers(0, 4, (H, W)).astype(np.uint8)
+            got, _ = oracle.recon_erode(marker, mask, conn, plant=plant)
+            if not np.array_equal(got, refs.brute_erode(marker, mask, conn)):
+                fails.append(f"erode-random/conn{conn}")
+                break
+        marker, mask = synth.make_erode_tile(40, 44, 2, 5, "u8", 0.0)
+        got, _ = oracle.recon_erode(marker, mask, conn, plant=plant)
+        if not np.array_equal(got, refs.minimax_path(marker, mask, conn)):
+            fails.append(f"erode-minimax/conn{conn}")
     return fails
 
 
-@pytest.mark.parametrize("plant", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("plant", [1, 2, 3, 4, 5, 6, 7, 8, 9])
 def test_planted_mistakes_are_caught(plant):
     """Each planted mistake (a neighbour missing from the seed test, a skipped queue phase, a
     wrong operator, a mask read at the wrong pixel, wrap-around at the edge, missing border
-    seeds, an off-by-one loop bound) must fail at least one pin."""
+    seeds, an off-by-one loop bound, an erosion marker clipped with max instead of min, an
+    erosion mask not complemented) must fail at least one pin."""
     oracle.build(plant=plant, force=True)
     assert _battery(plant), f"planted mistake {plant} slipped through every pin"
 
 
 def test_clean_oracle_passes_battery():
     assert _battery(0) == []
+
+
+# ------------------------------------------------- reconstruction by erosion
+
+@settings(max_examples=120, deadline=None)
+@given(H=st.integers(1, 14), W=st.integers(1, 14), levels=st.sampled_from([2, 3, 4, 0]),
+       conn=st.sampled_from([4, 8]), dt=st.sampled_from(["u8", "i32"]),
+       seed=st.integers(0, 2**31 - 1))
+def test_erode_random_vs_bruteforce(H, W, levels, conn, dt, seed):
+    rng = np.random.default_rng(seed)
+    if dt == "u8":
+        hi = levels if levels else 256
+        mask = rng.integers(0, hi, (H, W)).astype(np.uint8)
+        marker = rng.integers(0, hi, (H, W)).astype(np.uint8)
+    else:
+        lo, top = (-2**31, 2**31)
+        if levels:
+            vals = rng.integers(lo, top - 1, levels, dtype=np.int64)
+            mask = rng.choice(vals, (H, W)).astype(np.int32)
+            marker = rng.choice(vals, (H, W)).astype(np.int32)
+        else:
+            mask = rng.integers(lo, top, (H, W), dtype=np.int64).astype(np.int32)
+            marker = rng.integers(lo, top, (H, W), dtype=np.int64).astype(np.int32)
+    if seed % 2:  # half the cases keep marker >= mask, half exercise the clip
+        marker = np.maximum(marker, mask)
+    got, _ = oracle.recon_erode(marker, mask, conn)
+    np.testing.assert_array_equal(got, refs.brute_erode(marker, mask, conn))
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+@pytest.mark.parametrize("dt", ["u8", "i32"])
+def test_erode_synthetic_vs_bruteforce_and_minimax(conn, dt):
+    marker, mask = synth.make_erode_tile(72, 90, 4, 3, dt, 0.3)
+    got, _ = oracle.recon_erode(marker, mask, conn)
+    np.testing.assert_array_equal(got, refs.brute_erode(marker, mask, conn))
+    np.testing.assert_array_equal(got, refs.minimax_path(marker, mask, conn))
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_erode_binary_components(conn):
+    # binary special case: marker all high except seeds of 0; the result keeps
+    # 0 on the background components (mask == 0) that hold a seed, 1 elsewhere
+    rng = np.random.default_rng(conn + 10)
+    mask = (rng.random((40, 50)) < 0.45).astype(np.uint8)
+    seeds = rng.random((40, 50)) < 0.02
+    marker = np.where(seeds, 0, 1).astype(np.uint8)
+    got, _ = oracle.recon_erode(marker, mask, conn)
+    lab, _ = refs.ndi.label(mask == 0, structure=refs.footprint(conn))
+    keep = np.unique(lab[seeds & (mask == 0)])
+    keep = keep[keep > 0]
+    expect = np.where(np.isin(lab, keep), 0, 1).astype(np.uint8)
+    np.testing.assert_array_equal(got, expect)
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+@pytest.mark.parametrize("dt", ["u8", "i32"])
+def test_erode_invariants(conn, dt):
+    marker, mask = synth.make_erode_tile(80, 64, 4, 9, dt, 0.2)
+    E, _ = oracle.recon_erode(marker, mask, conn)
+    assert (mask <= E).all() and (E <= np.maximum(marker, mask)).all()
+    # a fixed point of the elementary geodesic erosion, and idempotent
+    fp = refs.footprint(conn)
+    step = np.maximum(refs.ndi.grey_erosion(E, footprint=fp, mode="constant",
+                                            cval=refs.maxval(E.dtype)), mask)
+    np.testing.assert_array_equal(step, E)
+    E2, _ = oracle.recon_erode(E, mask, conn)
+    np.testing.assert_array_equal(E2, E)
+    # 8-connectivity reaches at least as far down as 4-connectivity
+    if conn == 8:
+        E4, _ = oracle.recon_erode(marker, mask, 4)
+        assert (E <= E4).all()
