@@ -16,7 +16,7 @@ tile) x 3 bytes per pixel (read J, read the mask, write J), over the launch's
 duration measured with HIP events on the call's stream during the timed
 steps. ``--gpus`` above 1 is refused: the library runs on one GPU.
 
-Two more legs are added to the same line (``--legs``):
+Three more legs are added to the same line (``--legs``):
 
 * ``batched``: 512 uneven u8 tiles (sides log-uniform 256-4096, per-tile
   seeds, ~1.0 Gpixel in all), reconstruction 8-conn: one ``mr_recon_dilate``
@@ -33,6 +33,10 @@ Two more legs are added to the same line (``--legs``):
   passes afterwards hash every result of the sequential path and of the
   server (back to back and on the trace), which must agree job by job; a
   sample of jobs is checked against the oracle.
+* ``erode``: reconstruction by erosion (``mr_recon_erode``) on a 16384 x
+  16384 u8 image, 8-conn, the same mask with the marker raised by 30: a
+  complement pass, the reconstruction by dilation, the complement back.
+  Checked against the oracle.
 
 ``--atomic-probe`` instead times the device atomic-rate probe
 (``mr_probe_atomics``: relaxed device-scope add, and load + compare-and-swap,
@@ -242,6 +246,51 @@ def leg_batched(args, dev) -> dict:
         "bit_exact": bool(exact and same) if not args.no_verify else None,
         "batched_equals_per_tile": same,
     }
+
+
+def leg_erode(args, dev) -> dict:
+    """Reconstruction by erosion on the headline's image size: complement
+    pass, reconstruction by dilation, complement back, on fresh marker copies
+    resident in HBM."""
+    import torch
+    from paper_1311_0378_amd import mrecon, synth
+
+    S, conn = 16384, 8
+    t0 = time.time()
+    marker, mask = synth.make_erode_tile(S, S, 12800, 0, "u8", 0.0)
+    log(f"erode: generated {S}x{S} u8 in {time.time() - t0:.1f}s")
+    d_mask = torch.from_numpy(mask).to(dev)
+    d_src = torch.from_numpy(marker).to(dev)
+    K, W = args.steps, args.warmup
+    wsb = mrecon.erode_workspace_bytes(S, S, S, torch.uint8, conn)
+    copies = [torch.empty_like(d_src) for _ in range(K)]
+    ws = mrecon.alloc_workspace(wsb, dev)
+    stream = torch.cuda.current_stream()
+    for i in range(W):
+        copies[0].copy_(d_src)
+        mrecon.recon_erode(copies[0], d_mask, conn, workspace=ws, stream=stream)
+    for c in copies:
+        c.copy_(d_src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for i in range(K):
+        mrecon.recon_erode(copies[i], d_mask, conn, workspace=ws, stream=stream)
+    b.record(stream)
+    b.synchronize()
+    ms = a.elapsed_time(b) / K
+    out = {"workload": f"recon_erode {S}x{S} u8 conn{conn}, 12800 disks, seed 0, "
+                       "marker = min(mask + 30, 255)",
+           "mpx_s": round(S * S / ms / 1e3, 1), "ms_per_call": round(ms, 4),
+           "complement_bytes_per_call": 6 * S * S}
+    log(f"erode: {ms:.3f} ms per call")
+    if not args.no_verify:
+        import oracle
+        want, _ = oracle.recon_erode(marker, mask, conn)
+        out["bit_exact"] = bool(np.array_equal(copies[K - 1].cpu().numpy(), want))
+        log("erode: bit-exact vs oracle:", out["bit_exact"])
+    del copies, ws, d_mask, d_src
+    return out
 
 
 def leg_served(args, dev) -> dict:
@@ -474,8 +523,9 @@ def main():
     ap.add_argument("--dtype", default="u8", choices=["u8", "i32"])
     ap.add_argument("--conn", type=int, default=8, choices=[4, 8])
     ap.add_argument("--tune", default="", help="k=v,... overrides of mr_tune")
-    ap.add_argument("--legs", default="batched,served",
-                    help="extra legs after the headline: comma list of batched, served, or none")
+    ap.add_argument("--legs", default="batched,served,erode",
+                    help="extra legs after the headline: comma list of batched, served, erode, "
+                         "or none")
     ap.add_argument("--batch-n", type=int, default=512)
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--serve-n", type=int, default=2000)
@@ -664,7 +714,7 @@ def main():
                 "sample": f"the whole {S}x{S} {dt} image, one sequential oracle run "
                           f"({t_or:.1f} s) on {cpu_model()}, {os.cpu_count()} threads visible"}
     legs = [x for x in args.legs.split(",") if x and x != "none"]
-    unknown = set(legs) - {"batched", "served"}
+    unknown = set(legs) - {"batched", "served", "erode"}
     if unknown:
         raise SystemExit(f"unknown legs: {sorted(unknown)}")
     del copies, wss, d_mask, d_src
@@ -674,6 +724,9 @@ def main():
         torch.cuda.empty_cache()
     if "served" in legs:
         result["served"] = leg_served(args, dev)
+        torch.cuda.empty_cache()
+    if "erode" in legs:
+        result["erode"] = leg_erode(args, dev)
     print(json.dumps(result), flush=True)
 
 

@@ -135,6 +135,24 @@ int mr_recon_dilate(void *marker_inout, const void *mask, int64_t H, int64_t W, 
 int mr_fill_holes(void *img_inout, int64_t H, int64_t W, int64_t pitch, mr_dtype t, int conn,
                   void *ws, size_t ws_bytes, const mr_tune *tune, void *stream);
 
+/* Reconstruction by erosion, the dual of Table II's reconstruction (after
+ * Vincent 1993): E = the greatest image J <= max(marker, mask) that is stable
+ * under J(p) <- max(mask(p), min of J over p and its G-neighbours). Marker
+ * pixels below the mask are raised to it (no error). Computed as
+ * NOT R(NOT marker, NOT mask) with the bitwise complement: NOT mask goes into
+ * the workspace, the marker is complemented in place, reconstructed by
+ * dilation and complemented back.
+ * Arguments as for mr_recon_dilate; ws_bytes must be at least
+ * mr_recon_erode_workspace_bytes(H, W, pitch, ...), which also covers a
+ * plane of H x pitch pixels. mask is read only.
+ * Errors: as mr_recon_dilate, checked before anything is enqueued. After
+ * MR_EHIP the marker's contents are unspecified. */
+size_t mr_recon_erode_workspace_bytes(int64_t H, int64_t W, int64_t pitch, mr_dtype t, int conn,
+                                      const mr_tune *tune);
+int mr_recon_erode(void *marker_inout, const void *mask, int64_t H, int64_t W, int64_t pitch,
+                   mr_dtype t, int conn, void *ws, size_t ws_bytes, const mr_tune *tune,
+                   void *stream);
+
 /* ------------------------------------------------------------- batches */
 
 /* One image of a batch (the tiles of a whole-slide image are independent

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmrecon.so")
-SOURCES = ["mr_kernels.hip", "mr_api.hip", "mr_server.hip", "mr_probe.hip"]
+SOURCES = ["mr_kernels.hip", "mr_api.hip", "mr_server.hip", "mr_probe.hip", "mr_erode.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -91,6 +91,12 @@ def lib():
         L.mr_fill_holes.argtypes = [vp, i64, i64, i64, c_int, c_int, vp, sz,
                                     ctypes.POINTER(Tune), vp]
         L.mr_fill_holes.restype = c_int
+        L.mr_recon_erode_workspace_bytes.argtypes = [i64, i64, i64, c_int, c_int,
+                                                     ctypes.POINTER(Tune)]
+        L.mr_recon_erode_workspace_bytes.restype = sz
+        L.mr_recon_erode.argtypes = [vp, vp, i64, i64, i64, c_int, c_int, vp, sz,
+                                     ctypes.POINTER(Tune), vp]
+        L.mr_recon_erode.restype = c_int
         L.mr_read_counters.argtypes = [vp, ctypes.POINTER(Counters), vp]
         L.mr_read_counters.restype = c_int
         L.mr_read_round_tiles.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), i32,
@@ -222,6 +228,30 @@ def recon_dilate(marker: torch.Tensor, mask: torch.Tensor, conn: int = 8, tune=N
     _check(lib().mr_recon_dilate(marker.data_ptr(), mask.data_ptr(), H, W, pitch, t, conn,
                                  workspace.data_ptr(), workspace.numel(), _tune_ptr(tune),
                                  _stream_ptr(stream)))
+    return marker
+
+
+def erode_workspace_bytes(H: int, W: int, pitch: int, dtype: torch.dtype, conn: int,
+                          tune=None) -> int:
+    n = lib().mr_recon_erode_workspace_bytes(H, W, pitch, _DTYPES[dtype], conn, _tune_ptr(tune))
+    if n == 0:
+        raise MrError(MR_EINVAL, lib().mr_last_error().decode())
+    return int(n)
+
+
+def recon_erode(marker: torch.Tensor, mask: torch.Tensor, conn: int = 8, tune=None,
+                workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Reconstruction by erosion of ``marker`` over ``mask``, in place in
+    ``marker`` (returned). Enqueued on ``stream`` (default: current)."""
+    H, W, pitch, t = _image_args(marker)
+    if mask.shape != marker.shape or mask.dtype != marker.dtype or mask.stride() != marker.stride():
+        raise ValueError("mask must match the marker's shape, dtype and strides")
+    if workspace is None:
+        workspace = alloc_workspace(erode_workspace_bytes(H, W, pitch, marker.dtype, conn, tune),
+                                    marker.device)
+    _check(lib().mr_recon_erode(marker.data_ptr(), mask.data_ptr(), H, W, pitch, t, conn,
+                                workspace.data_ptr(), workspace.numel(), _tune_ptr(tune),
+                                _stream_ptr(stream)))
     return marker
 
 

@@ -181,3 +181,39 @@ def test_probe_atomics_rejects(L, words, n, kind, per_lane, waves):
     assert L.mr_probe_atomics(ctypes.c_void_p(words), n, kind, per_lane, waves, 0, None) \
         == mrecon.MR_EINVAL
     assert L.mr_last_error().startswith(b"probe:")
+
+
+def test_erode_workspace_bytes():
+    import torch
+    r = mrecon.workspace_bytes(mrecon.MR_OP_RECON, 100, 100, torch.uint8, 8)
+    e = mrecon.erode_workspace_bytes(100, 100, 0, torch.uint8, 8)
+    e_pitched = mrecon.erode_workspace_bytes(100, 100, 160, torch.uint8, 8)
+    e32 = mrecon.erode_workspace_bytes(100, 100, 0, torch.int32, 8)
+    assert e >= r + 100 * 100 and e_pitched >= r + 100 * 160 and e32 >= r + 4 * 100 * 100
+
+
+@pytest.mark.parametrize("H,W,pitch,t,conn", [
+    (0, 10, 0, 1, 8), (10, 10, 5, 1, 8), (10, 10, 0, 2, 8), (10, 10, 0, 1, 6),
+    (1 << 20, 1 << 14, 0, 1, 8)])
+def test_erode_workspace_bytes_invalid(L, H, W, pitch, t, conn):
+    assert L.mr_recon_erode_workspace_bytes(H, W, pitch, t, conn, None) == 0
+    assert L.mr_last_error()
+
+
+def _erode(L, marker=FAKE, mask=FAKE, H=8, W=8, pitch=0, t=1, conn=8, ws=FAKE,
+           ws_bytes=1 << 30, tune=None):
+    return L.mr_recon_erode(ctypes.c_void_p(marker), ctypes.c_void_p(mask), H, W, pitch, t,
+                            conn, ctypes.c_void_p(ws), ws_bytes, tune, None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(marker=0), mrecon.MR_EINVAL), (dict(mask=0), mrecon.MR_EINVAL),
+    (dict(ws=0), mrecon.MR_EINVAL), (dict(H=0), mrecon.MR_EINVAL), (dict(W=-3), mrecon.MR_EINVAL),
+    (dict(pitch=4), mrecon.MR_EINVAL), (dict(conn=6), mrecon.MR_EINVAL),
+    (dict(t=2), mrecon.MR_EINVAL), (dict(ws=FAKE + 8), mrecon.MR_EINVAL),
+    (dict(t=4, marker=FAKE + 2), mrecon.MR_EINVAL), (dict(t=4, mask=FAKE + 1), mrecon.MR_EINVAL),
+    (dict(ws_bytes=100), mrecon.MR_ENOMEM),
+])
+def test_erode_rejects(L, kw, code):
+    assert _erode(L, **kw) == code
+    assert L.mr_last_error()

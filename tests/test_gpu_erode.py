@@ -1,0 +1,74 @@
+"""Reconstruction by erosion on the GPU (mr_recon_erode) against the oracle,
+element by element: ragged shapes over several tiles, both pixel types, both
+connectivities, pitched rows, the clip of a marker below the mask, and the
+synthetic 4096 x 4096 workload."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # collected on CPU-only hosts too
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+from gpu_util import to_dev  # noqa: E402
+from paper_1311_0378_amd import mrecon, synth  # noqa: E402
+
+
+def gpu_erode(marker, mask, conn, tune=None, pad=0):
+    m, k = to_dev(marker, pad), to_dev(mask, pad)
+    print(f"[gpu] erode {marker.shape} {marker.dtype} conn{conn} tune={tune} pad={pad}",
+          flush=True)
+    mrecon.recon_erode(m, k, conn, tune=tune)
+    out = m.cpu().numpy()
+    np.testing.assert_array_equal(k.cpu().numpy(), mask)  # the mask is read only
+    return out
+
+
+@pytest.mark.parametrize("dt", ["u8", "i32"])
+@pytest.mark.parametrize("conn", [4, 8])
+@pytest.mark.parametrize("shape", [(1, 1), (1, 300), (257, 1), (63, 65), (200, 333),
+                                   (517, 129)])
+def test_erode_random_shapes(shape, conn, dt):
+    H, W = shape
+    marker, mask = synth.make_erode_tile(H, W, max(1, H * W // 4000), H * 7 + W, dt, 0.2)
+    want, _ = oracle.recon_erode(marker, mask, conn)
+    np.testing.assert_array_equal(gpu_erode(marker, mask, conn), want)
+
+
+@pytest.mark.parametrize("tune", [None, dict(sweep_rounds=2, max_sweeps=2),
+                                  dict(sweep_rounds=-1, tail_rounds=0)],
+                         ids=["default", "rounds+queue", "converge"])
+@pytest.mark.parametrize("conn", [4, 8])
+def test_erode_tunes(tune, conn):
+    marker, mask = synth.make_erode_tile(300, 420, 40, 3, "u8", 0.3)
+    want, _ = oracle.recon_erode(marker, mask, conn)
+    np.testing.assert_array_equal(gpu_erode(marker, mask, conn, tune=tune), want)
+
+
+@pytest.mark.parametrize("dt", ["u8", "i32"])
+def test_erode_pitched_and_clipped(dt):
+    rng = np.random.default_rng(5)
+    marker, mask = synth.make_erode_tile(130, 190, 12, 8, dt, 0.0)
+    # some marker pixels below the mask: raised to it
+    low = rng.random(mask.shape) < 0.05
+    marker = np.where(low, np.minimum(marker, mask // 2), marker).astype(mask.dtype)
+    want, _ = oracle.recon_erode(marker, mask, 8)
+    np.testing.assert_array_equal(gpu_erode(marker, mask, 8, pad=37), want)
+
+
+def test_erode_i32_full_range():
+    rng = np.random.default_rng(11)
+    mask = rng.integers(-2**31, 2**31, (150, 170), dtype=np.int64).astype(np.int32)
+    marker = rng.integers(-2**31, 2**31, (150, 170), dtype=np.int64).astype(np.int32)
+    for conn in (4, 8):
+        want, _ = oracle.recon_erode(marker, mask, conn)
+        np.testing.assert_array_equal(gpu_erode(marker, mask, conn), want)
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_erode_workload_4096(conn):
+    marker, mask = synth.make_erode_tile(4096, 4096, 800, 0, "u8", 0.05)
+    want, _ = oracle.recon_erode(marker, mask, conn)
+    np.testing.assert_array_equal(gpu_erode(marker, mask, conn), want)
