@@ -266,23 +266,28 @@ def leg_erode(args, dev) -> dict:
     copies = [torch.empty_like(d_src) for _ in range(K)]
     ws = mrecon.alloc_workspace(wsb, dev)
     stream = torch.cuda.current_stream()
+    tune = None
+    if args.erode_tune:
+        tune = {k: int(v) for k, v in (kv.split("=") for kv in args.erode_tune.split(","))}
     for i in range(W):
         copies[0].copy_(d_src)
-        mrecon.recon_erode(copies[0], d_mask, conn, workspace=ws, stream=stream)
+        mrecon.recon_erode(copies[0], d_mask, conn, tune=tune, workspace=ws, stream=stream)
     for c in copies:
         c.copy_(d_src)
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record(stream)
     for i in range(K):
-        mrecon.recon_erode(copies[i], d_mask, conn, workspace=ws, stream=stream)
+        mrecon.recon_erode(copies[i], d_mask, conn, tune=tune, workspace=ws, stream=stream)
     b.record(stream)
     b.synchronize()
     ms = a.elapsed_time(b) / K
+    cnt = mrecon.read_counters(ws)
     out = {"workload": f"recon_erode {S}x{S} u8 conn{conn}, 12800 disks, seed 0, "
                        "marker = min(mask + 30, 255)",
            "mpx_s": round(S * S / ms / 1e3, 1), "ms_per_call": round(ms, 4),
-           "complement_bytes_per_call": 6 * S * S}
+           "complement_bytes_per_call": 6 * S * S, "tune": tune or "library default",
+           "counters_last_call": {k: cnt[k] for k in ("rounds", "tiles", "pops", "sweeps")}}
     log(f"erode: {ms:.3f} ms per call")
     if not args.no_verify:
         import oracle
@@ -526,6 +531,9 @@ def main():
     ap.add_argument("--legs", default="batched,served,erode",
                     help="extra legs after the headline: comma list of batched, served, erode, "
                          "or none")
+    ap.add_argument("--erode-tune", default="sweep_rounds=-1,tail_rounds=0",
+                    help="k=v,... mr_tune overrides for the erode leg (default: tile rounds until "
+                         "none is dirty, the fastest schedule measured for that workload)")
     ap.add_argument("--batch-n", type=int, default=512)
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--serve-n", type=int, default=2000)
