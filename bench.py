@@ -276,18 +276,34 @@ def leg_erode(args, dev) -> dict:
         c.copy_(d_src)
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    mrecon.timing_enable("spans")  # as in the headline's timed steps
     a.record(stream)
     for i in range(K):
         mrecon.recon_erode(copies[i], d_mask, conn, tune=tune, workspace=ws, stream=stream)
     b.record(stream)
     b.synchronize()
+    mrecon.timing_enable(False)
+    recs = mrecon.timing_collect()
     ms = a.elapsed_time(b) / K
     cnt = mrecon.read_counters(ws)
+    # the tile rounds of the last call: its records follow the last round-1 record
+    first = max(i for i, r in enumerate(recs) if r[0] == "tile_round" and r[1] == 1)
+    tr = [r for r in recs[first:] if r[0] == "tile_round"]
+    tile_ms = sum(r[2] for r in tr)
+    rt = mrecon.read_round_tiles(ws)
+    visits = sum(rt[:-1])
+    n_tiles = ((S + 61) // 62) ** 2
+    achieved = visits * 3 * S * S / n_tiles / (tile_ms * 1e-3) / 1e9
     out = {"workload": f"recon_erode {S}x{S} u8 conn{conn}, 12800 disks, seed 0, "
                        "marker = min(mask + 30, 255)",
            "mpx_s": round(S * S / ms / 1e3, 1), "ms_per_call": round(ms, 4),
            "complement_bytes_per_call": 6 * S * S, "tune": tune or "library default",
-           "counters_last_call": {k: cnt[k] for k in ("rounds", "tiles", "pops", "sweeps")}}
+           "counters_last_call": {k: cnt[k] for k in ("rounds", "tiles", "pops", "sweeps")},
+           "roofline_tile_round_last_call": {
+               "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+               "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+               "launches": sum(r[3] for r in tr), "tile_round_ms": round(tile_ms, 4),
+               "timing": "spans"}}
     log(f"erode: {ms:.3f} ms per call")
     if not args.no_verify:
         import oracle
