@@ -11,7 +11,9 @@
 //  2. the reconstruction by dilation runs on the two (mr_recon_dilate, with
 //     the head of the workspace);
 //  3. one pass complements the marker back.
-// The passes are plain streaming kernels: each wave walks 512 consecutive
+// The passes are plain streaming kernels. Where rows and pointers are
+// 16-byte aligned each lane moves 16-byte words; otherwise (and for the
+// columns past a row's last whole word) each wave walks 512 consecutive
 // pixels of one row, 64 lanes on consecutive pixels per access.
 #include <algorithm>
 #include <cstdio>
@@ -58,9 +60,51 @@ __global__ __launch_bounds__(256) void k_not_planes(T *__restrict__ a, const T *
     }
 }
 
+// The same on 16-byte words, for rows whose start and pitch are 16-byte
+// aligned: bitwise NOT of the raw bits complements u8 and i32 pixels alike.
+// vecs = whole 16-byte words per row, vpitch = the pitch in 16-byte words.
+__global__ __launch_bounds__(256) void k_not_planes16(uint4 *__restrict__ a,
+                                                      const uint4 *__restrict__ b,
+                                                      uint4 *__restrict__ b_not, int64_t H,
+                                                      int64_t vecs, int64_t vpitch) {
+    const int64_t items = H * vecs;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < items;
+         i += (int64_t)gridDim.x * 256) {
+        const int64_t y = i / vecs;
+        const int64_t o = y * vpitch + (i - y * vecs);
+        const uint4 va = a[o];
+        if (b) {
+            const uint4 vb = b[o];
+            b_not[o] = make_uint4(~vb.x, ~vb.y, ~vb.z, ~vb.w);
+        }
+        a[o] = make_uint4(~va.x, ~va.y, ~va.z, ~va.w);
+    }
+}
+
 template <typename T>
 hipError_t launch_not(T *a, const T *b, T *b_not, int64_t H, int64_t W, int64_t pitch,
                       hipStream_t s) {
+    const auto al16 = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
+    if ((pitch * (int64_t)sizeof(T)) % 16 == 0 && al16(a) && (!b || (al16(b) && al16(b_not)))) {
+        const int64_t vecs = W * (int64_t)sizeof(T) / 16;
+        if (vecs > 0) {
+            const int64_t blocks = std::min<int64_t>((H * vecs + 255) / 256, 1 << 16);
+            hipLaunchKernelGGL(k_not_planes16, dim3((unsigned)blocks), dim3(256), 0, s,
+                               (uint4 *)a, (const uint4 *)b, (uint4 *)b_not, H, vecs,
+                               pitch * (int64_t)sizeof(T) / 16);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        // the columns past the last whole word, element by element
+        const int64_t xv = vecs * 16 / (int64_t)sizeof(T);
+        if (xv == W) return hipSuccess;
+        a += xv;
+        if (b) {
+            b += xv;
+            b_not += xv;
+        }
+        W -= xv;
+    }
     const int64_t segs = (W + NOT_SEG - 1) / NOT_SEG;
     const int64_t blocks = std::min<int64_t>((H * segs + 3) / 4, 1 << 16);
     hipLaunchKernelGGL((k_not_planes<T>), dim3((unsigned)blocks), dim3(256), 0, s, a, b, b_not, H,

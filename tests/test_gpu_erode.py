@@ -72,3 +72,15 @@ def test_erode_workload_4096(conn):
     marker, mask = synth.make_erode_tile(4096, 4096, 800, 0, "u8", 0.05)
     want, _ = oracle.recon_erode(marker, mask, conn)
     np.testing.assert_array_equal(gpu_erode(marker, mask, conn), want)
+
+
+@pytest.mark.parametrize("dt,H,W,pad", [("u8", 70, 333, 19), ("i32", 70, 333, 3),
+                                        ("u8", 9, 64, 0), ("u8", 5, 15, 1), ("i32", 66, 300, 0)],
+                         ids=["u8-words+tail", "i32-words+tail", "u8-words", "u8-no-word",
+                              "i32-words"])
+def test_erode_complement_paths(dt, H, W, pad):
+    # rows whose pitch is a multiple of 16 bytes take the 16-byte-word pass; the
+    # columns past a row's last whole word take the element pass
+    marker, mask = synth.make_erode_tile(H, W, 3, H + W, dt, 0.1)
+    want, _ = oracle.recon_erode(marker, mask, 8)
+    np.testing.assert_array_equal(gpu_erode(marker, mask, 8, pad=pad), want)
