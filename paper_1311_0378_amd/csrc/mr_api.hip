@@ -222,13 +222,26 @@ struct RoundSpan {
     ~RoundSpan() { close(); }
 };
 
-// Pinned words the converge mode polls through (one round's band counts).
-unsigned long long *host_word() {
-    static thread_local unsigned long long *w = nullptr;
-    if (!w && hipHostMalloc((void **)&w, sizeof(uint32_t) * NBANDS, hipHostMallocDefault) !=
+// Pinned words the converge mode polls through: two slots of one round's
+// band counts, so that one slot is read while the other's copy is in flight.
+uint32_t *host_words() {
+    static thread_local uint32_t *w = nullptr;
+    if (!w && hipHostMalloc((void **)&w, sizeof(uint32_t) * 2 * NBANDS, hipHostMallocDefault) !=
                   hipSuccess)
         w = nullptr;
     return w;
+}
+
+// The events that mark each slot's copy complete (default flags: the host
+// reads the copied words after waiting on them).
+hipEvent_t *poll_events() {
+    static thread_local hipEvent_t ev[2] = {nullptr, nullptr};
+    for (int i = 0; i < 2; ++i)
+        if (!ev[i] && hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess) {
+            ev[i] = nullptr;
+            return nullptr;
+        }
+    return ev;
 }
 
 uint64_t round_total(const Ctrl &h, size_t r) {
@@ -334,14 +347,19 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
         }
         if (e != hipSuccess) return hip_fail(e, "tile queue");
     } else {
-        // converge mode: rounds until a round leaves no dirty tile, polling
-        // every few rounds
-        unsigned long long *hw = host_word();
-        if (!hw) return fail(MR_EHIP, "cannot allocate a pinned host word");
+        // converge mode: rounds until a round leaves no dirty tile, in
+        // batches of 8, each followed by a copy of the next round's list
+        // lengths to the host. The host reads a batch's count one batch
+        // behind: the next batch is already enqueued while it waits, so the
+        // device does not idle on the poll. A batch enqueued after the last
+        // dirty round finds empty lists and changes nothing.
+        uint32_t *hw = host_words();
+        hipEvent_t *ev = poll_events();
+        if (!hw || !ev) return fail(MR_EHIP, "cannot allocate the pinned poll words or events");
         const uint32_t poll = 8;
         const uint32_t cap = tn.converge_rounds > 0 ? (uint32_t)tn.converge_rounds : MAX_ROUNDS;
         bool left = false; // work still listed after `cap` rounds
-        while (true) {
+        auto batch = [&](int slot) -> hipError_t {
             for (uint32_t k = 0; k < poll && round < cap; ++k) {
                 ++round;
                 span.begin(round);
@@ -350,21 +368,31 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
                     e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl,
                                           round, tn.max_sweeps, grid, s, op_all);
                 }
-                if (e != hipSuccess) return hip_fail(e, "tile round");
+                if (e != hipSuccess) return e;
                 span.add();
             }
-            span.close(); // the host waits below
-            if ((e = hipMemcpyAsync(hw, ctrl->round_tiles[round + 1], sizeof(uint32_t) * NBANDS,
-                                    hipMemcpyDeviceToHost, s)) != hipSuccess)
-                return hip_fail(e, "poll copy");
-            if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "poll sync");
+            span.close(); // the host may wait after this batch
+            if ((e = hipMemcpyAsync(hw + slot * NBANDS, ctrl->round_tiles[round + 1],
+                                    sizeof(uint32_t) * NBANDS, hipMemcpyDeviceToHost, s)) !=
+                hipSuccess)
+                return e;
+            return hipEventRecord(ev[slot], s);
+        };
+        int slot = 0;
+        if ((e = batch(slot)) != hipSuccess) return hip_fail(e, "tile round batch");
+        while (true) {
+            const bool ahead = round < cap; // room for one more batch
+            if (ahead && (e = batch(slot ^ 1)) != hipSuccess)
+                return hip_fail(e, "tile round batch");
+            if ((e = hipEventSynchronize(ev[slot])) != hipSuccess) return hip_fail(e, "poll");
             uint64_t next = 0;
-            for (int b = 0; b < NBANDS; ++b) next += ((const uint32_t *)hw)[b];
-            if (next == 0) break;
-            if (round >= cap) {
+            for (int b = 0; b < NBANDS; ++b) next += hw[slot * NBANDS + b];
+            if (next == 0) break; // converged; a batch enqueued ahead is empty
+            if (!ahead) {         // this count was taken at the cap
                 left = true;
                 break;
             }
+            slot ^= 1;
         }
         if ((e = launch_store_u64(&ctrl->rounds, (unsigned long long)round, s)) != hipSuccess)
             return hip_fail(e, "store");
