@@ -756,7 +756,8 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
 // One tile round on a persistent grid (two waves per SIMD). Block b serves
 // band b % NBANDS and visits either every tile of the band (all_tiles) or the
 // band's dirty list. Tiles are dealt to the band's blocks by static
-// interleave, so no block gets more than one tile above another. A tile
+// interleave, so no block gets more than one tile above another. A round that
+// lists at most one tile per block deals across bands instead. A tile
 // builds its image's initial working values in the image's first round.
 // V selects the visit: -1 dispatches per tile on the image's op and first
 // round (mixed batches, the server); otherwise (FILL << 1) | INITIAL for
@@ -773,12 +774,43 @@ __global__ __launch_bounds__(64, 2) void k_tile_round(Imgs imgs, int64_t n_tiles
     __shared__ uint32_t tb[TS][TS + 1]; // transpose buffer (and load stage)
     __shared__ uint32_t abuf[APP_CAP];
     const int lane = threadIdx.x;
-    const int band = blockIdx.x % NBANDS;
-    const int64_t local = blockIdx.x / NBANDS, per = gridDim.x / NBANDS;
+    int band = blockIdx.x % NBANDS;
+    int64_t local = blockIdx.x / NBANDS, per = gridDim.x / NBANDS, n;
+    if (all_tiles) {
+        n = band_lo(n_tiles, band + 1) - band_lo(n_tiles, band);
+    } else {
+        // A round that lists no more tiles than the grid has blocks gives each
+        // tile a block of its own. The tail of a flood often sits in one or
+        // two bands, whose blocks would otherwise visit its tiles one after
+        // another while the rest of the grid idles. Block g takes entry g of
+        // the band lists laid end to end.
+        uint32_t c[NBANDS], total = 0;
+#pragma unroll
+        for (int q = 0; q < NBANDS; ++q) {
+            c[q] = counts_in[q];
+            total += c[q];
+        }
+        if (total <= gridDim.x) {
+            uint32_t i = blockIdx.x, cb = c[0];
+            int b = 0;
+#pragma unroll
+            for (int q = 0; q < NBANDS - 1; ++q)
+                if (b == q && i >= c[q]) {
+                    i -= c[q];
+                    b = q + 1;
+                    cb = c[q + 1];
+                }
+            band = b;
+            local = i;
+            per = cb > 0 ? cb : 1; // one iteration: entry i (or n - 1 - i backward)
+            n = blockIdx.x < total ? cb : 0;
+        } else {
+            n = counts_in[band];
+        }
+    }
     const int64_t lo = band_lo(n_tiles, band);
     Appender app{abuf, 0, lists + ((round + 1) & 1) * n_tiles, counts_out, n_tiles};
     const uint32_t *list_in = lists + (round & 1) * n_tiles + lo;
-    const int64_t n = all_tiles ? band_lo(n_tiles, band + 1) - lo : (int64_t)counts_in[band];
     // Odd rounds walk the band forward, even rounds backward: a tile stored
     // early in a round is read by tiles visited later in it, so information
     // travels down the image within odd rounds and up it within even ones,
