@@ -757,7 +757,8 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
 // band b % NBANDS and visits either every tile of the band (all_tiles) or the
 // band's dirty list. Tiles are dealt to the band's blocks by static
 // interleave, so no block gets more than one tile above another. A round that
-// lists at most one tile per block deals across bands instead. A tile
+// lists at most one tile per block, but more in some band than that band has
+// blocks, deals across bands instead. A tile
 // builds its image's initial working values in the image's first round.
 // V selects the visit: -1 dispatches per tile on the image's op and first
 // round (mixed batches, the server); otherwise (FILL << 1) | INITIAL for
@@ -779,18 +780,22 @@ __global__ __launch_bounds__(64, 2) void k_tile_round(Imgs imgs, int64_t n_tiles
     if (all_tiles) {
         n = band_lo(n_tiles, band + 1) - band_lo(n_tiles, band);
     } else {
-        // A round that lists no more tiles than the grid has blocks gives each
-        // tile a block of its own. The tail of a flood often sits in one or
-        // two bands, whose blocks would otherwise visit its tiles one after
-        // another while the rest of the grid idles. Block g takes entry g of
-        // the band lists laid end to end.
-        uint32_t c[NBANDS], total = 0;
+        // A round that lists no more tiles than the grid has blocks, but more
+        // in some band than that band has blocks, gives each tile a block of
+        // its own: the tail of a flood often sits in one or two bands, whose
+        // blocks would otherwise visit its tiles one after another while the
+        // rest of the grid idles. Block g takes entry g of the band lists laid
+        // end to end. When every band fits its blocks, the bands' dealing
+        // already gives each tile a block, and keeps neighbouring tiles on one
+        // die's L2.
+        uint32_t c[NBANDS], total = 0, cmax = 0;
 #pragma unroll
         for (int q = 0; q < NBANDS; ++q) {
             c[q] = counts_in[q];
             total += c[q];
+            cmax = c[q] > cmax ? c[q] : cmax;
         }
-        if (total <= gridDim.x) {
+        if (total <= gridDim.x && cmax > (uint32_t)per) {
             uint32_t i = blockIdx.x, cb = c[0];
             int b = 0;
 #pragma unroll
