@@ -101,9 +101,9 @@ static const int (*nbr_list(int conn, int *count))[2] {
 static inline int inside(int64_t y, int64_t x, int dy, int dx, int64_t H, int64_t W) {
     int64_t yy = y + dy, xx = x + dx;
 #if MRO_PLANT == 5
-    /* planted: rows wrap around at the right edge */
-    (void)W;
-    return yy >= 0 && yy < H && xx >= 0;
+    /* planted: rows wrap around at the right edge (onto the next row; never
+     * past the last pixel, so the planted copy stays inside its arrays) */
+    return yy >= 0 && yy < H && xx >= 0 && yy * W + xx < H * W;
 #else
     return yy >= 0 && yy < H && xx >= 0 && xx < W;
 #endif
