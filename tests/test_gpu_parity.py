@@ -192,3 +192,27 @@ def test_workload_4096_fill(w4096, conn):
     img = w4096[2]
     want, _ = oracle.fill_holes(img, conn)
     check(gpu_fill(img, conn), want)
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_converge_batches_and_cap(conn):
+    """Converge mode enqueues the next batch of 8 rounds before it reads the
+    previous batch's count. A cap that falls inside a batch enqueued ahead
+    stops the rounds there and hands the rest to the queue phase; without a
+    cap the rounds run in whole batches until none is dirty."""
+    from test_oracle_pins import serpentine
+    # a corridor through 10 x 12 tiles needs far more rounds than the caps
+    marker, mask = serpentine(600, 700, 11)
+    want, _ = oracle.recon_dilate(marker, mask, conn)
+    for cap in (12, 20):
+        tune = dict(sweep_rounds=-1, tail_rounds=0, converge_rounds=cap, max_sweeps=1)
+        got, c = gpu_recon(marker, mask, conn, tune=tune, counters=True)
+        check(got, want)
+        assert c["rounds"] == cap and c["pops"] > 0
+    # a corridor through 3 x 3 tiles converges in rounds alone
+    marker, mask = serpentine(127, 129, 7)
+    want, _ = oracle.recon_dilate(marker, mask, conn)
+    got, c = gpu_recon(marker, mask, conn, tune=dict(sweep_rounds=-1, tail_rounds=0),
+                       counters=True)
+    check(got, want)
+    assert c["rounds"] < 1000 and (c["rounds"] - 1) % 8 == 0 and c["pops"] == 0
