@@ -315,7 +315,9 @@ def leg_erode(args, dev) -> dict:
 
 
 def leg_served(args, dev) -> dict:
-    """Serving trace: sequential per-job launches versus the server."""
+    """Serving trace: sequential per-job launches versus the server, with the
+    jobs in host memory (PCIe in and out) and with the jobs already in HBM
+    (device-to-device copies into and out of the arena)."""
     import torch
     import xxhash
     import oracle
@@ -327,46 +329,41 @@ def leg_served(args, dev) -> dict:
     t0 = time.time()
     bm, bk, bf = synth.serving_banks()
     side = bm.shape[1]
-    pm, pk, pf = (torch.from_numpy(x).pin_memory() for x in (bm, bk, bf))
     npx = sum(H * W for _, H, W in jobs)
     log(f"served: {n} jobs, {npx / 1e9:.2f} Gpx, banks ready in {time.time() - t0:.1f}s")
+
+    # every job's oracle result, hashed, on the host's cores after the GPU
+    # passes (run beside them it would hold the interpreter lock in its array
+    # copies and delay the serving loop)
+    def oracle_hash(i):
+        kind, H, W = jobs[i]
+        y, x = wins[i]
+        if kind == "recon":
+            want = oracle.recon_dilate(np.ascontiguousarray(bm[y:y + H, x:x + W]),
+                                       np.ascontiguousarray(bk[y:y + H, x:x + W]), 8)[0]
+        else:
+            want = oracle.fill_holes(np.ascontiguousarray(bf[y:y + H, x:x + W]), 8)[0]
+        return xxhash.xxh3_64_intdigest(want)
+
     u8 = torch.uint8
     stream = torch.cuda.current_stream()
     hip = ctypes.CDLL(os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so"))
     hip.hipMemcpy2DAsync.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                      ctypes.c_size_t, ctypes.c_size_t, ctypes.c_size_t,
                                      ctypes.c_int, ctypes.c_void_p]
-    H2D, D2H = 1, 2
+    H2D, D2H, D2D = 1, 2, 3
+    max_jobs = args.serve_slots
+    arena = 8 << 30
 
     def copy2d(dst, dpitch, src, spitch, H, W, kind):
         rc = hip.hipMemcpy2DAsync(dst, dpitch, src, spitch, W, H, kind, stream.cuda_stream)
         if rc != 0:
             raise RuntimeError(f"hipMemcpy2DAsync failed ({rc})")
 
-    def views(i):
-        kind, H, W = jobs[i]
-        y, x = wins[i]
-        if kind == "recon":
-            return pm[y:y + H, x:x + W], pk[y:y + H, x:x + W]
-        return pf[y:y + H, x:x + W], None
-
-    max_jobs = args.serve_slots
-    # result buffers: H rows of W, 64-byte aligned row pitch, in pinned blocks
-    pool = queue.SimpleQueue()
-    for _ in range(max_jobs + 16):
-        pool.put(torch.empty(side * side, dtype=u8, pin_memory=True))
-
     def res_view(buf, i):
         _, H, W = jobs[i]
         ld = (W + 63) // 64 * 64
         return buf[:H * ld].view(H, ld)[:, :W]
-
-    def digest(i, buf, hashes):
-        hashes[i] = xxhash.xxh3_64_intdigest(np.ascontiguousarray(res_view(buf, i).numpy()))
-        pool.put(buf)
-
-    def recycle(i, buf, hashes):
-        pool.put(buf)
 
     d0 = torch.empty((side, side), dtype=u8, device=dev)
     d1 = torch.empty((side, side), dtype=u8, device=dev)
@@ -380,124 +377,160 @@ def leg_served(args, dev) -> dict:
                 return
             time.sleep(min(d, 2e-4))
 
-    def run_sequential(arr, hashing=False):
-        hasher = ThreadPoolExecutor(4)
-        consume = digest if hashing else recycle
-        hashes, lat, futs = [None] * n, [0.0] * n, []
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(n):
-            if arr is not None:
-                wait_until(t0 + arr[i])
+    def run_mode(where):
+        on_dev = where == "device"
+        if on_dev:
+            banks = [torch.from_numpy(x).to(dev) for x in (bm, bk, bf)]
+        else:
+            banks = [torch.from_numpy(x).pin_memory() for x in (bm, bk, bf)]
+        pm, pk, pf = banks
+        cin, cout = (D2D, D2D) if on_dev else (H2D, D2H)
+
+        def views(i):
             kind, H, W = jobs[i]
-            a, m = views(i)
-            buf = pool.get()
-            copy2d(d0.data_ptr(), side, a.data_ptr(), side, H, W, H2D)
-            if m is not None:
-                copy2d(d1.data_ptr(), side, m.data_ptr(), side, H, W, H2D)
-                mrecon.recon_dilate(d0[:H, :W], d1[:H, :W], 8, workspace=ws, stream=stream)
-            else:
-                mrecon.fill_holes(d0[:H, :W], 8, workspace=ws, stream=stream)
-            copy2d(buf.data_ptr(), (W + 63) // 64 * 64, d0.data_ptr(), side, H, W, D2H)
-            stream.synchronize()
-            lat[i] = time.perf_counter() - t0 - (arr[i] if arr is not None else 0.0)
-            futs.append(hasher.submit(consume, i, buf, hashes))
-        span = time.perf_counter() - t0 - (arr[0] if arr is not None else 0.0)
-        hasher.shutdown()
-        for f in futs:
-            f.result()
-        return hashes, lat, span
+            y, x = wins[i]
+            if kind == "recon":
+                return pm[y:y + H, x:x + W], pk[y:y + H, x:x + W]
+            return pf[y:y + H, x:x + W], None
 
-    arena = 8 << 30
+        # result buffers: H rows of W, 64-byte aligned row pitch, in blocks
+        # of host pinned memory or of HBM
+        pool = queue.SimpleQueue()
+        for _ in range(max_jobs + 16):
+            pool.put(torch.empty(side * side, dtype=u8, device=dev) if on_dev
+                     else torch.empty(side * side, dtype=u8, pin_memory=True))
 
-    def run_served(arr, hashing=False):
-        hasher = ThreadPoolExecutor(4)
-        consume = digest if hashing else recycle
-        srv = mrecon.Server(arena, max_jobs=max_jobs, dtype=u8, conn=8, device=dev,
-                            stream=stream, rounds_per_step=args.serve_rounds)
-        hashes, lat, futs = [None] * n, [0.0] * n, []
-        owned = {}
-        i = done = 0
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        while done < n:
-            now = time.perf_counter() - t0
-            while i < n and (arr is None or arr[i] <= now):
-                try:
-                    buf = pool.get_nowait()
-                except queue.Empty:
-                    break
+        def digest(i, buf, hashes):
+            r = res_view(buf, i)
+            r = r.cpu() if on_dev else r
+            hashes[i] = xxhash.xxh3_64_intdigest(np.ascontiguousarray(r.numpy()))
+            pool.put(buf)
+
+        def recycle(i, buf, hashes):
+            pool.put(buf)
+
+        def run_sequential(arr, hashing=False):
+            hasher = ThreadPoolExecutor(4)
+            consume = digest if hashing else recycle
+            hashes, lat, futs = [None] * n, [0.0] * n, []
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(n):
+                if arr is not None:
+                    wait_until(t0 + arr[i])
+                kind, H, W = jobs[i]
                 a, m = views(i)
-                jid = srv.submit(a, m, out=res_view(buf, i))
-                if jid is None:
-                    pool.put(buf)
-                    break
-                owned[jid] = (i, buf)
-                i += 1
-            if srv.stats()["resident"]:
-                srv.step()
-            elif i < n and arr is not None:
-                wait_until(t0 + arr[i])
-            for jid, _ in srv.poll():
-                k, buf = owned.pop(jid)
-                lat[k] = time.perf_counter() - t0 - (arr[k] if arr is not None else 0.0)
-                futs.append(hasher.submit(consume, k, buf, hashes))
-                done += 1
-        span = time.perf_counter() - t0 - (arr[0] if arr is not None else 0.0)
-        rounds = srv.stats()["rounds"]
-        srv.close()
-        hasher.shutdown()
-        for f in futs:
-            f.result()
-        return hashes, lat, span, rounds
+                buf = pool.get()
+                copy2d(d0.data_ptr(), side, a.data_ptr(), side, H, W, cin)
+                if m is not None:
+                    copy2d(d1.data_ptr(), side, m.data_ptr(), side, H, W, cin)
+                    mrecon.recon_dilate(d0[:H, :W], d1[:H, :W], 8, workspace=ws, stream=stream)
+                else:
+                    mrecon.fill_holes(d0[:H, :W], 8, workspace=ws, stream=stream)
+                copy2d(buf.data_ptr(), (W + 63) // 64 * 64, d0.data_ptr(), side, H, W, cout)
+                stream.synchronize()
+                lat[i] = time.perf_counter() - t0 - (arr[i] if arr is not None else 0.0)
+                futs.append(hasher.submit(consume, i, buf, hashes))
+            span = time.perf_counter() - t0 - (arr[0] if arr is not None else 0.0)
+            hasher.shutdown()
+            for f in futs:
+                f.result()
+            return hashes, lat, span
 
-    def summary(lat, span):
-        return {"mpx_s": round(npx / span / 1e6, 1), "latency_ms_p50": round(pct(lat, 50) * 1e3, 2),
-                "latency_ms_p99": round(pct(lat, 99) * 1e3, 2), "span_s": round(span, 3)}
+        def run_served(arr, hashing=False):
+            hasher = ThreadPoolExecutor(4)
+            consume = digest if hashing else recycle
+            srv = mrecon.Server(arena, max_jobs=max_jobs, dtype=u8, conn=8, device=dev,
+                                stream=stream, rounds_per_step=args.serve_rounds)
+            hashes, lat, futs = [None] * n, [0.0] * n, []
+            owned = {}
+            i = done = 0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            while done < n:
+                now = time.perf_counter() - t0
+                while i < n and (arr is None or arr[i] <= now):
+                    try:
+                        buf = pool.get_nowait()
+                    except queue.Empty:
+                        break
+                    a, m = views(i)
+                    jid = srv.submit(a, m, out=res_view(buf, i))
+                    if jid is None:
+                        pool.put(buf)
+                        break
+                    owned[jid] = (i, buf)
+                    i += 1
+                if srv.stats()["resident"]:
+                    srv.step()
+                elif i < n and arr is not None:
+                    wait_until(t0 + arr[i])
+                for jid, _ in srv.poll():
+                    k, buf = owned.pop(jid)
+                    lat[k] = time.perf_counter() - t0 - (arr[k] if arr is not None else 0.0)
+                    futs.append(hasher.submit(consume, k, buf, hashes))
+                    done += 1
+            span = time.perf_counter() - t0 - (arr[0] if arr is not None else 0.0)
+            rounds = srv.stats()["rounds"]
+            srv.close()
+            hasher.shutdown()
+            for f in futs:
+                f.result()
+            return hashes, lat, span, rounds
 
-    # timed passes: results land in host memory and their buffers are reused
-    _, lat_sb, span_sb = run_sequential(None)
-    log(f"served: sequential back to back {span_sb:.2f}s")
-    _, lat_vb, span_vb, rounds_vb = run_served(None)
-    log(f"served: server back to back {span_vb:.2f}s, {rounds_vb} rounds")
-    rate = args.serve_load * n / span_sb
-    arr = synth.poisson_arrivals(n, rate)
-    _, lat_st, span_st = run_sequential(arr)
-    log(f"served: sequential on the trace {span_st:.2f}s")
-    _, lat_vt, span_vt, rounds_vt = run_served(arr)
-    log(f"served: server on the trace {span_vt:.2f}s")
-    # untimed verification passes: every result hashed, job by job
-    ref, _, _ = run_sequential(None, hashing=True)
-    h_vb, _, _, _ = run_served(None, hashing=True)
-    h_vt, _, _, _ = run_served(arr, hashing=True)
-    agree = ref == h_vb == h_vt and None not in ref
+        def summary(lat, span):
+            return {"mpx_s": round(npx / span / 1e6, 1),
+                    "latency_ms_p50": round(pct(lat, 50) * 1e3, 2),
+                    "latency_ms_p99": round(pct(lat, 99) * 1e3, 2), "span_s": round(span, 3)}
 
-    # oracle check on a sample: the first jobs of each kind up to 4 Mpx
-    sample = ([i for i, j in enumerate(jobs) if j[0] == "recon" and j[1] * j[2] <= 4 << 20][:8] +
-              [i for i, j in enumerate(jobs) if j[0] == "fill" and j[1] * j[2] <= 4 << 20][:8])
+        # timed passes: results land in their buffers, which are reused
+        _, lat_sb, span_sb = run_sequential(None)
+        log(f"served ({where}): sequential back to back {span_sb:.2f}s")
+        _, lat_vb, span_vb, rounds_vb = run_served(None)
+        log(f"served ({where}): server back to back {span_vb:.2f}s, {rounds_vb} rounds")
+        rate = args.serve_load * n / span_sb
+        arr = synth.poisson_arrivals(n, rate)
+        _, lat_st, span_st = run_sequential(arr)
+        log(f"served ({where}): sequential on the trace {span_st:.2f}s")
+        _, lat_vt, span_vt, rounds_vt = run_served(arr)
+        log(f"served ({where}): server on the trace {span_vt:.2f}s")
+        # untimed verification passes: every result hashed, job by job
+        ref, _, _ = run_sequential(None, hashing=True)
+        h_vb, _, _, _ = run_served(None, hashing=True)
+        h_vt, _, _, _ = run_served(arr, hashing=True)
+        agree = ref == h_vb == h_vt and None not in ref
+        del banks, pm, pk, pf
+        return ref, {
+            "jobs_in": "HBM (device-to-device copies into and out of the arena)" if on_dev
+                       else "pinned host memory (PCIe in and out)",
+            "back_to_back": {"sequential": summary(lat_sb, span_sb),
+                             "served": summary(lat_vb, span_vb), "served_rounds": rounds_vb},
+            "trace": {"rate_jobs_s": round(rate, 2),
+                      "load_vs_sequential_capacity": args.serve_load,
+                      "sequential": summary(lat_st, span_st), "served": summary(lat_vt, span_vt),
+                      "served_rounds": rounds_vt},
+            "results_agree": bool(agree),
+        }
 
-    def check(i):
-        a, m = views(i)
-        a = np.ascontiguousarray(a.numpy())
-        want = (oracle.recon_dilate(a, np.ascontiguousarray(m.numpy()), 8) if m is not None
-                else oracle.fill_holes(a, 8))[0]
-        return xxhash.xxh3_64_intdigest(want) == ref[i]
-
-    with ThreadPoolExecutor(8) as ex:
-        oracle_ok = all(ex.map(check, sample))
-    log("served: all runs agree:", agree, "oracle sample ok:", oracle_ok)
+    ref_host, host = run_mode("host")
+    torch.cuda.empty_cache()
+    ref_dev, device = run_mode("device")
+    t1 = time.time()
+    with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        want = list(ex.map(oracle_hash, range(n)))
+    log(f"served: oracle over all {n} jobs in {time.time() - t1:.1f}s")
+    host["oracle_bit_exact"] = ref_host == want
+    device["oracle_bit_exact"] = ref_dev == want
+    log("served: host jobs agree:", host["results_agree"], "oracle:", host["oracle_bit_exact"],
+        "| device jobs agree:", device["results_agree"], "oracle:", device["oracle_bit_exact"])
     return {
         "workload": f"{n} jobs, sides log-uniform 512-8192, 70% recon / 30% fill-holes, u8 "
-                    f"conn8, {npx / 1e9:.2f} Gpx, host memory in and out",
+                    f"conn8, {npx / 1e9:.2f} Gpx",
         "arena_gib": arena >> 30, "max_jobs": max_jobs,
         "rounds_per_step": args.serve_rounds or "library default",
-        "back_to_back": {"sequential": summary(lat_sb, span_sb),
-                         "served": summary(lat_vb, span_vb), "served_rounds": rounds_vb},
-        "trace": {"rate_jobs_s": round(rate, 2), "load_vs_sequential_capacity": args.serve_load,
-                  "sequential": summary(lat_st, span_st), "served": summary(lat_vt, span_vt),
-                  "served_rounds": rounds_vt},
-        "results_agree": bool(agree),
-        "oracle_sample": {"jobs": len(sample), "bit_exact": bool(oracle_ok)},
+        "host_jobs": host,
+        "device_jobs": device,
+        "oracle_checked_jobs": n,
     }
 
 
@@ -722,6 +755,9 @@ def main():
         "tune": tune or "library default",
     }
 
+    # every timed output must be the same image; the last one then goes to
+    # the oracle
+    same = all(torch.equal(copies[i], copies[K - 1]) for i in range(K - 1))
     got = copies[K - 1].cpu().numpy()
     if not args.no_verify or not args.no_cpu_baseline:
         import oracle
@@ -729,7 +765,8 @@ def main():
         want, _ = oracle.recon_dilate(marker, mask, conn)
         t_or = time.perf_counter() - t1
         if not args.no_verify:
-            result["bit_exact"] = bool(np.array_equal(got, want))
+            result["bit_exact"] = bool(same and np.array_equal(got, want))
+            result["bit_exact_outputs_checked"] = K
             log("bit-exact vs oracle:", result["bit_exact"])
         if not args.no_cpu_baseline:
             result["cpu_baseline"] = {

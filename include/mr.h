@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define MR_ABI_VERSION 2 /* 2: mr_tune.tail_rounds */
+#define MR_ABI_VERSION 3 /* 2: mr_tune.tail_rounds; 3: mr_job.flags */
 
 typedef enum { MR_U8 = 1, MR_I32 = 4 } mr_dtype; /* value = bytes per pixel */
 
@@ -102,8 +102,12 @@ typedef struct {
     uint64_t pops;        /* frontier entries processed by the queue phase */
     uint64_t pushes;      /* frontier entries produced by the queue phase */
     uint64_t cas_retries; /* failed compare-and-swap attempts (u8 updates) */
-    uint64_t overflows;   /* entries that did not fit the device ring and were
-                             handed back to tile rounds (never an error) */
+    uint64_t overflows;   /* ring pushes refused because their slot was still
+                             taken after a capped wait. The ring holds more
+                             slots than a launch has tiles plus waves, so this
+                             stays 0; a nonzero value means the capacity bound
+                             broke, the call's result is incomplete, and
+                             mr_status reports MR_EHIP */
     uint64_t sweeps;      /* sweep iterations summed over all tile visits (one
                              iteration = down, up, right and left sweeps) */
 } mr_counters;
@@ -202,12 +206,18 @@ int mr_autotune(const mr_tile *tiles, int32_t n, mr_dtype t, int conn, void *ws,
 
 /* --------------------------------------------------------------- serving */
 
-/* A request: one image in host memory, answered in host memory. Rows of
- * the inputs are `ld` elements apart and rows of the result `ld_result` apart
+/* A request: one image, answered in a buffer of the same kind. Rows of the
+ * inputs are `ld` elements apart and rows of the result `ld_result` apart
  * (0 means W), so a job can be a window of a larger image. The buffers must
- * stay valid until the job is reported done; pinned (page-locked) memory
- * lets the copies run asynchronously, pageable memory works but copies
- * synchronously. */
+ * stay valid until the job is reported done.
+ * Host jobs (flags 0): data, mask and result are host memory; pinned
+ * (page-locked) memory lets the copies run asynchronously, pageable memory
+ * works but copies synchronously.
+ * Device jobs (flags MR_JOB_DEVICE): data, mask and result are device
+ * memory of the server's GPU, for callers whose tiles are already in HBM
+ * (an upstream kernel produced them): the copies into and out of the arena
+ * are device-to-device, and no PCIe transfer is involved. */
+enum { MR_JOB_DEVICE = 1 };
 typedef struct {
     const void *data; /* H x W: the marker (MR_OP_RECON) or the image (MR_OP_FILL) */
     const void *mask; /* H x W mask (MR_OP_RECON); NULL otherwise */
@@ -216,7 +226,7 @@ typedef struct {
     int64_t ld;        /* input row pitch in elements, >= W, or 0 */
     int64_t ld_result; /* result row pitch in elements, >= W, or 0 */
     int32_t op;        /* MR_OP_RECON or MR_OP_FILL */
-    int32_t reserved;  /* must be 0 */
+    int32_t flags;     /* 0 (host buffers) or MR_JOB_DEVICE */
 } mr_job;
 
 /* Continuous-batching server over a caller-provided device arena, the HBM
@@ -272,6 +282,16 @@ void mr_server_destroy(mr_server *s);
  * queue phase or the tile queue saw no new ring entry for 2 s and gave up:
  * the result of that call is then incomplete; *out is still written). */
 int mr_read_counters(const void *ws, mr_counters *out, void *stream);
+
+/* Status of the last call that used a workspace (mr_recon_dilate,
+ * mr_fill_holes, mr_recon_erode, mr_batch or a graph launch over it). Waits
+ * for `stream`, then returns MR_OK if that call ran to its fixed point, or
+ * MR_EHIP if a wave of its queue phase or tile queue gave up (no new ring
+ * entry for 2 s) or a ring push was refused: the result is then incomplete.
+ * The status is kept until the next call on the same workspace clears it, so
+ * check it before reusing the workspace. Costs one 8-byte copy.
+ * Errors: MR_EINVAL (null ws), MR_EHIP (as above, or a failed copy). */
+int mr_status(const void *ws, void *stream);
 
 /* Tile visits per round of the last call that used a workspace: out[i] is
  * the number of 64 x 64 tiles visited in round i + 1, and out[rounds] the

@@ -1,5 +1,6 @@
 """Build libmrecon.so (gfx950) in place with hipcc.
 
+Every source compiles to its own object in parallel, then hipcc links them.
 Usage: ``python -m paper_1311_0378_amd.build [--verbose]``.
 """
 from __future__ import annotations
@@ -7,6 +8,8 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -20,25 +23,35 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     "-Wall",
     # packed fp32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 
 
-def build(verbose: bool = False, extra=()) -> str:
-    """Compile every HIP source into ``libmrecon.so`` next to this file."""
-    tmp = f"{LIB}.tmp{os.getpid()}"
-    cmd = [HIPCC, *FLAGS, *extra, *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError(f"hipcc failed with status {res.returncode}")
+        raise RuntimeError(f"hipcc failed with status {res.returncode}: {' '.join(cmd[-3:])}")
     if verbose and res.stderr:
         sys.stderr.write(res.stderr)
+
+
+def build(verbose: bool = False, extra=()) -> str:
+    """Compile every HIP source into ``libmrecon.so`` next to this file."""
+    srcs = list(SOURCES)
+    with tempfile.TemporaryDirectory(prefix="mrecon_build_") as tmpd:
+        objs = [os.path.join(tmpd, s.replace(".hip", ".o")) for s in srcs]
+        cmds = [[HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, s), "-o", o]
+                for s, o in zip(srcs, objs)]
+        jobs = min(len(cmds), max(1, min(8, os.cpu_count() or 1)))
+        with ThreadPoolExecutor(jobs) as ex:
+            list(ex.map(lambda c: _run(c, verbose), cmds))
+        tmp = f"{LIB}.tmp{os.getpid()}"
+        _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 

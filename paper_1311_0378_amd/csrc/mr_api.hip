@@ -140,12 +140,13 @@ struct Timing {
     int on = MR_TIMING_OFF;
     std::vector<TimedLaunch> recs;
     std::vector<hipEvent_t> pool;
+    // (thread exit: nobody is left to report a failed destroy to)
     ~Timing() {
         for (auto &r : recs) {
-            hipEventDestroy(r.a);
-            hipEventDestroy(r.b);
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
         }
-        for (auto e : pool) hipEventDestroy(e);
+        for (auto e : pool) (void)hipEventDestroy(e);
     }
     hipEvent_t get() {
         hipEvent_t e = nullptr;
@@ -222,26 +223,55 @@ struct RoundSpan {
     ~RoundSpan() { close(); }
 };
 
-// Pinned words the converge mode polls through: two slots of one round's
-// band counts, so that one slot is read while the other's copy is in flight.
-uint32_t *host_words() {
-    static thread_local uint32_t *w = nullptr;
-    if (!w && hipHostMalloc((void **)&w, sizeof(uint32_t) * 2 * NBANDS, hipHostMallocDefault) !=
-                  hipSuccess)
-        w = nullptr;
-    return w;
-}
+// Pinned words and events the converge mode polls through: two slots of one
+// round's band counts, so that one slot is read while the other's copy is in
+// flight. A call that stops polling may leave its last copy (of a batch
+// enqueued ahead) in flight when it returns; a later call on this thread,
+// perhaps on another stream, must not reuse that slot before the copy has
+// landed, or the stale count could overwrite the new one. So each call takes
+// a set whose recorded events have all completed, and makes a new set only
+// when every set is still busy (calls in flight on several streams at once).
+struct PollSet {
+    uint32_t *words = nullptr;              // [2][NBANDS], pinned
+    hipEvent_t ev[2] = {nullptr, nullptr};  // slot copy complete
+    bool recorded[2] = {false, false};
+};
+struct PollSets {
+    std::vector<PollSet> sets;
+    // (thread exit: nobody is left to report a failed free to)
+    ~PollSets() {
+        for (auto &p : sets) {
+            for (auto e : p.ev)
+                if (e) (void)hipEventDestroy(e);
+            if (p.words) (void)hipHostFree(p.words);
+        }
+    }
+};
+thread_local PollSets g_polls;
 
-// The events that mark each slot's copy complete (default flags: the host
-// reads the copied words after waiting on them).
-hipEvent_t *poll_events() {
-    static thread_local hipEvent_t ev[2] = {nullptr, nullptr};
+PollSet *idle_poll_set() {
+    for (auto &p : g_polls.sets) {
+        bool busy = false;
+        for (int i = 0; i < 2; ++i)
+            if (p.recorded[i] && hipEventQuery(p.ev[i]) == hipErrorNotReady) busy = true;
+        if (!busy) {
+            p.recorded[0] = p.recorded[1] = false;
+            return &p;
+        }
+    }
+    PollSet p;
+    if (hipHostMalloc((void **)&p.words, sizeof(uint32_t) * 2 * NBANDS, hipHostMallocDefault) !=
+        hipSuccess)
+        return nullptr;
     for (int i = 0; i < 2; ++i)
-        if (!ev[i] && hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess) {
-            ev[i] = nullptr;
+        if (hipEventCreateWithFlags(&p.ev[i], hipEventDisableTiming) != hipSuccess) {
+            for (auto e : p.ev)
+                if (e) (void)hipEventDestroy(e);
+            (void)hipHostFree(p.words);
             return nullptr;
         }
-    return ev;
+    g_polls.sets.push_back(p);
+    return &g_polls.sets.back();
 }
 
 uint64_t round_total(const Ctrl &h, size_t r) {
@@ -353,9 +383,10 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
         // behind: the next batch is already enqueued while it waits, so the
         // device does not idle on the poll. A batch enqueued after the last
         // dirty round finds empty lists and changes nothing.
-        uint32_t *hw = host_words();
-        hipEvent_t *ev = poll_events();
-        if (!hw || !ev) return fail(MR_EHIP, "cannot allocate the pinned poll words or events");
+        PollSet *ps = idle_poll_set();
+        if (!ps) return fail(MR_EHIP, "cannot allocate the pinned poll words or events");
+        uint32_t *hw = ps->words;
+        hipEvent_t *ev = ps->ev;
         const uint32_t poll = 8;
         const uint32_t cap = tn.converge_rounds > 0 ? (uint32_t)tn.converge_rounds : MAX_ROUNDS;
         bool left = false; // work still listed after `cap` rounds
@@ -376,7 +407,9 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
                                     sizeof(uint32_t) * NBANDS, hipMemcpyDeviceToHost, s)) !=
                 hipSuccess)
                 return e;
-            return hipEventRecord(ev[slot], s);
+            if ((e = hipEventRecord(ev[slot], s)) != hipSuccess) return e;
+            ps->recorded[slot] = true;
+            return hipSuccess;
         };
         int slot = 0;
         if ((e = batch(slot)) != hipSuccess) return hip_fail(e, "tile round batch");
@@ -628,7 +661,8 @@ int mr_batch_graph_create(const mr_tile *tiles, int32_t n, mr_dtype t, int conn,
             rc = hip_fail(e, "instantiate");
     }
     g_timing.on = timing;
-    hipStreamDestroy(s);
+    // the capture stream never ran work: a failed destroy changes nothing
+    (void)hipStreamDestroy(s);
     if (rc != MR_OK) {
         mr_graph_destroy(g);
         return rc;
@@ -646,8 +680,9 @@ int mr_graph_launch(mr_graph *g, void *stream) {
 
 void mr_graph_destroy(mr_graph *g) {
     if (!g) return;
-    if (g->exec) hipGraphExecDestroy(g->exec);
-    if (g->graph) hipGraphDestroy(g->graph);
+    // (a void function: a failed destroy can only leak the handle)
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
     delete g;
 }
 
@@ -696,8 +731,10 @@ int mr_autotune(const mr_tile *tiles, int32_t n, mr_dtype t, int conn, void *ws,
                                   {12, 16, 0}, {16, 16, 0}, {24, 16, 0}, {32, 16, 0},
                                   {48, 16, 0}, {16, 3, 0}};
     hipEvent_t a = nullptr, b = nullptr;
-    if ((e = hipEventCreate(&a)) != hipSuccess || (e = hipEventCreate(&b)) != hipSuccess)
+    if ((e = hipEventCreate(&a)) != hipSuccess || (e = hipEventCreate(&b)) != hipSuccess) {
+        if (a) (void)hipEventDestroy(a);
         return hip_fail(e, "event");
+    }
     const int timing = g_timing.on;
     g_timing.on = MR_TIMING_OFF;
     float best = 1e30f;
@@ -712,12 +749,13 @@ int mr_autotune(const mr_tile *tiles, int32_t n, mr_dtype t, int conn, void *ws,
         float t_best = 1e30f;
         for (int rep = 0; rep < 2 && rc == MR_OK; ++rep) {
             if ((e = copy_all(false)) != hipSuccess) { rc = hip_fail(e, "restore"); break; }
-            hipEventRecord(a, s);
+            if ((e = hipEventRecord(a, s)) != hipSuccess) { rc = hip_fail(e, "event"); break; }
             rc = run_batch(tiles, n, ti, conn, ws, ws_bytes, &tn, s);
-            hipEventRecord(b, s);
+            if (rc != MR_OK) break;
+            if ((e = hipEventRecord(b, s)) != hipSuccess) { rc = hip_fail(e, "event"); break; }
             if ((e = hipEventSynchronize(b)) != hipSuccess) { rc = hip_fail(e, "sync"); break; }
             float ms = 0.f;
-            hipEventElapsedTime(&ms, a, b);
+            if ((e = hipEventElapsedTime(&ms, a, b)) != hipSuccess) { rc = hip_fail(e, "event"); break; }
             t_best = std::min(t_best, ms);
         }
         if (rc != MR_OK) break;
@@ -729,8 +767,9 @@ int mr_autotune(const mr_tile *tiles, int32_t n, mr_dtype t, int conn, void *ws,
     g_timing.on = timing;
     if (rc == MR_OK && (e = copy_all(false)) != hipSuccess) rc = hip_fail(e, "restore");
     if (rc == MR_OK && (e = hipStreamSynchronize(s)) != hipSuccess) rc = hip_fail(e, "sync");
-    hipEventDestroy(a);
-    hipEventDestroy(b);
+    // the events are no longer recorded anywhere: a failed destroy only leaks them
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
     if (rc == MR_OK) *out = bt;
     return rc;
 }
@@ -758,6 +797,21 @@ int mr_read_counters(const void *ws, mr_counters *out, void *stream) {
     }
     *out = c;
     if (h.watchdog) return fail(MR_EHIP, "a queue or tile-queue wave saw no progress for its watchdog time");
+    return MR_OK;
+}
+
+int mr_status(const void *ws, void *stream) {
+    g_err.clear();
+    if (!ws) return fail(MR_EINVAL, "null workspace");
+    unsigned long long w = 0;
+    hipError_t e = hipMemcpyAsync(&w, &((const Ctrl *)ws)->watchdog, sizeof w,
+                                  hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "status copy");
+    if ((e = hipStreamSynchronize((hipStream_t)stream)) != hipSuccess)
+        return hip_fail(e, "status sync");
+    if (w)
+        return fail(MR_EHIP, "the last call on this workspace gave up (%llu watchdog or ring "
+                             "guard events): its result is incomplete", w);
     return MR_OK;
 }
 

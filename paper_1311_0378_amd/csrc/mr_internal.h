@@ -52,16 +52,15 @@ struct Ctrl {
     Line q_head;     // frontier ring: next entry to claim
     Line q_tail;     // frontier ring: next free entry
     Line pending;    // entries pushed and not yet fully processed
-    Line overflowed; // non-zero when a push was handed back to the tiles
     Line seeds_total;
     unsigned long long tiles[NCNT];  // tile visits (spread)
     unsigned long long pops[NCNT];   // queue-phase pops (spread)
     unsigned long long pushes[NCNT]; // queue-phase pushes (spread)
     unsigned long long cas[NCNT];    // failed CAS attempts (spread)
-    unsigned long long ovf[NCNT];    // overflowed pushes (spread)
+    unsigned long long ovf[NCNT];    // ring pushes refused by the guard (spread)
     unsigned long long iters[NCNT];  // sweep iterations over all tile visits (spread)
     unsigned long long rounds;       // written by the host sequence
-    unsigned long long watchdog;     // non-zero if a queue block hit its spin cap
+    unsigned long long watchdog;     // non-zero if a wave gave up waiting or a push was refused
     // round_tiles[r][b]: length of band b's dirty list for round r (round 1:
     // the band's size, written when the block is cleared); round k + 1's lists
     // are what the seed pass starts from after k rounds.

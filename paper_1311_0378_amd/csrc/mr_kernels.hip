@@ -501,12 +501,18 @@ __device__ __forceinline__ void ring_push(Ctrl *ctrl, uint32_t *ring, uint64_t c
         __hip_atomic_fetch_add(&ctrl->q_tail.v, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint32_t *slot = ring + (pos & (cap - 1));
     // The capacity bound means the slot is already free; the wait is a guard,
-    // capped so that a broken bound cannot hang the device.
+    // capped so that a broken bound cannot hang the device. Past the cap the
+    // entry is refused rather than written over another: its work is lost,
+    // counted as an overflow and raised as the watchdog status, so the call
+    // reports an incomplete result instead of returning a wrong one quietly.
     for (uint32_t spin = 0;
          __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != Q_EMPTY; ++spin) {
         if (spin > (1u << 22)) {
+            atomicAdd(&ctrl->ovf[t & (NCNT - 1)], 1ull);
             atomicAdd(&ctrl->watchdog, 1ull);
-            break;
+            __hip_atomic_fetch_add(&ctrl->pending.v, (unsigned long long)-1ll, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            return;
         }
         __builtin_amdgcn_s_sleep(2);
     }

@@ -162,7 +162,7 @@ int64_t job_tiles(const mr_job &j) { return ((j.H + TI - 1) / TI) * ((j.W + TI -
 int check_job(const mr_server *s, const mr_job *j) {
     if (!j) return sfail(MR_EINVAL, "null job");
     if (j->op != MR_OP_RECON && j->op != MR_OP_FILL) return sfail(MR_EINVAL, "unknown op %d", j->op);
-    if (j->reserved) return sfail(MR_EINVAL, "reserved must be 0");
+    if (j->flags & ~MR_JOB_DEVICE) return sfail(MR_EINVAL, "unknown job flags 0x%x", j->flags);
     if (j->H < 1 || j->W < 1) return sfail(MR_EINVAL, "empty image");
     if ((j->ld != 0 && j->ld < j->W) || (j->ld_result != 0 && j->ld_result < j->W))
         return sfail(MR_EINVAL, "host row pitch below the width");
@@ -202,16 +202,19 @@ int collect(mr_server *s, bool wait) {
     return MR_OK;
 }
 
+// Frees the server's host-side handles. Called on teardown paths that have
+// already waited for the streams (or never used them), where a failed destroy
+// can only leak a handle and has nobody to report to.
 void destroy_handles(mr_server *s) {
     for (hipEvent_t e : s->ev_in)
-        if (e) hipEventDestroy(e);
+        if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : s->ev_out)
-        if (e) hipEventDestroy(e);
+        if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : s->ev_round)
-        if (e) hipEventDestroy(e);
-    if (s->up) hipStreamDestroy(s->up);
-    if (s->down) hipStreamDestroy(s->down);
-    if (s->h_busy) hipHostFree(s->h_busy);
+        if (e) (void)hipEventDestroy(e);
+    if (s->up) (void)hipStreamDestroy(s->up);
+    if (s->down) (void)hipStreamDestroy(s->down);
+    if (s->h_busy) (void)hipHostFree(s->h_busy);
 }
 
 } // namespace
@@ -284,7 +287,9 @@ int mr_server_create(void *arena, size_t arena_bytes, int32_t max_jobs, mr_dtype
     if (e == hipSuccess) e = launch_clear_u32(s->busy, max_jobs, 0u, s->stream);
     if (e == hipSuccess) e = launch_clear_u32(s->flags, nt, 0u, s->stream);
     if (e != hipSuccess) {
-        hipStreamSynchronize(s->stream);
+        // the set-up error is what gets reported; the wait only makes sure
+        // nothing enqueued above still runs when the handles go
+        (void)hipStreamSynchronize(s->stream);
         destroy_handles(s);
         delete s;
         return hip_err(e, "server set-up");
@@ -320,11 +325,11 @@ int mr_server_submit(mr_server *s, const mr_job *job, uint64_t *id) {
     char *p0 = s->arena + s->data_off + mo, *p1 = p0 + j.plane;
     const size_t row = (size_t)job->W * s->t, dp = (size_t)j.pitch * s->t;
     const size_t hp = (size_t)(job->ld ? job->ld : job->W) * s->t;
-    hipError_t e = hipMemcpy2DAsync(p0, dp, job->data, hp, row, (size_t)job->H,
-                                    hipMemcpyHostToDevice, s->up);
+    const hipMemcpyKind in_kind =
+        (job->flags & MR_JOB_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    hipError_t e = hipMemcpy2DAsync(p0, dp, job->data, hp, row, (size_t)job->H, in_kind, s->up);
     if (e == hipSuccess && job->op == MR_OP_RECON)
-        e = hipMemcpy2DAsync(p1, dp, job->mask, hp, row, (size_t)job->H, hipMemcpyHostToDevice,
-                             s->up);
+        e = hipMemcpy2DAsync(p1, dp, job->mask, hp, row, (size_t)job->H, in_kind, s->up);
     if (e == hipSuccess) e = hipEventRecord(s->ev_in[j.slot], s->up);
     if (e == hipSuccess) e = hipStreamWaitEvent(s->stream, s->ev_in[j.slot], 0);
     ImgDesc &d = j.d;
@@ -432,8 +437,11 @@ int mr_server_step(mr_server *s) {
             const char *src = (const char *)(j.spec.op == MR_OP_RECON ? j.d.J : j.d.out);
             const size_t row = (size_t)j.spec.W * s->t, dp = (size_t)j.pitch * s->t;
             const size_t hp = (size_t)(j.spec.ld_result ? j.spec.ld_result : j.spec.W) * s->t;
+            const hipMemcpyKind out_kind = (j.spec.flags & MR_JOB_DEVICE)
+                                               ? hipMemcpyDeviceToDevice
+                                               : hipMemcpyDeviceToHost;
             if ((e = hipMemcpy2DAsync(j.spec.result, hp, src, dp, row, (size_t)j.spec.H,
-                                      hipMemcpyDeviceToHost, s->down)) != hipSuccess ||
+                                      out_kind, s->down)) != hipSuccess ||
                 (e = hipEventRecord(s->ev_out[slot], s->down)) != hipSuccess)
                 return hip_err(e, "result copy");
             s->returning.push_back(
@@ -490,9 +498,12 @@ int mr_server_stats(const mr_server *s, int32_t *resident, uint64_t *rounds, siz
 
 void mr_server_destroy(mr_server *s) {
     if (!s) return;
-    hipStreamSynchronize(s->stream);
-    if (s->up) hipStreamSynchronize(s->up);
-    if (s->down) hipStreamSynchronize(s->down);
+    // A void function: a failed wait (a device fault) is reported again by
+    // the caller's next synchronization on the stream, and the handles go
+    // either way.
+    (void)hipStreamSynchronize(s->stream);
+    if (s->up) (void)hipStreamSynchronize(s->up);
+    if (s->down) (void)hipStreamSynchronize(s->down);
     destroy_handles(s);
     delete s;
 }

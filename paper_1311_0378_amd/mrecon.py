@@ -15,13 +15,14 @@ import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmrecon.so")
-ABI_VERSION = 2  # the layout of the structs below (include/mr.h MR_ABI_VERSION)
+ABI_VERSION = 3  # the layout of the structs below (include/mr.h MR_ABI_VERSION)
 HEADER = os.path.join(HERE, "..", "include", "mr.h")
 
 MR_U8, MR_I32 = 1, 4
 MR_OK, MR_EINVAL, MR_ENOMEM, MR_EHIP, MR_EAGAIN = 0, -1, -2, -3, -4
 MR_OP_RECON, MR_OP_FILL = 0, 1
 MR_PROBE_ADD, MR_PROBE_CAS = 0, 1
+MR_JOB_DEVICE = 1
 
 _DTYPES = {torch.uint8: MR_U8, torch.int32: MR_I32}
 
@@ -48,7 +49,7 @@ class Job(ctypes.Structure):
     _fields_ = [("data", ctypes.c_void_p), ("mask", ctypes.c_void_p), ("result", ctypes.c_void_p),
                 ("H", ctypes.c_int64), ("W", ctypes.c_int64), ("ld", ctypes.c_int64),
                 ("ld_result", ctypes.c_int64), ("op", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("flags", ctypes.c_int32)]
 
 
 class LaunchTime(ctypes.Structure):
@@ -99,6 +100,8 @@ def lib():
         L.mr_recon_erode.restype = c_int
         L.mr_read_counters.argtypes = [vp, ctypes.POINTER(Counters), vp]
         L.mr_read_counters.restype = c_int
+        L.mr_status.argtypes = [vp, vp]
+        L.mr_status.restype = c_int
         L.mr_read_round_tiles.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), i32,
                                           ctypes.POINTER(i32), vp]
         L.mr_read_round_tiles.restype = c_int
@@ -215,6 +218,17 @@ def alloc_workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
+def _call_workspace(nbytes: int, device, stream) -> torch.Tensor:
+    """A workspace for one call, made by the binding. It is allocated on the
+    current stream; when the call runs on another stream, the caching
+    allocator is told so (record_stream) and will not hand the block out
+    again until that stream's work on it has finished."""
+    ws = alloc_workspace(nbytes, device)
+    if stream is not None:
+        ws.record_stream(stream)
+    return ws
+
+
 def recon_dilate(marker: torch.Tensor, mask: torch.Tensor, conn: int = 8, tune=None,
                  workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """Reconstruction by dilation of ``marker`` under ``mask``, in place in
@@ -223,8 +237,8 @@ def recon_dilate(marker: torch.Tensor, mask: torch.Tensor, conn: int = 8, tune=N
     if mask.shape != marker.shape or mask.dtype != marker.dtype or mask.stride() != marker.stride():
         raise ValueError("mask must match the marker's shape, dtype and strides")
     if workspace is None:
-        workspace = alloc_workspace(workspace_bytes(MR_OP_RECON, H, W, marker.dtype, conn, tune),
-                                    marker.device)
+        workspace = _call_workspace(workspace_bytes(MR_OP_RECON, H, W, marker.dtype, conn, tune),
+                                    marker.device, stream)
     _check(lib().mr_recon_dilate(marker.data_ptr(), mask.data_ptr(), H, W, pitch, t, conn,
                                  workspace.data_ptr(), workspace.numel(), _tune_ptr(tune),
                                  _stream_ptr(stream)))
@@ -247,8 +261,8 @@ def recon_erode(marker: torch.Tensor, mask: torch.Tensor, conn: int = 8, tune=No
     if mask.shape != marker.shape or mask.dtype != marker.dtype or mask.stride() != marker.stride():
         raise ValueError("mask must match the marker's shape, dtype and strides")
     if workspace is None:
-        workspace = alloc_workspace(erode_workspace_bytes(H, W, pitch, marker.dtype, conn, tune),
-                                    marker.device)
+        workspace = _call_workspace(erode_workspace_bytes(H, W, pitch, marker.dtype, conn, tune),
+                                    marker.device, stream)
     _check(lib().mr_recon_erode(marker.data_ptr(), mask.data_ptr(), H, W, pitch, t, conn,
                                 workspace.data_ptr(), workspace.numel(), _tune_ptr(tune),
                                 _stream_ptr(stream)))
@@ -260,8 +274,8 @@ def fill_holes(img: torch.Tensor, conn: int = 8, tune=None,
     """Fill-holes of ``img`` in place (returned)."""
     H, W, pitch, t = _image_args(img)
     if workspace is None:
-        workspace = alloc_workspace(workspace_bytes(MR_OP_FILL, H, W, img.dtype, conn, tune),
-                                    img.device)
+        workspace = _call_workspace(workspace_bytes(MR_OP_FILL, H, W, img.dtype, conn, tune),
+                                    img.device, stream)
     _check(lib().mr_fill_holes(img.data_ptr(), H, W, pitch, t, conn, workspace.data_ptr(),
                                workspace.numel(), _tune_ptr(tune), _stream_ptr(stream)))
     return img
@@ -301,7 +315,7 @@ def batch(items, conn: int = 8, tune=None, workspace: torch.Tensor | None = None
     arr, n, t, _ = make_tiles(items)
     dev = items[0][0].device
     if workspace is None:
-        workspace = alloc_workspace(batch_workspace_bytes(items, conn, tune), dev)
+        workspace = _call_workspace(batch_workspace_bytes(items, conn, tune), dev, stream)
     _check(lib().mr_batch(arr, n, t, conn, workspace.data_ptr(), workspace.numel(),
                           _tune_ptr(tune), _stream_ptr(stream)))
     return workspace
@@ -388,11 +402,16 @@ class Server:
 
     def submit(self, data, mask=None, op=None, out=None):
         """Admit ``data`` (the marker, or for fill-holes the image when
-        ``mask`` is None). ``out`` (pinned host memory of the job's shape,
-        unit-stride rows) receives the result; by default a pinned buffer is
-        allocated. Returns the job id, or None if there is no room right now."""
+        ``mask`` is None). Host arrays make a host job: ``out`` (pinned host
+        memory of the job's shape, unit-stride rows) receives the result; by
+        default a pinned buffer is allocated. CUDA tensors make a device job
+        (MR_JOB_DEVICE): the result goes to ``out``, a device tensor (by
+        default a new one). Returns the job id, or None if there is no room
+        right now."""
         if op is None:
             op = MR_OP_RECON if mask is not None else MR_OP_FILL
+        if isinstance(data, torch.Tensor) and data.is_cuda:
+            return self._submit_device(data, mask, op, out)
         d = _host_rows(data, self.dtype)
         m = _host_rows(mask, self.dtype) if mask is not None else None
         if m is not None and m.shape != d.shape:
@@ -407,6 +426,29 @@ class Server:
             raise ValueError("out must be pinned, of the job's shape and type, rows unit-stride")
         job = Job(d.data_ptr(), m.data_ptr() if m is not None else None, out.data_ptr(),
                   H, W, d.stride(0), out.stride(0), int(op), 0)
+        jid = ctypes.c_uint64()
+        rc = lib().mr_server_submit(self._h, ctypes.byref(job), ctypes.byref(jid))
+        if rc == MR_EAGAIN:
+            return None
+        _check(rc)
+        self.jobs[jid.value] = (d, m, out)
+        return jid.value
+
+    def _submit_device(self, d, m, op, out):
+        for x in (d, m, out):
+            if x is not None and (not x.is_cuda or x.dim() != 2 or x.dtype != self.dtype
+                                  or x.stride(1) != 1 or x.stride(0) < x.shape[1]):
+                raise ValueError("device jobs take 2-D CUDA tensors of the server's pixel type "
+                                 "with unit-stride rows")
+        if m is not None and (m.shape != d.shape or m.stride(0) != d.stride(0)):
+            raise ValueError("marker and mask must share shape and row pitch")
+        H, W = d.shape
+        if out is None:
+            out = torch.empty((H, W), dtype=self.dtype, device=d.device)
+        elif tuple(out.shape) != (H, W):
+            raise ValueError("out must have the job's shape")
+        job = Job(d.data_ptr(), m.data_ptr() if m is not None else None, out.data_ptr(),
+                  H, W, d.stride(0), out.stride(0), int(op), MR_JOB_DEVICE)
         jid = ctypes.c_uint64()
         rc = lib().mr_server_submit(self._h, ctypes.byref(job), ctypes.byref(jid))
         if rc == MR_EAGAIN:
@@ -483,6 +525,13 @@ def timing_collect() -> list:
     _check(lib().mr_timing_collect(buf, cap, ctypes.byref(n)))
     return [(KIND_NAMES.get(buf[i].kind, str(buf[i].kind)), int(buf[i].round), float(buf[i].ms),
              int(buf[i].launches)) for i in range(min(cap, n.value))]
+
+
+def status(workspace: torch.Tensor, stream=None) -> None:
+    """Wait for ``stream`` and raise MrError (MR_EHIP) if the last call that
+    used ``workspace`` gave up before its fixed point (watchdog or ring
+    guard); its result is then incomplete."""
+    _check(lib().mr_status(workspace.data_ptr(), _stream_ptr(stream)))
 
 
 def read_counters(workspace: torch.Tensor, stream=None) -> dict:

@@ -20,7 +20,7 @@ def test_exports_every_declared_function(L):
 
 
 def test_abi_version(L):
-    assert L.mr_abi_version() == mrecon.ABI_VERSION == 2
+    assert L.mr_abi_version() == mrecon.ABI_VERSION == 3
 
 
 def test_default_tune():
@@ -217,3 +217,15 @@ def _erode(L, marker=FAKE, mask=FAKE, H=8, W=8, pitch=0, t=1, conn=8, ws=FAKE,
 def test_erode_rejects(L, kw, code):
     assert _erode(L, **kw) == code
     assert L.mr_last_error()
+
+
+def test_status_rejects_null(L):
+    assert L.mr_status(None, None) == mrecon.MR_EINVAL
+    assert b"null" in L.mr_last_error()
+
+
+def test_job_struct_layout():
+    # mr_job: three pointers, four int64, two int32 (flags last)
+    assert ctypes.sizeof(mrecon.Job) == 3 * 8 + 4 * 8 + 2 * 4
+    assert mrecon.Job.flags.offset == 3 * 8 + 4 * 8 + 4
+    assert mrecon.MR_JOB_DEVICE == 1

@@ -126,3 +126,43 @@ def test_server_windows_of_a_larger_image():
     for _, (_, sl) in ids.items():
         mask[sl] = True
     assert not out.numpy()[~mask].any() and not outf.numpy()[~mask].any()
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_server_device_jobs(conn):
+    # jobs whose inputs and results are device memory (MR_JOB_DEVICE): the
+    # same answers as the oracle; inputs are windows with a row pitch wider
+    # than the job, results land in pitched device buffers
+    jobs = make_batch(24, seed=40 + conn)
+    want = [oracle_of(j, conn) for j in jobs]
+    srv = mrecon.Server(256 << 20, max_jobs=8, conn=conn)
+    pending = list(range(len(jobs)))
+    owned, got = {}, {}
+    keep = []
+    print(f"[gpu] server device jobs conn{conn}", flush=True)
+    while pending or owned:
+        while pending:
+            i = pending[0]
+            kind, a, m = jobs[i]
+            H, W = a.shape
+            big = torch.zeros((H, W + 37), dtype=torch.uint8, device=DEV)
+            big[:, :W] = torch.from_numpy(a).to(DEV)
+            d = big[:, :W]
+            mk = None
+            if kind == "recon":
+                bigm = torch.zeros_like(big)
+                bigm[:, :W] = torch.from_numpy(m).to(DEV)
+                mk = bigm[:, :W]
+            out = torch.full((H, W + 5), 7, dtype=torch.uint8, device=DEV)[:, :W]
+            jid = srv.submit(d, mk, out=out)
+            if jid is None:
+                break
+            keep.append((big, mk, out))
+            owned[jid] = i
+            pending.pop(0)
+        srv.step()
+        for jid, res in srv.poll():
+            got[owned.pop(jid)] = res.cpu().numpy()
+    srv.close()
+    for i in range(len(jobs)):
+        assert np.array_equal(got[i], want[i]), f"job {i}: " + first_mismatch(got[i], want[i])
