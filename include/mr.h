@@ -139,6 +139,33 @@ int mr_recon_dilate(void *marker_inout, const void *mask, int64_t H, int64_t W, 
 int mr_fill_holes(void *img_inout, int64_t H, int64_t W, int64_t pitch, mr_dtype t, int conn,
                   void *ws, size_t ws_bytes, const mr_tune *tune, void *stream);
 
+/* Reconstruction by dilation without any allocation, for callers that cannot
+ * allocate device memory or pass a workspace: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation. Computes exactly
+ * what mr_recon_dilate computes (same kernels), with its workspace in a
+ * scratch array the library holds in device memory, MR_NOALLOC_SCRATCH_BYTES
+ * per GPU, from the library's load on that GPU until the process ends. The
+ * call itself allocates nothing (no device, host or pinned memory, no
+ * events).
+ * Limits: the image's workspace (mr_workspace_bytes(MR_OP_RECON, ...)) must
+ * fit the scratch: at most MR_NOALLOC_SCRATCH_BYTES, which holds images up to
+ * 16384 x 16384 and somewhat beyond; larger ones return MR_ENOMEM. The tune
+ * must not select the converge mode (sweep_rounds > 0, or a negative
+ * sweep_rounds with tail_rounds > 0; the default tune qualifies): else
+ * MR_EINVAL.
+ * Concurrency: every call on one GPU shares that GPU's scratch, and each call
+ * rebuilds what it needs there, so calls on one GPU must be ordered (one
+ * stream, or events between streams): calls that overlap race on the scratch
+ * and give undefined results. Calls on different GPUs are independent.
+ * mr_status, mr_read_counters and mr_read_round_tiles read a caller's
+ * workspace, so they do not report on these calls.
+ * Other arguments and errors as for mr_recon_dilate; MR_EHIP also when the
+ * scratch array's device address cannot be looked up. */
+#define MR_NOALLOC_SCRATCH_BYTES (64u << 20)
+int mr_recon_dilate_noalloc(void *marker_inout, const void *mask, int64_t H, int64_t W,
+                            int64_t pitch, mr_dtype t, int conn, const mr_tune *tune,
+                            void *stream);
+
 /* Reconstruction by erosion, the dual of Table II's reconstruction (after
  * Vincent 1993): E = the greatest image J <= max(marker, mask) that is stable
  * under J(p) <- max(mask(p), min of J over p and its G-neighbours). Marker

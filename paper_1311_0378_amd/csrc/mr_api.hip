@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -573,6 +574,50 @@ int run_batch(const mr_tile *tiles, int32_t n, int t, int conn, void *ws, size_t
 
 } // namespace
 
+// ------------------------------------------------- allocation-free entry
+
+namespace {
+
+// Scratch of mr_recon_dilate_noalloc: one array per GPU, allocated by the
+// runtime when the library's code object is loaded on that GPU and held until
+// the process ends. In host code `scratch` names a host-side stand-in, not
+// the device array: kernels and copies get the device address that
+// hipGetSymbolAddress returns for the current device, kept per device.
+static __device__ __align__(256) unsigned char scratch[MR_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// The device address of this device's scratch array, looked up once per
+// device with that device current. Null with the error set on failure.
+void *scratch_for_current_device() {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        hip_fail(e, "hipGetDevice");
+        return nullptr;
+    }
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        fail(MR_EINVAL, "device %d is beyond the %d devices the scratch table holds", dev,
+             MAX_DEVICES);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+} // namespace
+
 namespace mr {
 void clear_error() { g_err.clear(); }
 int set_error(int code, const char *msg) {
@@ -851,6 +896,35 @@ int mr_timing_collect(mr_launch_time *out, int32_t cap, int32_t *n) {
         g_timing.pool.push_back(r.b);
     }
     g_timing.recs.clear();
+    return rc;
+}
+
+int mr_recon_dilate_noalloc(void *marker_inout, const void *mask, int64_t H, int64_t W,
+                            int64_t pitch, mr_dtype t, int conn, const mr_tune *tune,
+                            void *stream) {
+    g_err.clear();
+    int rc;
+    if ((rc = check_image(MR_OP_RECON, H, W, pitch, (int)t, conn)) != MR_OK) return rc;
+    if ((rc = check_tune(tune)) != MR_OK) return rc;
+    const mr_tune tn = effective_tune(tune);
+    // the converge mode polls the device through pinned host words it
+    // allocates; the other schedules never wait for the device
+    if (tn.sweep_rounds <= 0 && tn.tail_rounds <= 0)
+        return fail(MR_EINVAL, "mr_recon_dilate_noalloc needs tune->sweep_rounds > 0 or "
+                               "tune->tail_rounds > 0 (the converge mode allocates its poll words)");
+    const size_t need = single_layout(MR_OP_RECON, H, W, (int)t).total;
+    if (need > (size_t)MR_NOALLOC_SCRATCH_BYTES)
+        return fail(MR_ENOMEM, "a %lld x %lld image needs %zu bytes of scratch; "
+                               "mr_recon_dilate_noalloc holds %zu",
+                    (long long)H, (long long)W, need, (size_t)MR_NOALLOC_SCRATCH_BYTES);
+    void *ws = scratch_for_current_device();
+    if (!ws) return MR_EHIP;
+    // per-launch timing would create events: off for this call
+    const int timing = g_timing.on;
+    g_timing.on = MR_TIMING_OFF;
+    rc = run_single(MR_OP_RECON, marker_inout, mask, H, W, pitch, (int)t, conn, ws,
+                    (size_t)MR_NOALLOC_SCRATCH_BYTES, &tn, stream);
+    g_timing.on = timing;
     return rc;
 }
 

@@ -92,6 +92,9 @@ def lib():
         L.mr_fill_holes.argtypes = [vp, i64, i64, i64, c_int, c_int, vp, sz,
                                     ctypes.POINTER(Tune), vp]
         L.mr_fill_holes.restype = c_int
+        L.mr_recon_dilate_noalloc.argtypes = [vp, vp, i64, i64, i64, c_int, c_int,
+                                              ctypes.POINTER(Tune), vp]
+        L.mr_recon_dilate_noalloc.restype = c_int
         L.mr_recon_erode_workspace_bytes.argtypes = [i64, i64, i64, c_int, c_int,
                                                      ctypes.POINTER(Tune)]
         L.mr_recon_erode_workspace_bytes.restype = sz
@@ -242,6 +245,19 @@ def recon_dilate(marker: torch.Tensor, mask: torch.Tensor, conn: int = 8, tune=N
     _check(lib().mr_recon_dilate(marker.data_ptr(), mask.data_ptr(), H, W, pitch, t, conn,
                                  workspace.data_ptr(), workspace.numel(), _tune_ptr(tune),
                                  _stream_ptr(stream)))
+    return marker
+
+
+def recon_dilate_noalloc(marker: torch.Tensor, mask: torch.Tensor, conn: int = 8, tune=None,
+                         stream=None) -> torch.Tensor:
+    """Reconstruction by dilation in place in ``marker`` without a workspace:
+    the library's per-GPU scratch array serves instead (calls on one GPU must
+    not overlap). Nothing is allocated."""
+    H, W, pitch, t = _image_args(marker)
+    if mask.shape != marker.shape or mask.dtype != marker.dtype or mask.stride() != marker.stride():
+        raise ValueError("mask must match the marker's shape, dtype and strides")
+    _check(lib().mr_recon_dilate_noalloc(marker.data_ptr(), mask.data_ptr(), H, W, pitch, t, conn,
+                                         _tune_ptr(tune), _stream_ptr(stream)))
     return marker
 
 
