@@ -14,7 +14,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmrecon.so")
-SOURCES = ["mr_kernels.hip", "mr_api.hip", "mr_server.hip", "mr_probe.hip", "mr_erode.hip"]
+SOURCES = ["mr_kernels.hip", "mr_api.hip", "mr_server.hip", "mr_probe.hip", "mr_erode.hip",
+           "mr_ops.hip", "mr_ccl.hip", "mr_dt.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -61,7 +62,7 @@ def sources_newer_than_lib() -> bool:
         return True
     t = os.path.getmtime(LIB)
     deps = [os.path.join(CSRC, f) for f in os.listdir(CSRC)]
-    deps.append(os.path.join(HERE, "..", "include", "mr.h"))
+    deps += [os.path.join(HERE, "..", "include", h) for h in ("mr.h", "mr_ops.h")]
     return any(os.path.getmtime(p) > t for p in deps if os.path.exists(p))
 
 

@@ -1,0 +1,368 @@
+// mr_ccl.hip -- connected components labeling (union-find) and area threshold
+// (map + reduction), Table II; mr_ccl and mr_area_threshold in
+// include/mr_ops.h.
+//
+// Union-find as Sec. II-B describes it: every foreground pixel starts as its
+// own tree, trees of adjacent foreground pixels are merged with the smaller
+// root becoming the root of the merged tree, and the labels are read from
+// the flattened forest. Here a pixel's value in the forest is its linear
+// index y * W + x, so every root is the smallest index of its tree and the
+// labels (root + 1) do not depend on the order of the merges.
+//
+// The GPU version follows Sec. III-B's split: each 32 x 64 tile is merged by
+// one workgroup in LDS with LDS atomics (k_ccl_local), then the trees that
+// cross tile borders are merged in the global forest with device atomics
+// (k_ccl_merge), and finally every pixel follows its tree to the root
+// (k_ccl_flatten). A merge links the larger of two roots below the smaller
+// with an atomic minimum on the larger's parent; if another merge got there
+// first, the atomic returns the new parent and the merge goes on from it.
+// Parents only ever decrease and stay below their children, so every walk
+// ends at a root.
+//
+// Area threshold: the map step reads each pixel's label; the reduction counts
+// pixels per label with device atomic adds into one counter per possible
+// label (the workspace), adding a lane's run of equal labels in one atomic;
+// the filter clears every pixel whose label's count is out of range.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+
+#include "../../include/mr_ops.h"
+#include "mr_internal.h"
+
+using namespace mr;
+
+namespace {
+
+int cfail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    return set_error(code, buf);
+}
+
+int chip(hipError_t e, const char *what) {
+    return cfail(MR_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t up256(size_t n) { return (n + 255) / 256 * 256; }
+
+constexpr int CT_H = 32, CT_W = 64;     // tile of the local phase
+constexpr int CT_N = CT_H * CT_W;
+constexpr int CT_THREADS = 256;         // 8 pixels per lane
+constexpr uint32_t NONE = 0xFFFFFFFFu;  // background in the forest
+
+// ------------------------------------------------------------- local phase
+
+__device__ __forceinline__ uint32_t lds_load(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ uint32_t lfind(const uint32_t *P, uint32_t x) {
+    uint32_t p = lds_load(P + x);
+    while (p != x) {
+        x = p;
+        p = lds_load(P + x);
+    }
+    return x;
+}
+
+// Merge the trees of a and b in the tile's LDS forest: the larger root goes
+// below the smaller one.
+__device__ __forceinline__ void lunion(uint32_t *P, uint32_t a, uint32_t b) {
+    while (true) {
+        a = lfind(P, a);
+        b = lfind(P, b);
+        if (a == b) return;
+        if (a > b) {
+            const uint32_t t = a;
+            a = b;
+            b = t;
+        }
+        const uint32_t old = atomicMin(P + b, a);
+        if (old == b) return; // b was still a root: linked
+        b = old;              // b was linked meanwhile: go on from its parent
+    }
+}
+
+template <int CONN>
+__global__ __launch_bounds__(CT_THREADS) void k_ccl_local(const uint8_t *__restrict__ img,
+                                                          int64_t H, int64_t W, int64_t pitch,
+                                                          int64_t tiles_x,
+                                                          uint32_t *__restrict__ forest) {
+    __shared__ uint32_t P[CT_N];
+    const int64_t ty = blockIdx.x / tiles_x, tx = blockIdx.x - ty * tiles_x;
+    const int64_t y0 = ty * CT_H, x0 = tx * CT_W;
+    const int lx = threadIdx.x & (CT_W - 1), ly0 = threadIdx.x / CT_W;
+    constexpr int RSTEP = CT_THREADS / CT_W; // rows between a lane's pixels
+    bool fg[CT_H / RSTEP];
+#pragma unroll
+    for (int k = 0; k < CT_H / RSTEP; ++k) {
+        const int ly = ly0 + k * RSTEP;
+        const int64_t y = y0 + ly, x = x0 + lx;
+        fg[k] = y < H && x < W && img[y * pitch + x] != 0;
+        P[ly * CT_W + lx] = fg[k] ? (uint32_t)(ly * CT_W + lx) : NONE;
+    }
+    __syncthreads();
+    // merge with the backward neighbours inside the tile (left, up, and for
+    // 8-connectivity up-left and up-right): every adjacent pair once
+#pragma unroll
+    for (int k = 0; k < CT_H / RSTEP; ++k) {
+        if (!fg[k]) continue;
+        const int ly = ly0 + k * RSTEP;
+        const uint32_t p = ly * CT_W + lx;
+        if (lx > 0 && lds_load(P + p - 1) != NONE) lunion(P, p, p - 1);
+        if (ly > 0 && lds_load(P + p - CT_W) != NONE) lunion(P, p, p - CT_W);
+        if (CONN == 8 && ly > 0) {
+            if (lx > 0 && lds_load(P + p - CT_W - 1) != NONE) lunion(P, p, p - CT_W - 1);
+            if (lx < CT_W - 1 && lds_load(P + p - CT_W + 1) != NONE) lunion(P, p, p - CT_W + 1);
+        }
+    }
+    __syncthreads();
+    // each pixel points at its tile-local root, as a global linear index
+#pragma unroll
+    for (int k = 0; k < CT_H / RSTEP; ++k) {
+        const int ly = ly0 + k * RSTEP;
+        const int64_t y = y0 + ly, x = x0 + lx;
+        if (y >= H || x >= W) continue;
+        uint32_t v = NONE;
+        if (fg[k]) {
+            const uint32_t r = lfind(P, ly * CT_W + lx);
+            v = (uint32_t)((y0 + r / CT_W) * W + x0 + r % CT_W);
+        }
+        forest[y * W + x] = v;
+    }
+}
+
+// ------------------------------------------------------------- border phase
+
+__device__ __forceinline__ uint32_t gload(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t gfind(const uint32_t *F, uint32_t x) {
+    uint32_t p = gload(F + x);
+    while (p != x) {
+        x = p;
+        p = gload(F + x);
+    }
+    return x;
+}
+
+__device__ __forceinline__ void gunion(uint32_t *F, uint32_t a, uint32_t b) {
+    while (true) {
+        a = gfind(F, a);
+        b = gfind(F, b);
+        if (a == b) return;
+        if (a > b) {
+            const uint32_t t = a;
+            a = b;
+            b = t;
+        }
+        const uint32_t old =
+            __hip_atomic_fetch_min(F + b, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == b) return;
+        b = old;
+    }
+}
+
+// Pixels of a tile whose backward neighbours lie in another tile: the first
+// row (up, and the diagonals), the first column (left, up-left) and, with
+// 8-connectivity, the last column (up-right). One workgroup per tile, one
+// lane per border pixel.
+template <int CONN>
+__global__ __launch_bounds__(128) void k_ccl_merge(int64_t H, int64_t W, int64_t tiles_x,
+                                                   uint32_t *__restrict__ F) {
+    const int64_t ty = blockIdx.x / tiles_x, tx = blockIdx.x - ty * tiles_x;
+    const int64_t y0 = ty * CT_H, x0 = tx * CT_W;
+    const int i = threadIdx.x;
+    int64_t y, x;
+    if (i < CT_W) { // first row
+        y = y0;
+        x = x0 + i;
+    } else if (i < CT_W + CT_H) { // first column (its top pixel is in the row)
+        y = y0 + (i - CT_W);
+        x = x0;
+        if (i == CT_W) return;
+    } else if (i < CT_W + 2 * CT_H) { // last column, below the first row
+        y = y0 + (i - CT_W - CT_H);
+        x = x0 + CT_W - 1;
+        if (CONN != 8 || i == CT_W + CT_H) return;
+    } else {
+        return;
+    }
+    if (y >= H || x >= W) return;
+    const uint32_t p = (uint32_t)(y * W + x);
+    if (gload(F + p) == NONE) return;
+    const bool first_row = y == y0, first_col = x == x0, last_col = x == x0 + CT_W - 1;
+    // backward neighbours in another tile
+    if (first_col && x > 0 && gload(F + p - 1) != NONE) gunion(F, p, p - 1);
+    if (first_row && y > 0 && gload(F + p - W) != NONE) gunion(F, p, p - (uint32_t)W);
+    if (CONN == 8 && y > 0) {
+        if ((first_row || first_col) && x > 0 && gload(F + p - W - 1) != NONE)
+            gunion(F, p, p - (uint32_t)W - 1);
+        if ((first_row || last_col) && x + 1 < W && gload(F + p - W + 1) != NONE)
+            gunion(F, p, p - (uint32_t)W + 1);
+    }
+}
+
+// ----------------------------------------------------------- flatten, write
+
+__global__ __launch_bounds__(256) void k_ccl_flatten(int64_t H, int64_t W, uint32_t *__restrict__ F,
+                                                     int32_t *__restrict__ labels,
+                                                     int64_t lpitch) {
+    const int64_t n = H * W;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256) {
+        const uint32_t v = F[i];
+        int32_t l = 0;
+        if (v != NONE) {
+            const uint32_t r = gfind(F, v);
+            l = (int32_t)r + 1;
+        }
+        const int64_t y = i / W;
+        labels[y * lpitch + (i - y * W)] = l;
+    }
+}
+
+// --------------------------------------------------------------- area phase
+
+__global__ __launch_bounds__(256) void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256)
+        p[i] = v;
+}
+
+constexpr int AREA_RUN = 16; // consecutive pixels of a row per lane
+
+// Count pixels per label: each lane walks AREA_RUN consecutive pixels of one
+// row and adds each run of equal labels with one atomic.
+__global__ __launch_bounds__(256) void k_area_count(const int32_t *__restrict__ labels,
+                                                    int64_t H, int64_t W, int64_t pitch,
+                                                    int32_t *__restrict__ area) {
+    const int64_t runs = (W + AREA_RUN - 1) / AREA_RUN, n = H * runs;
+    const int64_t N = H * W;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256) {
+        const int64_t y = i / runs, x0 = (i - y * runs) * AREA_RUN;
+        const int32_t *row = labels + y * pitch;
+        int32_t cur = 0, cnt = 0;
+        for (int k = 0; k < AREA_RUN && x0 + k < W; ++k) {
+            const int32_t l = row[x0 + k];
+            if (l != cur) {
+                if (cur > 0 && cnt) atomicAdd(area + cur, cnt);
+                cur = l;
+                cnt = 0;
+            }
+            cnt += (l > 0 && (int64_t)l <= N) ? 1 : 0;
+        }
+        if (cur > 0 && cnt) atomicAdd(area + cur, cnt);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_area_filter(int32_t *__restrict__ labels, int64_t H,
+                                                     int64_t W, int64_t pitch,
+                                                     const int32_t *__restrict__ area,
+                                                     int64_t lo, int64_t hi) {
+    const int64_t n = H * W, N = H * W;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256) {
+        const int64_t y = i / W;
+        int32_t *p = labels + y * pitch + (i - y * W);
+        const int32_t l = *p;
+        if (l > 0 && (int64_t)l <= N) {
+            const int64_t a = area[l];
+            if (a < lo || a > hi) *p = 0;
+        }
+    }
+}
+
+unsigned grid_for(int64_t items) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((items + 255) / 256, 1 << 16));
+}
+
+int check_labels_dims(int64_t H, int64_t W, int64_t pitch) {
+    if (H < 1 || W < 1) return cfail(MR_EINVAL, "H and W must be >= 1");
+    if (pitch < W) return cfail(MR_EINVAL, "pitch below W");
+    if (H * W >= (1ll << 31) - 1) return cfail(MR_EINVAL, "H * W must be below 2^31 - 1");
+    return MR_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+size_t mr_ccl_workspace_bytes(int64_t H, int64_t W) {
+    clear_error();
+    if (check_labels_dims(H, W, W) != MR_OK) return 0;
+    return up256((size_t)(H * W) * 4);
+}
+
+int mr_ccl(const void *img, void *labels, int64_t H, int64_t W, int64_t pitch,
+           int64_t label_pitch, int conn, void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    if (pitch == 0) pitch = W;
+    if (label_pitch == 0) label_pitch = W;
+    int rc;
+    if ((rc = check_labels_dims(H, W, pitch)) != MR_OK) return rc;
+    if (label_pitch < W) return cfail(MR_EINVAL, "label_pitch below W");
+    if (conn != 4 && conn != 8) return cfail(MR_EINVAL, "conn must be 4 or 8 (got %d)", conn);
+    if (!img || !labels || !ws) return cfail(MR_EINVAL, "null pointer");
+    if ((uintptr_t)labels % 4) return cfail(MR_EINVAL, "labels must be 4-byte aligned");
+    if ((uintptr_t)ws % 256) return cfail(MR_EINVAL, "workspace must be 256-byte aligned");
+    const size_t need = up256((size_t)(H * W) * 4);
+    if (ws_bytes < need)
+        return cfail(MR_ENOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t *F = (uint32_t *)ws;
+    const int64_t tx = (W + CT_W - 1) / CT_W, ty = (H + CT_H - 1) / CT_H;
+    const unsigned tiles = (unsigned)(tx * ty);
+    if (conn == 8) {
+        hipLaunchKernelGGL(k_ccl_local<8>, dim3(tiles), dim3(CT_THREADS), 0, s,
+                           (const uint8_t *)img, H, W, pitch, tx, F);
+        hipLaunchKernelGGL(k_ccl_merge<8>, dim3(tiles), dim3(128), 0, s, H, W, tx, F);
+    } else {
+        hipLaunchKernelGGL(k_ccl_local<4>, dim3(tiles), dim3(CT_THREADS), 0, s,
+                           (const uint8_t *)img, H, W, pitch, tx, F);
+        hipLaunchKernelGGL(k_ccl_merge<4>, dim3(tiles), dim3(128), 0, s, H, W, tx, F);
+    }
+    hipLaunchKernelGGL(k_ccl_flatten, dim3(grid_for(H * W)), dim3(256), 0, s, H, W, F,
+                       (int32_t *)labels, label_pitch);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? MR_OK : chip(e, "ccl");
+}
+
+size_t mr_area_threshold_workspace_bytes(int64_t H, int64_t W) {
+    clear_error();
+    if (check_labels_dims(H, W, W) != MR_OK) return 0;
+    return up256((size_t)(H * W + 1) * 4);
+}
+
+int mr_area_threshold(void *labels_inout, int64_t H, int64_t W, int64_t pitch, int64_t min_area,
+                      int64_t max_area, void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    if (pitch == 0) pitch = W;
+    int rc;
+    if ((rc = check_labels_dims(H, W, pitch)) != MR_OK) return rc;
+    if (!labels_inout || !ws) return cfail(MR_EINVAL, "null pointer");
+    if ((uintptr_t)labels_inout % 4) return cfail(MR_EINVAL, "labels must be 4-byte aligned");
+    if ((uintptr_t)ws % 256) return cfail(MR_EINVAL, "workspace must be 256-byte aligned");
+    const size_t need = up256((size_t)(H * W + 1) * 4);
+    if (ws_bytes < need)
+        return cfail(MR_ENOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
+    hipStream_t s = (hipStream_t)stream;
+    int32_t *area = (int32_t *)ws;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(H * W + 1)), dim3(256), 0, s, area, H * W + 1, 0);
+    const int64_t runs = H * ((W + AREA_RUN - 1) / AREA_RUN);
+    hipLaunchKernelGGL(k_area_count, dim3(grid_for(runs)), dim3(256), 0, s,
+                       (const int32_t *)labels_inout, H, W, pitch, area);
+    hipLaunchKernelGGL(k_area_filter, dim3(grid_for(H * W)), dim3(256), 0, s,
+                       (int32_t *)labels_inout, H, W, pitch, (const int32_t *)area, min_area,
+                       max_area);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? MR_OK : chip(e, "area threshold");
+}
+
+} // extern "C"

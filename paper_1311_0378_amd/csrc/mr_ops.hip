@@ -1,0 +1,542 @@
+// mr_ops.hip -- the regular operations of Table II and the reconstruction-based
+// wrappers (include/mr_ops.h): h-dome, regional maxima, RGB to grayscale and
+// opening by a 13 x 13 disk.
+//
+// All of these are streaming passes over HBM (Sec. V-C.1's regular,
+// memory-bound class) except the reconstruction inside the wrappers, which
+// runs on the engine of mr.h.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+
+#include "../../include/mr_ops.h"
+#include "mr_internal.h"
+
+using namespace mr;
+
+namespace {
+
+int ofail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    return set_error(code, buf);
+}
+
+int ohip(hipError_t e, const char *what) {
+    return ofail(MR_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t up256(size_t n) { return (n + 255) / 256 * 256; }
+
+int check_dims(int64_t H, int64_t W, int64_t pitch, int64_t elem_bytes) {
+    if (H < 1 || W < 1) return ofail(MR_EINVAL, "H and W must be >= 1 (got %lld x %lld)",
+                                     (long long)H, (long long)W);
+    if (pitch < W) return ofail(MR_EINVAL, "pitch %lld is below W %lld", (long long)pitch,
+                                (long long)W);
+    if ((double)H * (double)pitch * (double)elem_bytes >= 9.0e18)
+        return ofail(MR_EINVAL, "image too large");
+    return MR_OK;
+}
+
+unsigned grid_for(int64_t items, int per_block) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((items + per_block - 1) / per_block,
+                                                            1 << 20));
+}
+
+// ------------------------------------------------------ h-dome, regional max
+
+// Pixel keys of the two types (the key order is the pixel order; key 0 is
+// the type's minimum).
+template <typename T> struct K;
+template <> struct K<uint8_t> {
+    __device__ static uint32_t key(uint8_t v) { return v; }
+    __device__ static uint8_t val(uint32_t k) { return (uint8_t)k; }
+};
+template <> struct K<int32_t> {
+    __device__ static uint32_t key(int32_t v) { return (uint32_t)v ^ 0x80000000u; }
+    __device__ static int32_t val(uint32_t k) { return (int32_t)(k ^ 0x80000000u); }
+};
+
+constexpr int ROW_SEG = 512; // pixels of one row per wave and step (8 per lane)
+
+// marker = f - h, saturating at the type's minimum (in key space: key - h
+// floored at 0); *above |= 1 if some pixel is above the minimum.
+template <typename T>
+__global__ __launch_bounds__(256) void k_hdome_marker(const T *__restrict__ f, T *__restrict__ m,
+                                                      int64_t H, int64_t W, int64_t pitch,
+                                                      uint32_t h, uint32_t *above) {
+    const int lane = threadIdx.x & 63;
+    const int64_t segs = (W + ROW_SEG - 1) / ROW_SEG;
+    bool any = false;
+    for (int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); it < H * segs;
+         it += (int64_t)gridDim.x * 4) {
+        const int64_t y = it / segs, x0 = (it - y * segs) * ROW_SEG;
+#pragma unroll
+        for (int k = 0; k < ROW_SEG / 64; ++k) {
+            const int64_t x = x0 + k * 64 + lane;
+            if (x < W) {
+                const uint32_t kf = K<T>::key(f[y * pitch + x]);
+                any |= kf != 0;
+                m[y * pitch + x] = K<T>::val(kf > h ? kf - h : 0u);
+            }
+        }
+    }
+    if (__ballot(any) != 0 && lane == 0) atomicOr(above, 1u);
+}
+
+// f <- f - R (the h-dome), R <= f everywhere.
+template <typename T>
+__global__ __launch_bounds__(256) void k_hdome_out(T *__restrict__ f, const T *__restrict__ r,
+                                                   int64_t H, int64_t W, int64_t pitch) {
+    const int lane = threadIdx.x & 63;
+    const int64_t segs = (W + ROW_SEG - 1) / ROW_SEG;
+    for (int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); it < H * segs;
+         it += (int64_t)gridDim.x * 4) {
+        const int64_t y = it / segs, x0 = (it - y * segs) * ROW_SEG;
+#pragma unroll
+        for (int k = 0; k < ROW_SEG / 64; ++k) {
+            const int64_t x = x0 + k * 64 + lane;
+            if (x < W) {
+                const uint32_t d = K<T>::key(f[y * pitch + x]) - K<T>::key(r[y * pitch + x]);
+                f[y * pitch + x] = (T)(int32_t)d; // 0 <= d <= h fits either type
+            }
+        }
+    }
+}
+
+// out = 255 where f > R (a dome of height 1), or everywhere when no pixel is
+// above the minimum; else 0.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rmax_out(const T *__restrict__ f, const T *__restrict__ r,
+                                                  uint8_t *__restrict__ out, int64_t H, int64_t W,
+                                                  int64_t pitch, int64_t out_pitch,
+                                                  const uint32_t *above) {
+    const int lane = threadIdx.x & 63;
+    const int64_t segs = (W + ROW_SEG - 1) / ROW_SEG;
+    const bool all_min = *above == 0;
+    for (int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); it < H * segs;
+         it += (int64_t)gridDim.x * 4) {
+        const int64_t y = it / segs, x0 = (it - y * segs) * ROW_SEG;
+#pragma unroll
+        for (int k = 0; k < ROW_SEG / 64; ++k) {
+            const int64_t x = x0 + k * 64 + lane;
+            if (x < W) {
+                const bool top = all_min || K<T>::key(f[y * pitch + x]) > K<T>::key(r[y * pitch + x]);
+                out[y * out_pitch + x] = top ? 255 : 0;
+            }
+        }
+    }
+}
+
+__global__ void k_zero_u32(uint32_t *p) { *p = 0u; }
+
+struct HdomeLayout {
+    size_t recon = 0, plane = 0, flag = 0, total = 0;
+};
+
+int hdome_layout(int64_t H, int64_t W, int64_t pitch, int t, int conn, const mr_tune *tune,
+                 HdomeLayout &L) {
+    const size_t r = mr_workspace_bytes(MR_OP_RECON, H, W, (mr_dtype)t, conn, tune);
+    if (r == 0) return MR_EINVAL; // the message is set
+    L.recon = up256(r);
+    L.plane = L.recon;
+    L.flag = L.plane + up256((size_t)H * (size_t)pitch * (size_t)t);
+    L.total = L.flag + 256;
+    return MR_OK;
+}
+
+int hdome_common(const void *img, int64_t H, int64_t W, int64_t &pitch, int t, int conn,
+                 void *ws, size_t ws_bytes, const mr_tune *tune, HdomeLayout &L) {
+    clear_error();
+    if (t != MR_U8 && t != MR_I32) return ofail(MR_EINVAL, "unknown pixel type %d", t);
+    if (pitch == 0) pitch = W;
+    int rc;
+    if ((rc = check_dims(H, W, pitch, t)) != MR_OK) return rc;
+    if (!img || !ws) return ofail(MR_EINVAL, "null image or workspace");
+    if ((uintptr_t)ws % 256) return ofail(MR_EINVAL, "workspace must be 256-byte aligned");
+    if ((uintptr_t)img % t) return ofail(MR_EINVAL, "image must be aligned to the pixel size");
+    if ((rc = hdome_layout(H, W, pitch, t, conn, tune, L)) != MR_OK) return rc;
+    if (ws_bytes < L.total)
+        return ofail(MR_ENOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes,
+                     L.total);
+    return MR_OK;
+}
+
+template <typename T>
+hipError_t hdome_marker(const void *f, void *m, int64_t H, int64_t W, int64_t pitch, uint32_t h,
+                        uint32_t *flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, flag);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t items = H * ((W + ROW_SEG - 1) / ROW_SEG);
+    hipLaunchKernelGGL((k_hdome_marker<T>), dim3(grid_for(items, 4)), dim3(256), 0, s,
+                       (const T *)f, (T *)m, H, W, pitch, h, flag);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ RGB2Gray
+
+// BT.601 luma weights in 14-bit fixed point (0.299, 0.587, 0.114; sum 2^14)
+constexpr uint32_t WR = 4899u, WG = 9617u, WB = 1868u;
+
+__device__ __forceinline__ uint32_t luma(uint32_t r, uint32_t g, uint32_t b) {
+    return (WR * r + WG * g + WB * b + 8192u) >> 14;
+}
+
+// 16 pixels per lane from three 16-byte words (48 bytes = 16 RGB triples),
+// one 16-byte word out. Rows and both planes are 16-byte aligned; vec = the
+// whole 16-pixel groups per row.
+__global__ __launch_bounds__(256) void k_rgb2gray16(const uint8_t *__restrict__ rgb,
+                                                    int64_t rgb_pitch, uint8_t *__restrict__ gray,
+                                                    int64_t gray_pitch, int64_t H, int64_t vec) {
+    const int64_t items = H * vec;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < items;
+         i += (int64_t)gridDim.x * 256) {
+        const int64_t y = i / vec, g = i - y * vec;
+        const uint4 *src = (const uint4 *)(rgb + y * rgb_pitch + g * 48);
+        const uint4 a = src[0], b = src[1], c = src[2];
+        const uint32_t w[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
+        uint32_t o[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int p = 0; p < 16; ++p) {
+            const int q = 3 * p; // byte index of this pixel's R
+            const uint32_t r = (w[q >> 2] >> ((q & 3) * 8)) & 0xFFu;
+            const uint32_t gg = (w[(q + 1) >> 2] >> (((q + 1) & 3) * 8)) & 0xFFu;
+            const uint32_t bb = (w[(q + 2) >> 2] >> (((q + 2) & 3) * 8)) & 0xFFu;
+            o[p >> 2] |= luma(r, gg, bb) << ((p & 3) * 8);
+        }
+        *(uint4 *)(gray + y * gray_pitch + g * 16) = make_uint4(o[0], o[1], o[2], o[3]);
+    }
+}
+
+// One pixel per lane, for unaligned planes and the columns past the last
+// whole 16-pixel group (x0 = first column handled).
+__global__ __launch_bounds__(256) void k_rgb2gray1(const uint8_t *__restrict__ rgb,
+                                                   int64_t rgb_pitch, uint8_t *__restrict__ gray,
+                                                   int64_t gray_pitch, int64_t H, int64_t x0,
+                                                   int64_t W) {
+    const int64_t cols = W - x0, items = H * cols;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < items;
+         i += (int64_t)gridDim.x * 256) {
+        const int64_t y = i / cols, x = x0 + (i - y * cols);
+        const uint8_t *p = rgb + y * rgb_pitch + 3 * x;
+        gray[y * gray_pitch + x] = (uint8_t)luma(p[0], p[1], p[2]);
+    }
+}
+
+// -------------------------------------------------------- 13 x 13 disk
+
+// The disk of radius 6 as rows: offset dy has half-width HW[|dy|]
+// (dy^2 + dx^2 <= 36: 6, 5, 5, 5, 4, 3, 0).
+// Each workgroup of DK_THREADS lanes produces DK_TH rows x 4 * DK_THREADS
+// columns. The input rows it needs (DK_TH + 12, with 6 columns of halo on
+// each side) are staged in LDS as bytes. Each lane owns 4 adjacent columns:
+// per input row it reads the 16 bytes around them (4 LDS words), forms the
+// horizontal extrema of widths 0, 3, 4, 5 and 6 for its 4 columns, and folds
+// them into 13 running accumulators, one per output row that this input row
+// still contributes to (the accumulator of the output row dy above gets the
+// extremum of width HW[|dy|]). Each output row is complete once its last
+// input row is folded in, and is stored. Pixels outside the image read as
+// the operation's identity (255 for the erosion, 0 for the dilation), which
+// leaves the extrema over the inside offsets.
+constexpr int DK_THREADS = 128;
+constexpr int DK_TW = 4 * DK_THREADS;    // output columns per workgroup
+constexpr int DK_TH = 64;                // output rows per workgroup
+constexpr int DK_ROWS = DK_TH + 12;      // staged input rows
+constexpr int DK_SW = DK_TW + 16;        // staged row bytes: 8 left, 8 right (6 used)
+
+template <bool MIN> __device__ __forceinline__ uint32_t ext(uint32_t a, uint32_t b) {
+    return MIN ? min(a, b) : max(a, b);
+}
+template <bool MIN> __device__ __forceinline__ uint32_t ext3(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    if (MIN)
+        asm("v_min3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    else
+        asm("v_max3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+template <bool MIN>
+__global__ __launch_bounds__(DK_THREADS) void k_disk13(const uint8_t *__restrict__ in,
+                                                       uint8_t *__restrict__ out, int64_t H,
+                                                       int64_t W, int64_t pitch, int64_t tiles_x) {
+    __shared__ uint32_t st[DK_ROWS * (DK_SW / 4)];
+    const uint32_t ident = MIN ? 0xFFu : 0u;
+    const uint32_t ident4 = MIN ? 0xFFFFFFFFu : 0u;
+    const int64_t tile = blockIdx.x;
+    const int64_t ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    const int64_t y0 = ty * DK_TH, x0 = tx * DK_TW;
+    // stage rows y0-6 .. y0+DK_TH+5, columns x0-8 .. x0+DK_TW+7, one word per
+    // lane and step; a word is gathered byte by byte at the image edges
+    constexpr int WPR = DK_SW / 4; // words per staged row
+    for (int i = threadIdx.x; i < DK_ROWS * WPR; i += DK_THREADS) {
+        const int r = i / WPR, wc = i - r * WPR;
+        const int64_t gy = y0 - 6 + r, gx = x0 - 8 + 4 * (int64_t)wc;
+        uint32_t v = ident4;
+        if (gy >= 0 && gy < H) {
+            const uint8_t *row = in + gy * pitch;
+            if (gx >= 0 && gx + 3 < W && (((uintptr_t)(row + gx)) & 3) == 0) {
+                v = *(const uint32_t *)(row + gx);
+            } else {
+                v = 0u;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int64_t x = gx + b;
+                    const uint32_t byte = (x >= 0 && x < W) ? row[x] : ident;
+                    v |= byte << (8 * b);
+                }
+            }
+        }
+        st[i] = v;
+    }
+    __syncthreads();
+
+    const int lx = threadIdx.x * 4; // first of this lane's columns, tile-relative
+    // 13 accumulators per column in a ring: output row o (tile-relative) lives
+    // in slot o mod 13. Input row r reaches output rows r - 12 .. r (offsets
+    // dy = 6 .. -6), which sit in slots (r + 1 + k) mod 13, k = 0..12; the
+    // rows are walked 13 at a time so that every slot index is a constant.
+    uint32_t acc[13][4];
+#pragma unroll
+    for (int k = 0; k < 13; ++k)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[k][c] = ident;
+    constexpr int HWID[7] = {6, 5, 5, 5, 4, 3, 0}; // half-width of the disk row |dy|
+#pragma unroll 1
+    for (int r0 = 0; r0 < DK_ROWS; r0 += 13) {
+#pragma unroll
+        for (int rr = 0; rr < 13; ++rr) {
+            const int r = r0 + rr;
+            if (r >= DK_ROWS) break;
+            // staged row r starts 8 columns left of the tile, so column
+            // lx - 6 + j (j = 0..15) is staged byte lx + 2 + j: the 5 words
+            // from staged byte lx hold them
+            const uint32_t *w = st + r * WPR + (lx >> 2);
+            uint32_t wd[5];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) wd[k] = w[k];
+            uint32_t b[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int q = j + 2;
+                b[j] = (wd[q >> 2] >> ((q & 3) * 8)) & 0xFFu;
+            }
+            // horizontal extrema over the columns j-w .. j+w (widths 1, 3, 4,
+            // 5, 6) for the positions the next width needs; this lane's
+            // output column c is position c + 6
+            uint32_t e1[16], e3[16], e4[16], e5[16], e6[4];
+#pragma unroll
+            for (int j = 1; j < 15; ++j) e1[j] = ext3<MIN>(b[j - 1], b[j], b[j + 1]);
+#pragma unroll
+            for (int j = 3; j < 13; ++j) e3[j] = ext3<MIN>(e1[j - 2], e1[j], e1[j + 2]);
+#pragma unroll
+            for (int j = 4; j < 12; ++j) e4[j] = ext<MIN>(e3[j - 1], e3[j + 1]);
+#pragma unroll
+            for (int j = 5; j < 11; ++j) e5[j] = ext<MIN>(e4[j - 1], e4[j + 1]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) e6[c] = ext<MIN>(e5[c + 5], e5[c + 7]);
+            // fold into output row r - 12 + k, which lies dy = 6 - k rows above
+            // this input row, with the disk row's half-width at |dy|
+#pragma unroll
+            for (int k = 0; k < 13; ++k) {
+                const int ady = k <= 6 ? 6 - k : k - 6;
+                const int hw = HWID[ady];
+                const int slot = (rr + 1 + k) % 13;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int j = c + 6;
+                    const uint32_t v = hw == 6 ? e6[c] : hw == 5 ? e5[j] : hw == 4 ? e4[j]
+                                     : hw == 3 ? e3[j] : b[j];
+                    acc[slot][c] = ext<MIN>(acc[slot][c], v);
+                }
+            }
+            // output row r - 12 has all 13 of its input rows: store it, and
+            // start the slot over for output row r + 1
+            const int done = (rr + 1) % 13;
+            const int64_t oy = y0 + r - 12;
+            if (r >= 12 && oy < H) {
+                const int64_t ox = x0 + lx;
+                uint8_t *orow = out + oy * pitch;
+                if (ox + 3 < W && (((uintptr_t)(orow + ox)) & 3) == 0) {
+                    *(uint32_t *)(orow + ox) = acc[done][0] | (acc[done][1] << 8) |
+                                               (acc[done][2] << 16) | (acc[done][3] << 24);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        if (ox + c < W) orow[ox + c] = (uint8_t)acc[done][c];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[done][c] = ident;
+        }
+    }
+}
+
+hipError_t launch_disk13(bool erode, const uint8_t *in, uint8_t *out, int64_t H, int64_t W,
+                         int64_t pitch, hipStream_t s) {
+    const int64_t tx = (W + DK_TW - 1) / DK_TW, ty = (H + DK_TH - 1) / DK_TH;
+    const int64_t n = tx * ty;
+    if (n >= (1ll << 31)) return hipErrorInvalidValue;
+    if (erode)
+        hipLaunchKernelGGL(k_disk13<true>, dim3((unsigned)n), dim3(DK_THREADS), 0, s, in, out, H,
+                           W, pitch, tx);
+    else
+        hipLaunchKernelGGL(k_disk13<false>, dim3((unsigned)n), dim3(DK_THREADS), 0, s, in, out,
+                           H, W, pitch, tx);
+    return hipGetLastError();
+}
+
+} // namespace
+
+extern "C" {
+
+size_t mr_hdome_workspace_bytes(int64_t H, int64_t W, int64_t pitch, mr_dtype t, int conn,
+                                const mr_tune *tune) {
+    clear_error();
+    if (pitch == 0) pitch = W;
+    if (check_dims(H, W, pitch, (int)t) != MR_OK) return 0;
+    HdomeLayout L;
+    if (hdome_layout(H, W, pitch, (int)t, conn, tune, L) != MR_OK) return 0;
+    return L.total;
+}
+
+int mr_hdome(void *img_inout, int64_t H, int64_t W, int64_t pitch, mr_dtype t, int conn,
+             int64_t h, void *ws, size_t ws_bytes, const mr_tune *tune, void *stream) {
+    HdomeLayout L;
+    int rc = hdome_common(img_inout, H, W, pitch, (int)t, conn, ws, ws_bytes, tune, L);
+    if (rc != MR_OK) return rc;
+    if (h < 0) return ofail(MR_EINVAL, "h must be >= 0 (got %lld)", (long long)h);
+    // the dome f - R lies in [0, h]: for int32 pixels h must fit the type
+    if ((int)t == MR_I32 && h > 0x7FFFFFFFll)
+        return ofail(MR_EINVAL, "h must be at most 2^31 - 1 for int32 pixels");
+    const uint32_t hk = h > 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)h;
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    void *marker = w + L.plane;
+    uint32_t *flag = (uint32_t *)(w + L.flag);
+    hipError_t e = (int)t == MR_U8
+        ? hdome_marker<uint8_t>(img_inout, marker, H, W, pitch, hk, flag, s)
+        : hdome_marker<int32_t>(img_inout, marker, H, W, pitch, hk, flag, s);
+    if (e != hipSuccess) return ohip(e, "h-dome marker");
+    rc = mr_recon_dilate(marker, img_inout, H, W, pitch, t, conn, ws, L.recon, tune, stream);
+    if (rc != MR_OK) return rc;
+    const int64_t items = H * ((W + ROW_SEG - 1) / ROW_SEG);
+    if ((int)t == MR_U8)
+        hipLaunchKernelGGL(k_hdome_out<uint8_t>, dim3(grid_for(items, 4)), dim3(256), 0, s,
+                           (uint8_t *)img_inout, (const uint8_t *)marker, H, W, pitch);
+    else
+        hipLaunchKernelGGL(k_hdome_out<int32_t>, dim3(grid_for(items, 4)), dim3(256), 0, s,
+                           (int32_t *)img_inout, (const int32_t *)marker, H, W, pitch);
+    e = hipGetLastError();
+    return e == hipSuccess ? MR_OK : ohip(e, "h-dome output");
+}
+
+int mr_regional_maxima(const void *img, void *out_u8, int64_t H, int64_t W, int64_t pitch,
+                       int64_t out_pitch, mr_dtype t, int conn, void *ws, size_t ws_bytes,
+                       const mr_tune *tune, void *stream) {
+    HdomeLayout L;
+    int rc = hdome_common(img, H, W, pitch, (int)t, conn, ws, ws_bytes, tune, L);
+    if (rc != MR_OK) return rc;
+    if (!out_u8) return ofail(MR_EINVAL, "null output");
+    if (out_pitch == 0) out_pitch = W;
+    if (out_pitch < W) return ofail(MR_EINVAL, "out_pitch below W");
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    void *marker = w + L.plane;
+    uint32_t *flag = (uint32_t *)(w + L.flag);
+    hipError_t e = (int)t == MR_U8
+        ? hdome_marker<uint8_t>(img, marker, H, W, pitch, 1u, flag, s)
+        : hdome_marker<int32_t>(img, marker, H, W, pitch, 1u, flag, s);
+    if (e != hipSuccess) return ohip(e, "regional maxima marker");
+    rc = mr_recon_dilate(marker, img, H, W, pitch, t, conn, ws, L.recon, tune, stream);
+    if (rc != MR_OK) return rc;
+    const int64_t items = H * ((W + ROW_SEG - 1) / ROW_SEG);
+    if ((int)t == MR_U8)
+        hipLaunchKernelGGL(k_rmax_out<uint8_t>, dim3(grid_for(items, 4)), dim3(256), 0, s,
+                           (const uint8_t *)img, (const uint8_t *)marker, (uint8_t *)out_u8, H, W,
+                           pitch, out_pitch, (const uint32_t *)flag);
+    else
+        hipLaunchKernelGGL(k_rmax_out<int32_t>, dim3(grid_for(items, 4)), dim3(256), 0, s,
+                           (const int32_t *)img, (const int32_t *)marker, (uint8_t *)out_u8, H, W,
+                           pitch, out_pitch, (const uint32_t *)flag);
+    e = hipGetLastError();
+    return e == hipSuccess ? MR_OK : ohip(e, "regional maxima output");
+}
+
+int mr_rgb2gray(const void *rgb, int64_t rgb_pitch, void *gray, int64_t gray_pitch, int64_t H,
+                int64_t W, void *stream) {
+    clear_error();
+    if (!rgb || !gray) return ofail(MR_EINVAL, "null image");
+    if (rgb_pitch == 0) rgb_pitch = 3 * W;
+    if (gray_pitch == 0) gray_pitch = W;
+    int rc;
+    if ((rc = check_dims(H, W, gray_pitch, 1)) != MR_OK) return rc;
+    if (rgb_pitch < 3 * W) return ofail(MR_EINVAL, "rgb_pitch %lld is below 3 W",
+                                        (long long)rgb_pitch);
+    hipStream_t s = (hipStream_t)stream;
+    const uint8_t *src = (const uint8_t *)rgb;
+    uint8_t *dst = (uint8_t *)gray;
+    int64_t x0 = 0;
+    const bool al = ((uintptr_t)src % 16 == 0) && rgb_pitch % 16 == 0 &&
+                    ((uintptr_t)dst % 16 == 0) && gray_pitch % 16 == 0;
+    if (al && W >= 16) {
+        const int64_t vec = W / 16;
+        hipLaunchKernelGGL(k_rgb2gray16, dim3(grid_for(H * vec, 256)), dim3(256), 0, s, src,
+                           rgb_pitch, dst, gray_pitch, H, vec);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return ohip(e, "rgb2gray");
+        x0 = vec * 16;
+    }
+    if (x0 < W) {
+        hipLaunchKernelGGL(k_rgb2gray1, dim3(grid_for(H * (W - x0), 256)), dim3(256), 0, s, src,
+                           rgb_pitch, dst, gray_pitch, H, x0, W);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return ohip(e, "rgb2gray");
+    }
+    return MR_OK;
+}
+
+int mr_disk13(int op, const void *in, void *out, int64_t H, int64_t W, int64_t pitch,
+              void *stream) {
+    clear_error();
+    if (op != MR_DISK_ERODE && op != MR_DISK_DILATE) return ofail(MR_EINVAL, "unknown op %d", op);
+    if (!in || !out) return ofail(MR_EINVAL, "null image");
+    if (pitch == 0) pitch = W;
+    int rc;
+    if ((rc = check_dims(H, W, pitch, 1)) != MR_OK) return rc;
+    const char *a = (const char *)in, *b = (const char *)out;
+    const size_t span = (size_t)((H - 1) * pitch + W);
+    if (a < b + span && b < a + span) return ofail(MR_EINVAL, "in and out overlap");
+    hipError_t e = launch_disk13(op == MR_DISK_ERODE, (const uint8_t *)in, (uint8_t *)out, H, W,
+                                 pitch, (hipStream_t)stream);
+    return e == hipSuccess ? MR_OK : ohip(e, "disk13");
+}
+
+size_t mr_open_disk13_workspace_bytes(int64_t H, int64_t W, int64_t pitch) {
+    clear_error();
+    if (pitch == 0) pitch = W;
+    if (check_dims(H, W, pitch, 1) != MR_OK) return 0;
+    return up256((size_t)H * (size_t)pitch);
+}
+
+int mr_open_disk13(const void *in, void *out, int64_t H, int64_t W, int64_t pitch, void *ws,
+                   size_t ws_bytes, void *stream) {
+    clear_error();
+    if (pitch == 0) pitch = W;
+    int rc;
+    if ((rc = check_dims(H, W, pitch, 1)) != MR_OK) return rc;
+    if (!ws) return ofail(MR_EINVAL, "null workspace");
+    if ((uintptr_t)ws % 256) return ofail(MR_EINVAL, "workspace must be 256-byte aligned");
+    const size_t need = up256((size_t)H * (size_t)pitch);
+    if (ws_bytes < need)
+        return ofail(MR_ENOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes,
+                     need);
+    if ((rc = mr_disk13(MR_DISK_ERODE, in, ws, H, W, pitch, stream)) != MR_OK) return rc;
+    return mr_disk13(MR_DISK_DILATE, ws, out, H, W, pitch, stream);
+}
+
+} // extern "C"

@@ -160,10 +160,13 @@ def lib():
 
 
 def header_functions():
-    """Names of the functions declared in include/mr.h."""
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(mr_[a-z_0-9]+)\s*\(", text)))
+    """Names of the functions declared in include/*.h (mr.h and mr_ops.h)."""
+    import glob
+    names = set()
+    for path in sorted(glob.glob(os.path.join(os.path.dirname(HEADER), "*.h"))):
+        text = re.sub(r"/\*.*?\*/", "", open(path).read(), flags=re.S)
+        names.update(re.findall(r"\b(mr_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 def _check(rc: int):
