@@ -16,27 +16,43 @@ tile) x 3 bytes per pixel (read J, read the mask, write J), over the launch's
 duration measured with HIP events on the call's stream during the timed
 steps. ``--gpus`` above 1 is refused: the library runs on one GPU.
 
-Three more legs are added to the same line (``--legs``):
+More legs are added to the same line (``--legs``):
 
+* ``i32``: the int32 variant of the headline image (values scaled to
+  0..65535), measured the same way with its own ``roofline`` and
+  ``bit_exact``.
+* ``small``: the cache-resident configurations, 1024^2 recon conn8 and the
+  4096^2 image's recon conn4 / conn8 and fill-holes conn4 / conn8: per-call
+  p50 / p99 over 30 calls and Mpx/s, each checked against the oracle.
 * ``batched``: 512 uneven u8 tiles (sides log-uniform 256-4096, per-tile
   seeds, ~1.0 Gpixel in all), reconstruction 8-conn: one ``mr_recon_dilate``
   per tile on one stream versus one batched launch sequence with the
   autotuner's settings (replayed as a HIP graph when the settings allow it).
-  Every batched result is checked against the oracle.
+  Every batched result is checked against the oracle, on all host cores,
+  which also gives the leg's all-cores CPU baseline.
 * ``served``: 2000 jobs (sides log-uniform 512-8192, 70 % reconstruction /
-  30 % fill-holes, ~15 Gpixel) answered from and to pinned host memory.
-  Each job is a window of one of two seeded 8192 x 8192 images, its first
-  column on a 64-byte boundary. Compared: sequential per-job launches (copy
-  in, one call, copy out, wait) versus the continuous-batching server with an
-  8 GiB arena and 128 job slots (--serve-slots), first back to back, then on one Poisson arrival trace at
+  30 % fill-holes, ~15 Gpixel). Each job is a window of one of two seeded
+  8192 x 8192 images, its first column on a 64-byte boundary. Run twice: with
+  the jobs in pinned host memory (PCIe in and out) and with the jobs already
+  in HBM (device-to-device copies into and out of the arena). Compared each
+  time: sequential per-job launches (copy in, one call, copy out, wait)
+  versus the continuous-batching server with an 8 GiB arena and 128 job slots
+  (--serve-slots), first back to back, then on one Poisson arrival trace at
   0.8 x the sequential capacity (p50/p99 of completion - arrival). Untimed
   passes afterwards hash every result of the sequential path and of the
-  server (back to back and on the trace), which must agree job by job; a
-  sample of jobs is checked against the oracle.
+  server, which must agree job by job, and every job is checked against the
+  oracle on all host cores (the leg's all-cores CPU baseline).
 * ``erode``: reconstruction by erosion (``mr_recon_erode``) on a 16384 x
   16384 u8 image, 8-conn, the same mask with the marker raised by 30: a
   complement pass, the reconstruction by dilation, the complement back.
   Checked against the oracle.
+* ``ops``: the other Table II operations on the same 16384^2 image: RGB2Gray,
+  opening by the 13 x 13 disk, distance transform, CCL, area threshold,
+  h-dome and regional maxima, each with its time, algorithmic bytes against
+  the HBM peak, and an oracle check.
+
+The line also carries ``copy_bandwidth``: what a plain 1 GiB device copy
+reaches, beside the 8 TB/s peak the rooflines use.
 
 ``--atomic-probe`` instead times the device atomic-rate probe
 (``mr_probe_atomics``: relaxed device-scope add, and load + compare-and-swap,
@@ -91,10 +107,13 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload_key: str):
+def traffic_path(size: int, dtype: str, conn: int) -> str:
+    return os.path.join(ROOT, "profiles", f"tile_round_traffic_{size}_{dtype}_conn{conn}.json")
+
+
+def load_traffic(workload_key: str, path: str):
     """HBM bytes per tile-round launch from the committed rocprofv3 counter
     runs, if they were taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "tile_round_traffic.json")
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
@@ -144,12 +163,203 @@ def summarize_traffic(fetch_csv: str, write_csv: str, args) -> None:
         "fetch_kib_raw": out["fetch"]["kib_per_launch_raw"],
         "write_kib_raw": out["write"]["kib_per_launch_raw"],
     }
-    path = os.path.join(ROOT, "profiles", "tile_round_traffic.json")
+    path = traffic_path(args.size, args.dtype, args.conn)
     json.dump(rec, open(path, "w"), indent=1)
     print(json.dumps(rec))
 
 def pct(xs, q) -> float:
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q))
+
+
+def measure_recon(args, torch, mrecon, dev, marker, mask, conn, tune) -> dict:
+    """K whole mr_recon_dilate calls on fresh marker copies resident in HBM
+    (after W warm-up calls), with the tile rounds timed by the library's
+    events on the call's stream; every output checked equal, the last one
+    against the oracle."""
+    S = marker.shape[0]
+    dt = "u8" if marker.dtype == np.uint8 else "i32"
+    T = 1 if dt == "u8" else 4
+    d_mask = torch.from_numpy(mask).to(dev)
+    d_src = torch.from_numpy(marker).to(dev)
+    K, W = args.steps, args.warmup
+    wsb = mrecon.workspace_bytes(mrecon.MR_OP_RECON, S, S, d_src.dtype, conn, tune)
+    copies = [torch.empty_like(d_src) for _ in range(K)]
+    wss = [mrecon.alloc_workspace(wsb, dev) for _ in range(K)]
+    stream = torch.cuda.current_stream()
+    for i in range(W):
+        copies[0].copy_(d_src)
+        mrecon.recon_dilate(copies[0], d_mask, conn, tune=tune, workspace=wss[0], stream=stream)
+    for c in copies:
+        c.copy_(d_src)
+    torch.cuda.synchronize()
+
+    # span mode: one pair of events per run of consecutive tile rounds (its
+    # average launch duration includes the dispatch gaps between them);
+    # "launches" brackets every launch, at a few microseconds per event
+    mrecon.timing_enable(args.timing)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(K):
+        mrecon.recon_dilate(copies[i], d_mask, conn, tune=tune, workspace=wss[i], stream=stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    mrecon.timing_enable(False)
+    launches = mrecon.timing_collect()
+
+    # per-launch algorithmic bytes of the tile rounds, matched by round number
+    n_tiles = ((S + 61) // 62) ** 2
+    px_per_tile = S * S / n_tiles
+    bytes_per_visit = 3 * T * px_per_tile
+    per_step = []
+    li = 0
+    tile_ms, tile_bytes, tile_launches = 0.0, 0.0, 0
+    seed_ms = queue_ms = tq_ms = 0.0
+    for i in range(K):
+        mrecon.status(wss[i], stream)
+        rt = mrecon.read_round_tiles(wss[i])
+        cnt = mrecon.read_counters(wss[i])
+        step_tiles = 0
+        # launches of step i: tile rounds 1..R, then optionally seed and queue
+        while li < len(launches):
+            kind, rnd, ms, nl = launches[li]
+            if kind == "tile_round":
+                if rnd == 1 and step_tiles:
+                    break  # next step's first round
+                # every launch counts, also the few that find an empty list
+                # after convergence, as in a profiler's per-kernel average; a
+                # span record covers rounds rnd .. rnd + nl - 1
+                visits = sum(rt[r - 1] for r in range(rnd, rnd + nl) if r - 1 < len(rt))
+                step_tiles += visits
+                tile_ms += ms
+                tile_bytes += visits * bytes_per_visit
+                tile_launches += nl
+            elif kind == "seed":
+                seed_ms += ms
+            elif kind == "queue":
+                queue_ms += ms
+            elif kind == "tile_queue":
+                tq_ms += ms
+            li += 1
+        per_step.append({"tiles": step_tiles, "counters": cnt, "round_tiles": rt})
+
+    npx = S * S
+    ms_per_step = elapsed * 1e3 / K
+    achieved = tile_bytes / (tile_ms * 1e-3) / 1e9 if tile_ms else 0.0
+    b_alg_step = sum(p["tiles"] for p in per_step) / K * bytes_per_visit
+    workload_key = f"recon {S}x{S} {dt} conn{conn}"
+    traffic = load_traffic(workload_key, traffic_path(S, dt, conn))
+    out = {
+        "mpx_s": round(npx * K / elapsed / 1e6, 1),
+        "ms_per_call": round(ms_per_step, 4),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_tile_round",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "launches": tile_launches,
+            "avg_launch_ms": round(tile_ms / max(1, tile_launches), 4),
+            "bytes_per_tile_visit": round(bytes_per_visit, 1),
+            "timing": args.timing,
+        },
+        "whole_call": {
+            "b_alg_gb_per_step": round(b_alg_step / 1e9, 4),
+            "b_alg_gbs": round(b_alg_step / (ms_per_step * 1e-3) / 1e9, 1),
+            "frac_of_peak": round(b_alg_step / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "passes_equivalent": round(b_alg_step / (3 * T * npx), 3),
+            "tile_round_ms_per_step": round(tile_ms / K, 4),
+            "seed_ms_per_step": round(seed_ms / K, 4),
+            "queue_ms_per_step": round(queue_ms / K, 4),
+            "tile_queue_ms_per_step": round(tq_ms / K, 4),
+        },
+        "counters_last_step": per_step[-1]["counters"],
+        "round_tiles_last_step": [int(x) for x in per_step[-1]["round_tiles"]],
+        "tune": tune or "library default",
+    }
+    # every timed output must be the same image; the last one then goes to
+    # the oracle
+    same = all(torch.equal(copies[i], copies[K - 1]) for i in range(K - 1))
+    if not args.no_verify:
+        import oracle
+        got = copies[K - 1].cpu().numpy()
+        want, _ = oracle.recon_dilate(marker, mask, conn)
+        out["bit_exact"] = bool(same and np.array_equal(got, want))
+        out["bit_exact_outputs_checked"] = K
+        log(f"recon {S}x{S} {dt}: {ms_per_step:.3f} ms per call, bit-exact vs oracle:",
+            out["bit_exact"])
+    del copies, wss, d_mask, d_src
+    return out
+
+
+def copy_bandwidth(torch, dev, nbytes: int = 1 << 30, reps: int = 10) -> dict:
+    """Achievable HBM bandwidth: a device-to-device copy of 1 GiB (read +
+    write counted), timed with events, best of `reps`."""
+    a = torch.ones(nbytes, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = 1e30
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    gbs = 2 * nbytes / (best * 1e-3) / 1e9
+    return {"gbs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "how": "torch device copy of 1 GiB, bytes read + written, best of 10"}
+
+
+def leg_small(args, dev) -> dict:
+    """The cache-resident configurations: 1024^2 u8 recon conn8, and on the
+    4096^2 image (800 disks, 5 % rings) recon conn4 and conn8 and fill-holes
+    conn4 and conn8 of the thresholded image. Each: per-call time over reps
+    (p50 / p99) on fresh inputs in HBM, Mpx/s at p50, and the last output
+    against the oracle."""
+    import torch
+    import oracle
+    from paper_1311_0378_amd import mrecon, synth
+
+    reps, warm = 30, 3
+    stream = torch.cuda.current_stream()
+    m1, k1 = synth.single_1024()
+    m4, k4, b4 = synth.single_4096()
+    cases = [("recon 1024x1024 u8 conn8", m1, k1, 8), ("recon 4096x4096 u8 conn4", m4, k4, 4),
+             ("recon 4096x4096 u8 conn8", m4, k4, 8), ("fill 4096x4096 u8 conn4", b4, None, 4),
+             ("fill 4096x4096 u8 conn8", b4, None, 8)]
+    out = {}
+    for name, a, m, conn in cases:
+        src = torch.from_numpy(a).to(dev)
+        dm = torch.from_numpy(m).to(dev) if m is not None else None
+        op = mrecon.MR_OP_RECON if m is not None else mrecon.MR_OP_FILL
+        ws = mrecon.alloc_workspace(mrecon.workspace_bytes(op, *a.shape, src.dtype, conn), dev)
+        work = torch.empty_like(src)
+        times = []
+        for r in range(warm + reps):
+            work.copy_(src)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            if m is not None:
+                mrecon.recon_dilate(work, dm, conn, workspace=ws, stream=stream)
+            else:
+                mrecon.fill_holes(work, conn, workspace=ws, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            if r >= warm:
+                times.append(e0.elapsed_time(e1))
+        mrecon.status(ws, stream)
+        ok = None
+        if not args.no_verify:
+            want = (oracle.recon_dilate(a, m, conn) if m is not None else oracle.fill_holes(a, conn))[0]
+            ok = bool(np.array_equal(work.cpu().numpy(), want))
+        p50 = pct(times, 50)
+        out[name] = {"ms_p50": round(p50, 4), "ms_p99": round(pct(times, 99), 4),
+                     "mpx_s": round(a.size / p50 / 1e3, 1), "reps": reps, "bit_exact": ok}
+        log(f"small: {name} {p50:.3f} ms, exact {ok}")
+    return out
 
 
 def leg_batched(args, dev) -> dict:
@@ -221,11 +431,19 @@ def leg_batched(args, dev) -> dict:
 
     same = all(bool(torch.equal(a, b)) for a, b in zip(work, per_tile_out))
     exact = True
+    cpu_all = None
     if not args.no_verify:
         outs = [w.cpu().numpy() for w in work]
-        with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
-            exact = all(ex.map(lambda i: bool(np.array_equal(
-                outs[i], oracle.recon_dilate(tiles[i][0], tiles[i][1], 8)[0])), range(n)))
+        threads = min(16, os.cpu_count() or 1)
+        t1 = time.perf_counter()
+        with ThreadPoolExecutor(threads) as ex:
+            wants = list(ex.map(lambda i: oracle.recon_dilate(tiles[i][0], tiles[i][1], 8)[0],
+                                range(n)))
+        t_or = time.perf_counter() - t1
+        exact = all(bool(np.array_equal(outs[i], wants[i])) for i in range(n))
+        cpu_all = {"value": round(npx / t_or / 1e6, 1), "unit": "Mpixel/s", "cores": threads,
+                   "kind": "oracle", "sample": f"all {n} tiles, one tile per thread at a time, "
+                                              f"{t_or:.1f} s on {cpu_model()}"}
         log("batched: bit-exact vs oracle:", exact)
     if graph is not None:
         graph.close()
@@ -245,6 +463,7 @@ def leg_batched(args, dev) -> dict:
         "reps": reps,
         "bit_exact": bool(exact and same) if not args.no_verify else None,
         "batched_equals_per_tile": same,
+        "cpu_baseline_all_cores": cpu_all,
     }
 
 
@@ -516,9 +735,11 @@ def leg_served(args, dev) -> dict:
     torch.cuda.empty_cache()
     ref_dev, device = run_mode("device")
     t1 = time.time()
-    with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+    threads = min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(threads) as ex:
         want = list(ex.map(oracle_hash, range(n)))
-    log(f"served: oracle over all {n} jobs in {time.time() - t1:.1f}s")
+    t_or = time.time() - t1
+    log(f"served: oracle over all {n} jobs in {t_or:.1f}s")
     host["oracle_bit_exact"] = ref_host == want
     device["oracle_bit_exact"] = ref_dev == want
     log("served: host jobs agree:", host["results_agree"], "oracle:", host["oracle_bit_exact"],
@@ -531,7 +752,148 @@ def leg_served(args, dev) -> dict:
         "host_jobs": host,
         "device_jobs": device,
         "oracle_checked_jobs": n,
+        "cpu_baseline_all_cores": {
+            "value": round(npx / t_or / 1e6, 1), "unit": "Mpixel/s", "cores": threads,
+            "kind": "oracle", "sample": f"all {n} jobs, one job per thread at a time (window "
+                                       f"copies and hashing included), {t_or:.1f} s on "
+                                       f"{cpu_model()}"},
     }
+
+
+def leg_ops(args, dev, mask) -> dict:
+    """The other Table II operations on the headline's 16384^2 workload:
+    RGB2Gray on a colour image made from the mask, opening by the 13 x 13
+    disk on the mask, the distance transform, CCL and area threshold on the
+    binary image (mask >= 128), h-dome (h = 20) and regional maxima on the
+    mask. Each is timed with events around K calls on inputs resident in HBM
+    and checked against the oracle (the opening on sampled windows, the others
+    on the whole image)."""
+    import torch
+    import oracle
+    from paper_1311_0378_amd import ops, synth
+
+    S = mask.shape[0]
+    npx = S * mask.shape[1]
+    K = max(1, min(args.steps, 5))
+    stream = torch.cuda.current_stream()
+    out = {"workload": f"{S}x{S}, from the headline's mask (12800 disks, seed 0)", "calls": K}
+    t0 = time.time()
+    binary = synth.binary_from_mask(mask)
+    rgb = synth.rgb_from_mask(mask)
+    log(f"ops: inputs in {time.time() - t0:.1f}s")
+    d_mask = torch.from_numpy(mask).to(dev)
+    d_bin = torch.from_numpy(binary).to(dev)
+
+    def timed(fn, prep=None):
+        """ms per call over K calls (prep runs before each, outside the
+        timing of that call), and the last call's output."""
+        res, total = None, 0.0
+        fn() if prep is None else (prep(), fn())  # warm-up
+        for _ in range(K):
+            if prep is not None:
+                prep()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            res = fn()
+            b.record(stream)
+            b.synchronize()
+            total += a.elapsed_time(b)
+        return total / K, res
+
+    def line(ms, alg_bytes, exact, **kw):
+        gbs = alg_bytes / (ms * 1e-3) / 1e9
+        d = {"ms": round(ms, 4), "mpx_s": round(npx / ms / 1e3, 1),
+             "algorithmic_gb": round(alg_bytes / 1e9, 4),
+             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)},
+             "bit_exact": exact}
+        d.update(kw)
+        return d
+
+    verify = not args.no_verify
+    # RGB2Gray: 3 bytes in, 1 out per pixel
+    d_rgb = torch.from_numpy(rgb).to(dev)
+    gray = torch.empty((S, S), dtype=torch.uint8, device=dev)
+    ms, _ = timed(lambda: ops.rgb2gray(d_rgb, out=gray))
+    ok = bool(np.array_equal(gray.cpu().numpy(), oracle.rgb2gray(rgb))) if verify else None
+    out["rgb2gray"] = line(ms, 4 * npx, ok)
+    log(f"ops: rgb2gray {ms:.3f} ms, exact {ok}")
+    del d_rgb, gray
+
+    # opening: erosion and dilation, each 1 byte in and 1 out per pixel
+    o = torch.empty_like(d_mask)
+    wso = torch.empty(S * S, dtype=torch.uint8, device=dev)
+    ms, _ = timed(lambda: ops.open_disk13(d_mask, out=o, workspace=wso))
+    ok = None
+    if verify:
+        rng = np.random.default_rng(11)
+        got = o.cpu().numpy()
+        ok = True
+        for _ in range(48):
+            y, x = (int(v) for v in rng.integers(0, S - 256, 2))
+            y0, x0 = max(0, y - 12), max(0, x - 12)
+            y1, x1 = min(S, y + 256 + 12), min(S, x + 256 + 12)
+            want = oracle.open_disk13(mask[y0:y1, x0:x1])
+            ok &= bool(np.array_equal(got[y:y + 256, x:x + 256],
+                                      want[y - y0:y - y0 + 256, x - x0:x - x0 + 256]))
+    out["open_disk13"] = line(ms, 4 * npx, ok, check="48 windows of 256x256 (12-pixel margin)",
+                              note="two passes (erosion, dilation); bound by instruction "
+                                   "issue rather than HBM")
+    log(f"ops: open {ms:.3f} ms, exact {ok}")
+    del o, wso
+
+    # distance transform: 1 byte in, 4 out per pixel (round 1; later rounds
+    # revisit a few tiles)
+    dist = torch.empty((S, S), dtype=torch.int32, device=dev)
+    wsd = torch.empty(ops.lib().mr_distance_transform_workspace_bytes(S, S, 8),
+                      dtype=torch.uint8, device=dev)
+    ms, _ = timed(lambda: ops.distance_transform(d_bin, 8, out=dist, workspace=wsd))
+    ok = bool(np.array_equal(dist.cpu().numpy(), oracle.distance_transform(binary, 8))) \
+        if verify else None
+    out["distance_transform"] = line(ms, 5 * npx, ok, conn=8)
+    log(f"ops: distance transform {ms:.3f} ms, exact {ok}")
+    del dist, wsd
+
+    # CCL: 1 byte in, 4-byte labels out; then area threshold on the labels
+    # (4 bytes read and 4 written per pixel)
+    lab = torch.empty((S, S), dtype=torch.int32, device=dev)
+    wsc = torch.empty(ops.lib().mr_ccl_workspace_bytes(S, S), dtype=torch.uint8, device=dev)
+    ms, _ = timed(lambda: ops.ccl(d_bin, 8, out=lab, workspace=wsc))
+    want_lab = oracle.ccl(binary, 8) if verify else None
+    ok = bool(np.array_equal(lab.cpu().numpy(), want_lab)) if verify else None
+    out["ccl"] = line(ms, 5 * npx, ok, conn=8)
+    log(f"ops: ccl {ms:.3f} ms, exact {ok}")
+    del wsc
+    lab2 = torch.empty_like(lab)
+    wsa = torch.empty(ops.lib().mr_area_threshold_workspace_bytes(S, S), dtype=torch.uint8,
+                      device=dev)
+    lo, hi = 150, 500
+    ms, _ = timed(lambda: ops.area_threshold(lab2, lo, hi, workspace=wsa),
+                  prep=lambda: lab2.copy_(lab))
+    ok = bool(np.array_equal(lab2.cpu().numpy(), oracle.area_threshold(want_lab, lo, hi)[0])) \
+        if verify else None
+    out["area_threshold"] = line(ms, 8 * npx, ok, range=[lo, hi])
+    log(f"ops: area threshold {ms:.3f} ms, exact {ok}")
+    del lab, lab2, wsa
+
+    # h-dome and regional maxima: a reconstruction each, plus two streaming
+    # passes (the minimum is the reconstruction's 3 bytes per pixel)
+    h = 20
+    hd = torch.empty_like(d_mask)
+    wsh = torch.empty(ops.hdome_workspace_bytes(S, S, S, torch.uint8, 8), dtype=torch.uint8,
+                      device=dev)
+    ms, _ = timed(lambda: ops.hdome(hd, h, 8, workspace=wsh), prep=lambda: hd.copy_(d_mask))
+    ok = bool(np.array_equal(hd.cpu().numpy(), oracle.hdome(mask, h, 8))) if verify else None
+    out["hdome"] = line(ms, 3 * npx, ok, h=h)
+    log(f"ops: h-dome {ms:.3f} ms, exact {ok}")
+    rm = torch.empty_like(d_mask)
+    ms, _ = timed(lambda: ops.regional_maxima(d_mask, 8, out=rm, workspace=wsh))
+    ok = bool(np.array_equal(rm.cpu().numpy(), oracle.regional_maxima(mask, 8))) \
+        if verify else None
+    out["regional_maxima"] = line(ms, 3 * npx, ok)
+    log(f"ops: regional maxima {ms:.3f} ms, exact {ok}")
+    del hd, rm, wsh, d_mask, d_bin
+    return out
 
 
 def atomic_probe(torch, mrecon, dev, reps: int = 5) -> dict:
@@ -577,9 +939,9 @@ def main():
     ap.add_argument("--dtype", default="u8", choices=["u8", "i32"])
     ap.add_argument("--conn", type=int, default=8, choices=[4, 8])
     ap.add_argument("--tune", default="", help="k=v,... overrides of mr_tune")
-    ap.add_argument("--legs", default="batched,served,erode",
-                    help="extra legs after the headline: comma list of batched, served, erode, "
-                         "or none")
+    ap.add_argument("--legs", default="i32,small,batched,served,erode,ops",
+                    help="extra legs after the headline: comma list of i32, small, batched, "
+                         "served, erode, ops, or none")
     ap.add_argument("--erode-tune", default="sweep_rounds=-1,tail_rounds=0",
                     help="k=v,... mr_tune overrides for the erode leg (default: tile rounds until "
                          "none is dirty, the fastest schedule measured for that workload)")
@@ -633,15 +995,6 @@ def main():
     n_disks = 12800 if S == 16384 else synth.density_disks(S, S)
     marker, mask = synth.make_tile(S, S, n_disks, 0, dt, 0.0)
     log(f"generated {S}x{S} {dt} in {time.time() - t0:.1f}s")
-    tdt = torch.uint8 if dt == "u8" else torch.int32
-    T = 1 if dt == "u8" else 4
-    d_mask = torch.from_numpy(mask).to(dev)
-    d_src = torch.from_numpy(marker).to(dev)
-    K, W = args.steps, args.warmup
-    wsb = mrecon.workspace_bytes(mrecon.MR_OP_RECON, S, S, tdt, conn, tune)
-    copies = [torch.empty_like(d_src) for _ in range(K)]
-    wss = [mrecon.alloc_workspace(wsb, dev) for _ in range(K)]
-    stream = torch.cuda.current_stream()
 
     if args.calibrate_copy:
         a = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
@@ -651,76 +1004,14 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    for i in range(W):
-        copies[0].copy_(d_src)
-        mrecon.recon_dilate(copies[0], d_mask, conn, tune=tune, workspace=wss[0], stream=stream)
-    for c in copies:
-        c.copy_(d_src)
-    torch.cuda.synchronize()
-
-    # span mode: one pair of events per run of consecutive tile rounds (its
-    # average launch duration includes the dispatch gaps between them);
-    # "launches" brackets every launch, at a few microseconds per event
-    mrecon.timing_enable(args.timing)
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for i in range(K):
-        mrecon.recon_dilate(copies[i], d_mask, conn, tune=tune, workspace=wss[i], stream=stream)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    mrecon.timing_enable(False)
-    launches = mrecon.timing_collect()
-
-    # per-launch algorithmic bytes of the tile rounds, matched by round number
-    n_tiles = ((S + 61) // 62) ** 2
-    px_per_tile = S * S / n_tiles
-    bytes_per_visit = 3 * T * px_per_tile
-    per_step = []
-    li = 0
-    tile_ms, tile_bytes, tile_launches = 0.0, 0.0, 0
-    seed_ms = queue_ms = tq_ms = 0.0
-    for i in range(K):
-        rt = mrecon.read_round_tiles(wss[i])
-        cnt = mrecon.read_counters(wss[i])
-        step_tiles = 0
-        # launches of step i: tile rounds 1..R, then optionally seed and queue
-        while li < len(launches):
-            kind, rnd, ms, nl = launches[li]
-            if kind == "tile_round":
-                if rnd == 1 and step_tiles:
-                    break  # next step's first round
-                # every launch counts, also the few that find an empty list
-                # after convergence, as in a profiler's per-kernel average; a
-                # span record covers rounds rnd .. rnd + nl - 1
-                visits = sum(rt[r - 1] for r in range(rnd, rnd + nl) if r - 1 < len(rt))
-                step_tiles += visits
-                tile_ms += ms
-                tile_bytes += visits * bytes_per_visit
-                tile_launches += nl
-            elif kind == "seed":
-                seed_ms += ms
-            elif kind == "queue":
-                queue_ms += ms
-            elif kind == "tile_queue":
-                tq_ms += ms
-            li += 1
-        per_step.append({"tiles": step_tiles, "counters": cnt, "round_tiles": rt})
-
-    npx = S * S
-    ms_per_step = elapsed * 1e3 / K
-    value = npx * K / elapsed / 1e6
-    achieved = tile_bytes / (tile_ms * 1e-3) / 1e9 if tile_ms else 0.0
-    b_alg_step = sum(p["tiles"] for p in per_step) / K * bytes_per_visit
-    workload_key = f"recon {S}x{S} {dt} conn{conn}"
-    traffic = load_traffic(workload_key)
     result = {
         "metric": "reconstructed Mpixel/s (bit-exact) + %HBM roofline; batched vs per-tile; p50/p99",
-        "value": round(value, 1),
+        "value": None,
         "unit": "Mpixel/s",
         "n_gpus": 1,
-        "steps": K,
-        "warmup": W,
-        "ms_per_step": round(ms_per_step, 4),
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -728,58 +1019,46 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"recon_dilate {S}x{S} {dt} conn{conn}, {n_disks} disks, seed 0",
                    "image": f"{S}x{S}", "pixel": dt, "conn": conn},
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_tile_round",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-            "launches": tile_launches,
-            "avg_launch_ms": round(tile_ms / max(1, tile_launches), 4),
-            "bytes_per_tile_visit": round(bytes_per_visit, 1),
-            "timing": args.timing,
-        },
-        "whole_call": {
-            "b_alg_gb_per_step": round(b_alg_step / 1e9, 4),
-            "b_alg_gbs": round(b_alg_step / (ms_per_step * 1e-3) / 1e9, 1),
-            "passes_equivalent": round(b_alg_step / (3 * T * npx), 3),
-            "tile_round_ms_per_step": round(tile_ms / K, 4),
-            "seed_ms_per_step": round(seed_ms / K, 4),
-            "queue_ms_per_step": round(queue_ms / K, 4),
-            "tile_queue_ms_per_step": round(tq_ms / K, 4),
-        },
-        "counters_last_step": per_step[-1]["counters"],
-        "round_tiles_last_step": [int(x) for x in per_step[-1]["round_tiles"]],
-        "tune": tune or "library default",
     }
-
-    # every timed output must be the same image; the last one then goes to
-    # the oracle
-    same = all(torch.equal(copies[i], copies[K - 1]) for i in range(K - 1))
-    got = copies[K - 1].cpu().numpy()
-    if not args.no_verify or not args.no_cpu_baseline:
+    head = measure_recon(args, torch, mrecon, dev, marker, mask, conn, tune)
+    result["value"] = head.pop("mpx_s")
+    result["ms_per_step"] = head.pop("ms_per_call")
+    result.update(head)
+    if not args.no_cpu_baseline:
         import oracle
-        t1 = time.perf_counter()
-        want, _ = oracle.recon_dilate(marker, mask, conn)
-        t_or = time.perf_counter() - t1
-        if not args.no_verify:
-            result["bit_exact"] = bool(same and np.array_equal(got, want))
-            result["bit_exact_outputs_checked"] = K
-            log("bit-exact vs oracle:", result["bit_exact"])
-        if not args.no_cpu_baseline:
-            result["cpu_baseline"] = {
-                "value": round(npx / t_or / 1e6, 2), "unit": "Mpixel/s", "cores": 1,
-                "kind": "oracle",
-                "sample": f"the whole {S}x{S} {dt} image, one sequential oracle run "
-                          f"({t_or:.1f} s) on {cpu_model()}, {os.cpu_count()} threads visible"}
+        # the oracle as it stands, one thread, on the whole image: median of 3
+        times = []
+        for _ in range(3):
+            t1 = time.perf_counter()
+            oracle.recon_dilate(marker, mask, conn)
+            times.append(time.perf_counter() - t1)
+        t_or = float(np.median(times))
+        result["cpu_baseline"] = {
+            "value": round(S * S / t_or / 1e6, 2), "unit": "Mpixel/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"the whole {S}x{S} {dt} image, median of 3 sequential oracle runs "
+                      f"({', '.join(f'{x:.2f}' for x in times)} s) on {cpu_model()}, "
+                      f"{os.cpu_count()} threads visible"}
+    result["copy_bandwidth"] = copy_bandwidth(torch, dev)
     legs = [x for x in args.legs.split(",") if x and x != "none"]
-    unknown = set(legs) - {"batched", "served", "erode"}
+    unknown = set(legs) - {"i32", "small", "batched", "served", "erode", "ops"}
     if unknown:
         raise SystemExit(f"unknown legs: {sorted(unknown)}")
-    del copies, wss, d_mask, d_src
     torch.cuda.empty_cache()
+    if "i32" in legs and dt == "u8":
+        # the int32 variant of the same workload (values scaled to 0..65535)
+        t0 = time.time()
+        marker32, mask32 = synth.make_tile(S, S, n_disks, 0, "i32", 0.0)
+        log(f"i32: generated in {time.time() - t0:.1f}s")
+        leg = measure_recon(args, torch, mrecon, dev, marker32, mask32, conn, tune)
+        leg["workload"] = f"recon_dilate {S}x{S} i32 conn{conn}, {n_disks} disks, seed 0, " \
+                          "values scaled to 0..65535"
+        result["i32"] = leg
+        del marker32, mask32
+        torch.cuda.empty_cache()
+    if "small" in legs:
+        result["small"] = leg_small(args, dev)
+        torch.cuda.empty_cache()
     if "batched" in legs:
         result["batched"] = leg_batched(args, dev)
         torch.cuda.empty_cache()
@@ -788,6 +1067,13 @@ def main():
         torch.cuda.empty_cache()
     if "erode" in legs:
         result["erode"] = leg_erode(args, dev)
+        torch.cuda.empty_cache()
+    if "ops" in legs:
+        if dt == "u8":
+            result["ops"] = leg_ops(args, dev, mask)
+        else:
+            u8_mask = synth.make_tile(S, S, n_disks, 0, "u8", 0.0)[1]
+            result["ops"] = leg_ops(args, dev, u8_mask)
     print(json.dumps(result), flush=True)
 
 

@@ -230,3 +230,17 @@ def poisson_arrivals(n: int, rate_per_s: float, seed: int = 2) -> np.ndarray:
     """Arrival times (seconds from 0) of a Poisson process of the given rate."""
     rng = np.random.default_rng(seed)
     return np.cumsum(rng.exponential(1.0 / rate_per_s, n))
+
+
+def rgb_from_mask(mask: np.ndarray) -> np.ndarray:
+    """An H x W x 3 uint8 colour image made from a u8 mask of this module, for
+    the RGB-to-grayscale workload: the brighter a pixel of the mask (tissue,
+    blobs), the darker and bluer the colour, as in stained tissue (background
+    near white, blobs purple). Channels, with m the mask value:
+    R = 235 - (141 m >> 8), G = 225 - (205 m >> 8), B = 240 - (77 m >> 8),
+    clipped to 0..255 (integer arithmetic, deterministic)."""
+    m = mask.astype(np.int32)
+    r = 235 - ((141 * m) >> 8)
+    g = 225 - ((205 * m) >> 8)
+    b = 240 - ((77 * m) >> 8)
+    return np.clip(np.stack([r, g, b], -1), 0, 255).astype(np.uint8)
