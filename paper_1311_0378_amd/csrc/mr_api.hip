@@ -80,6 +80,13 @@ Layout layout_for(int64_t n_tiles, int64_t fill_plane_bytes, int64_t plane_pitch
 
 int64_t tiles_across(int64_t n) { return (n + TI - 1) / TI; }
 
+// uint8 planes whose base and pitch are multiples of 16 bytes: the tile
+// loads then move whole aligned 16-byte words (and the rounds may prefetch)
+bool staged_planes(int t, const ImgDesc &d) {
+    const auto a16 = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
+    return t == MR_U8 && a16(d.J) && a16(d.I) && d.pJ % 16 == 0 && d.pI % 16 == 0;
+}
+
 bool valid_dtype(int t) { return t == MR_U8 || t == MR_I32; }
 
 int check_tune(const mr_tune *tn) {
@@ -484,6 +491,7 @@ int run_single(int op, void *J_io, const void *I, int64_t H, int64_t W, int64_t 
     imgs.n = 1;
     imgs.owner = nullptr;
     imgs.d = (const ImgDesc *)((char *)ws + L.off_desc);
+    imgs.staged = staged_planes(t, d) ? 1 : 0;
     hipError_t e = launch_put_desc((ImgDesc *)imgs.d, d, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "descriptor");
     return run_sequence(t, conn, imgs, L, ws, tn, (hipStream_t)stream, op == MR_OP_FILL, op);
@@ -567,7 +575,9 @@ int run_batch(const mr_tile *tiles, int32_t n, int t, int conn, void *ws, size_t
     ImgDesc *dd = (ImgDesc *)((char *)ws + bp.L.off_desc);
     hipError_t e = launch_put_descs(dd, bp.descs.data(), n, s);
     if (e != hipSuccess) return hip_fail(e, "descriptors");
-    Imgs imgs{dd, n, nullptr};
+    Imgs imgs{dd, n, nullptr, 1};
+    for (const auto &d : bp.descs)
+        if (!staged_planes(t, d)) imgs.staged = 0;
     const int op_all = bp.any_fill ? (bp.any_recon ? -1 : MR_OP_FILL) : MR_OP_RECON;
     return run_sequence(t, conn, imgs, bp.L, ws, effective_tune(tune), s, bp.any_fill, op_all);
 }

@@ -74,6 +74,9 @@ struct Imgs {
     const ImgDesc *d;
     int32_t n;
     const uint32_t *owner;
+    // 1 when every image is uint8 with 16-byte aligned planes and pitches
+    // (both J and I): the tile rounds may then use the pipelined kernel
+    int32_t staged;
 };
 
 constexpr uint32_t Q_EMPTY = 0xFFFFFFFFu;

@@ -54,17 +54,48 @@ __device__ __forceinline__ uint32_t from_upper_lane(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130 /* wave_shl:1 */, 0xF, 0xF, true);
 }
 
+// Data that earlier launches wrote and this one only reads (descriptors,
+// owner tables, the dirty lists and list lengths of the round being run),
+// read through the scalar cache: uniform loads that wait on the scalar
+// counter, not on the vector memory counter behind this wave's own loads
+// and stores.
+template <typename X> using kptr = const __attribute__((address_space(4))) X *;
+template <typename X> __device__ __forceinline__ kptr<X> kconst(const X *p) {
+    return (kptr<X>)p;
+}
+
+// Field-wise copy (the implicit copy constructor does not bind to a
+// constant-address-space object).
+__device__ __forceinline__ ImgDesc desc_at(kptr<ImgDesc> d, int64_t k) {
+    ImgDesc r;
+    r.J = d[k].J;
+    r.I = d[k].I;
+    r.out = d[k].out;
+    r.H = d[k].H;
+    r.W = d[k].W;
+    r.pJ = d[k].pJ;
+    r.pI = d[k].pI;
+    r.tile_base = d[k].tile_base;
+    r.first_round = d[k].first_round;
+    r.ntx = d[k].ntx;
+    r.nty = d[k].nty;
+    r.op = d[k].op;
+    r.done = d[k].done;
+    return r;
+}
+
 // Descriptor of the image that owns `tile` (owner table, else binary search
 // on tile_base).
 __device__ __forceinline__ ImgDesc load_desc(Imgs imgs, int64_t tile) {
-    if (imgs.owner) return imgs.d[imgs.owner[tile]];
+    const kptr<ImgDesc> d = kconst(imgs.d);
+    if (imgs.owner) return desc_at(d, kconst(imgs.owner)[tile]);
     int lo = 0, hi = imgs.n - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (imgs.d[mid].tile_base <= tile) lo = mid;
+        if (d[mid].tile_base <= tile) lo = mid;
         else hi = mid - 1;
     }
-    return imgs.d[lo];
+    return desc_at(d, lo);
 }
 
 // Coherent (device-scope) access to the working image, used while other
@@ -141,22 +172,22 @@ constexpr int CPOL_DEVICE = 16;
 constexpr int STAGE_BYTES = TS * SROW;
 static_assert(2 * STAGE_BYTES <= TS * (TS + 1) * 4, "the stage must fit in the transpose buffer");
 
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+
+// Lane r fetches tile row r, chunk k per load. Staged planes have a pitch of
+// at least 16 and H * pitch < 2^32, so rows and offsets fit 32 bits. The lane
+// id goes through an empty asm so that nothing derived from it is hoisted out
+// of the caller's tile loop: held across the sweeps, such values would be
+// spilled, and every reload would wait for all memory operations in flight.
 template <int CPOL = 0>
-__device__ __forceinline__ void stage_u8(__amdgpu_buffer_rsrc_t rs, int64_t gy0, int64_t H,
-                                         uint32_t pitch, int64_t a, int lane, uint8_t *st) {
-    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
-    // Lane r fetches tile row r, chunk k per load. Staged planes have a pitch
-    // of at least 16 and H * pitch < 2^32, so rows and offsets fit 32 bits.
-    // The lane id goes through an empty asm so that nothing derived from it
-    // is hoisted out of the caller's tile loop: held across the sweeps, such
-    // values would be spilled, and every reload would wait for all memory
-    // operations in flight.
+__device__ __forceinline__ void stage_issue(__amdgpu_buffer_rsrc_t rs, int64_t gy0, int64_t H,
+                                            uint32_t pitch, int64_t a, int lane, v4u (&v)[5],
+                                            bool live = true) {
     uint32_t ln = (uint32_t)lane;
     asm volatile("" : "+v"(ln));
     const int32_t gy = (int32_t)gy0 + (int32_t)ln;
-    const bool rowok = gy >= 0 && gy < (int32_t)H;
+    const bool rowok = live && gy >= 0 && gy < (int32_t)H;
     uint32_t off = (uint32_t)gy * pitch + (uint32_t)(int32_t)a;
-    v4u v[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
         // a + 16 k < 0 only for chunk 0 of a tile at the left image edge;
@@ -166,6 +197,12 @@ __device__ __forceinline__ void stage_u8(__amdgpu_buffer_rsrc_t rs, int64_t gy0,
         v[k] = __builtin_amdgcn_raw_buffer_load_b128(rs, in ? off : 0xFFFFFFF0u, 0, CPOL);
         off += 16;
     }
+}
+
+// Row `lane` of the stage at st gets the 80 bytes fetched by stage_issue.
+__device__ __forceinline__ void stage_commit(const v4u (&v)[5], int lane, uint8_t *st) {
+    uint32_t ln = (uint32_t)lane;
+    asm volatile("" : "+v"(ln));
     uint32_t *w = (uint32_t *)(st + ln * SROW);
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
@@ -173,6 +210,63 @@ __device__ __forceinline__ void stage_u8(__amdgpu_buffer_rsrc_t rs, int64_t gy0,
         w[4 * k + 1] = v[k].y;
         w[4 * k + 2] = v[k].z;
         w[4 * k + 3] = v[k].w;
+    }
+}
+
+template <int CPOL = 0>
+__device__ __forceinline__ void stage_u8(__amdgpu_buffer_rsrc_t rs, int64_t gy0, int64_t H,
+                                         uint32_t pitch, int64_t a, int lane, uint8_t *st) {
+    v4u v[5];
+    stage_issue<CPOL>(rs, gy0, H, pitch, a, lane, v);
+    stage_commit(v, lane, st);
+}
+
+// A tile's stage rows in flight, held by value (mask words, working-image
+// words) so that they stay in registers between the visit that fetches them
+// and the one that commits them.
+struct StageWords {
+    v4u i0, i1, i2, i3, i4, j0, j1, j2, j3, j4;
+};
+
+// Issue the stage loads of tile t of image d (uint8, staged planes); with
+// live false every load is out of the buffer's range (zeros, no memory
+// access), so that the count of loads does not depend on the path.
+template <bool NEEDJ>
+__device__ __forceinline__ StageWords stage_fetch(const ImgDesc &d, int64_t t, int lane,
+                                                  bool live = true) {
+    const int64_t lt = t - d.tile_base;
+    const int ty = (int)(lt / d.ntx), tx = (int)(lt - (int64_t)ty * d.ntx);
+    const int64_t gy0 = (int64_t)ty * TI - 1, gx0 = (int64_t)tx * TI - 1;
+    const int64_t a = gx0 & ~(int64_t)15;
+    StageWords w;
+    v4u v[5];
+    stage_issue(plane_rsrc(d.I, (uint64_t)(d.H * d.pI)), gy0, d.H, (uint32_t)d.pI, a, lane, v, live);
+    w.i0 = v[0];
+    w.i1 = v[1];
+    w.i2 = v[2];
+    w.i3 = v[3];
+    w.i4 = v[4];
+    if (NEEDJ) {
+        stage_issue(plane_rsrc(d.J, (uint64_t)(d.H * d.pJ)), gy0, d.H, (uint32_t)d.pJ, a, lane, v,
+                    live);
+        w.j0 = v[0];
+        w.j1 = v[1];
+        w.j2 = v[2];
+        w.j3 = v[3];
+        w.j4 = v[4];
+    } else {
+        w.j0 = w.j1 = w.j2 = w.j3 = w.j4 = v4u{0u, 0u, 0u, 0u};
+    }
+    return w;
+}
+
+template <bool NEEDJ>
+__device__ __forceinline__ void stage_commit_words(const StageWords &w, int lane, uint8_t *st) {
+    const v4u vi[5] = {w.i0, w.i1, w.i2, w.i3, w.i4};
+    stage_commit(vi, lane, st);
+    if (NEEDJ) {
+        const v4u vj[5] = {w.j0, w.j1, w.j2, w.j3, w.j4};
+        stage_commit(vj, lane, st + STAGE_BYTES);
     }
 }
 
@@ -205,6 +299,76 @@ __device__ __forceinline__ void store_j(gptr<T> p, uint32_t off, T v) {
 // transposed mask IT (lane = row, register = column) and the loaded halo
 // columns JL, JR (lane = row) are read straight from the stage, and `it_done`
 // says so.
+// From a stage that holds the tile's mask rows (stage) and working-image rows
+// (stage + STAGE_BYTES), written and synchronized: the register tile J, I
+// (lane = column), and for tiles inside the image the transposed mask IT and
+// the halo columns JL, JR (lane = row), with it_done set. Ends with a barrier:
+// the stage's memory is the transpose buffer afterwards.
+template <typename T, bool FILL, bool INITIAL>
+__device__ __forceinline__ void stage_read(const ImgDesc &d, int64_t gy0, int64_t gx0, int lane,
+                                           uint32_t (&J)[TS], uint32_t (&I)[TS],
+                                           uint32_t (&IT)[TS], uint32_t &JL, uint32_t &JR,
+                                           const uint8_t *stage, bool &it_done) {
+    using P = Pix<T>;
+    const int64_t H = d.H, W = d.W;
+    const int64_t gx = gx0 + lane;
+    const bool xin = gx >= 0 && gx < W;
+    const bool xedge = gx == 0 || gx == W - 1;
+    const bool inside =
+        !(FILL && INITIAL) && gy0 >= 0 && gy0 + TS <= H && gx0 >= 0 && gx0 + TS <= W;
+    const int64_t a = gx0 & ~(int64_t)15;
+    const int sh = (int)(gx0 - a) + lane;
+    const uint8_t *stI = stage, *stJ = stage + STAGE_BYTES;
+    if (inside) {
+#pragma unroll
+        for (int r = 0; r < TS; ++r) {
+            uint32_t iv = stI[r * SROW + sh];
+            if (FILL) iv = P::KMAX - iv;
+            uint32_t jv = stJ[r * SROW + sh];
+            if (INITIAL) jv = min(jv, iv);
+            J[r] = jv;
+            I[r] = iv;
+        }
+        // lane = row: this lane's row of the mask, and the working image's
+        // two halo pixels of that row
+        const uint8_t *row = stI + lane * SROW + (int)(gx0 - a);
+#pragma unroll
+        for (int c = 0; c < TS; ++c) {
+            uint32_t v = row[c];
+            if (FILL) v = P::KMAX - v;
+            IT[c] = v;
+        }
+        const uint8_t *rowJ = stJ + lane * SROW + (int)(gx0 - a);
+        JL = rowJ[0];
+        JR = rowJ[TS - 1];
+        if (INITIAL) {
+            JL = min(JL, IT[0]);
+            JR = min(JR, IT[TS - 1]);
+        }
+        it_done = true;
+    } else {
+#pragma unroll
+        for (int r = 0; r < TS; ++r) {
+            const int64_t gy = gy0 + r;
+            const bool ok = xin && gy >= 0 && gy < H;
+            uint32_t iv = stI[r * SROW + sh];
+            if (FILL) iv = P::KMAX - iv;
+            uint32_t jv;
+            if (FILL && INITIAL)
+                jv = (xedge || gy == 0 || gy == H - 1) ? iv : 0u;
+            else if (INITIAL)
+                jv = min((uint32_t)stJ[r * SROW + sh], iv);
+            else
+                jv = stJ[r * SROW + sh];
+            jv = ok ? jv : 0u;
+            iv = ok ? iv : 0u;
+            J[r] = jv;
+            I[r] = iv;
+        }
+    }
+    __syncthreads();
+}
+
 template <typename T, bool FILL, bool INITIAL, bool COH = false>
 __device__ __forceinline__ void load_tile(const ImgDesc &d, int64_t gy0, int64_t gx0, int lane,
                                           uint32_t (&J)[TS], uint32_t (&I)[TS],
@@ -222,7 +386,6 @@ __device__ __forceinline__ void load_tile(const ImgDesc &d, int64_t gy0, int64_t
         !(FILL && INITIAL) && gy0 >= 0 && gy0 + TS <= H && gx0 >= 0 && gx0 + TS <= W;
     if (sizeof(T) == 1 && stage_ok(d.I, d.pI) && stage_ok(d.J, d.pJ)) {
         const int64_t a = gx0 & ~(int64_t)15;
-        const int sh = (int)(gx0 - a) + lane;
         uint8_t *stI = stage, *stJ = stage + STAGE_BYTES;
         stage_u8(plane_rsrc(d.I, (uint64_t)(H * d.pI)), gy0, H, (uint32_t)d.pI, a, lane, stI);
         const bool needJ = !(FILL && INITIAL);
@@ -230,54 +393,7 @@ __device__ __forceinline__ void load_tile(const ImgDesc &d, int64_t gy0, int64_t
             stage_u8<COH ? CPOL_DEVICE : 0>(plane_rsrc(d.J, (uint64_t)(H * d.pJ)), gy0, H,
                                             (uint32_t)d.pJ, a, lane, stJ);
         __syncthreads();
-        if (inside) {
-#pragma unroll
-            for (int r = 0; r < TS; ++r) {
-                uint32_t iv = stI[r * SROW + sh];
-                if (FILL) iv = P::KMAX - iv;
-                uint32_t jv = stJ[r * SROW + sh];
-                if (INITIAL) jv = min(jv, iv);
-                J[r] = jv;
-                I[r] = iv;
-            }
-            // lane = row: this lane's row of the mask, and the working
-            // image's two halo pixels of that row
-            const uint8_t *row = stI + lane * SROW + (int)(gx0 - a);
-#pragma unroll
-            for (int c = 0; c < TS; ++c) {
-                uint32_t v = row[c];
-                if (FILL) v = P::KMAX - v;
-                IT[c] = v;
-            }
-            const uint8_t *rowJ = stJ + lane * SROW + (int)(gx0 - a);
-            JL = rowJ[0];
-            JR = rowJ[TS - 1];
-            if (INITIAL) {
-                JL = min(JL, IT[0]);
-                JR = min(JR, IT[TS - 1]);
-            }
-            it_done = true;
-        } else {
-#pragma unroll
-            for (int r = 0; r < TS; ++r) {
-                const int64_t gy = gy0 + r;
-                const bool ok = xin && gy >= 0 && gy < H;
-                uint32_t iv = stI[r * SROW + sh];
-                if (FILL) iv = P::KMAX - iv;
-                uint32_t jv;
-                if (FILL && INITIAL)
-                    jv = (xedge || gy == 0 || gy == H - 1) ? iv : 0u;
-                else if (INITIAL)
-                    jv = min((uint32_t)stJ[r * SROW + sh], iv);
-                else
-                    jv = stJ[r * SROW + sh];
-                jv = ok ? jv : 0u;
-                iv = ok ? iv : 0u;
-                J[r] = jv;
-                I[r] = iv;
-            }
-        }
-        __syncthreads();
+        stage_read<T, FILL, INITIAL>(d, gy0, gx0, lane, J, I, IT, JL, JR, stage, it_done);
         return;
     }
     cgptr<T> Jp = (cgptr<T>)d.J;
@@ -472,16 +588,19 @@ __device__ __forceinline__ void app_flush(Appender &a, int lane) {
     const bool valid = (uint32_t)lane < a.cnt;
     const uint32_t e = valid ? a.buf[lane] : 0u;
     const int be = valid ? band_of(a.n_tiles, e) : -1;
+    // lane b < NBANDS reserves band b's share with one atomic; all of them
+    // go out together, so the batch costs one round trip
+    uint64_t mine = 0, under = 0;
 #pragma unroll
     for (int b = 0; b < NBANDS; ++b) {
         const uint64_t m = __ballot(be == b);
-        if (!m) continue;
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(a.counter + b, (uint32_t)__popcll(m));
-        base = __shfl(base, 0);
-        if (be == b)
-            a.list_out[band_lo(a.n_tiles, b) + base + __popcll(m & ((1ull << lane) - 1))] = e;
+        if (lane == b) mine = m;
+        if (be == b) under = m & ((1ull << lane) - 1);
     }
+    uint32_t base = 0;
+    if (lane < NBANDS && mine) base = atomicAdd(a.counter + lane, (uint32_t)__popcll(mine));
+    const uint32_t my_base = __shfl(base, be < 0 ? 0 : be);
+    if (valid) a.list_out[band_lo(a.n_tiles, be) + my_base + __popcll(under)] = e;
     __syncthreads();
     a.cnt = 0;
 }
@@ -598,11 +717,92 @@ __device__ __forceinline__ void tail_mark(const TailQ &q, uint32_t t) {
 // One visit of one tile: load, sweep to a local fixed point (or the cap),
 // store, and mark the neighbours whose halo changed: onto the next round's
 // lists, or (TAIL) into the tile queue `tq`.
-template <typename T, int CONN, bool FILL, bool INITIAL, bool TAIL = false>
-__device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane,
-                                           uint32_t *__restrict__ flags, Appender &app,
-                                           Ctrl *__restrict__ ctrl, uint32_t round, int max_iters,
-                                           uint32_t (*tb)[TS + 1], const TailQ *tq = nullptr) {
+// Which tile this lane (0..8) asks to visit again: itself if the sweep cap
+// stopped it, or the neighbour next to a changed border pixel that can still
+// raise one of the neighbour's pixels in this tile's halo (min(mask, max of
+// the adjacent border pixels) above the value the halo pixel had when this
+// visit loaded it; pixels only rise, so a halo pixel that passes against its
+// loaded value passes against its current one too). Rows 0 and TS-1 are
+// checked in lanes 0..TS-1 (lane = column), columns 0 and TS-1 in lanes
+// 0..TS-1 (lane = row), whose border columns 1 and TS-2 the last transpose
+// left in LDS. Returns whether this lane wants tile `nb`.
+template <int CONN>
+__device__ __forceinline__ bool mark_decide(const ImgDesc &d, int lane, int ty, int tx,
+                                            const uint32_t (&J)[TS], const uint32_t (&I)[TS],
+                                            const uint32_t (&IT)[TS], uint32_t JT, uint32_t JB,
+                                            uint32_t JL, uint32_t JR, uint32_t top_in,
+                                            uint32_t bot_in, uint64_t col_in, uint64_t col_out,
+                                            bool stable, uint32_t (*tb)[TS + 1], uint32_t &nb) {
+    const bool in_lane = lane >= 1 && lane <= TS - 2;
+    const uint64_t bt = __ballot(in_lane && J[1] != top_in);
+    const uint64_t bb = __ballot(in_lane && J[TS - 2] != bot_in);
+    const uint64_t bc = __ballot(col_out != col_in);
+    const uint32_t b1 = in_lane ? J[1] : 0u, b2 = in_lane ? J[TS - 2] : 0u;
+    const uint32_t c1 = in_lane ? tb[1][lane] : 0u, c2 = in_lane ? tb[TS - 2][lane] : 0u;
+    const uint32_t nbT = CONN == 8 ? max3_lanes(b1) : b1, nbB = CONN == 8 ? max3_lanes(b2) : b2;
+    const uint32_t nbL = CONN == 8 ? max3_lanes(c1) : c1, nbR = CONN == 8 ? max3_lanes(c2) : c2;
+    const uint64_t rt = __ballot(med3(JT, nbT, I[0]) > JT);
+    const uint64_t rb = __ballot(med3(JB, nbB, I[TS - 1]) > JB);
+    // (after a relaxation step that still changed pixels at the sweep cap,
+    // LDS holds the columns from before it: then every halo column counts)
+    const uint64_t rl = stable ? __ballot(med3(JL, nbL, IT[0]) > JL) : ~0ull;
+    const uint64_t rr = stable ? __ballot(med3(JR, nbR, IT[TS - 1]) > JR) : ~0ull;
+    constexpr uint64_t EDGE = ~(1ull | (1ull << (TS - 1))); // lanes 1..TS-2
+    bool want = false;
+    int dy = 0, dx = 0;
+    switch (lane) {
+    case 0: want = !stable; break;
+    case 1: want = bt != 0 && (rt & EDGE) != 0; dy = -1; break;
+    case 2: want = bb != 0 && (rb & EDGE) != 0; dy = 1; break;
+    case 3: want = ((bc >> 1) & 1) && (rl & EDGE) != 0; dx = -1; break;
+    case 4: want = ((bc >> (TS - 2)) & 1) && (rr & EDGE) != 0; dx = 1; break;
+    case 5: want = CONN == 8 && ((bt >> 1) & 1) && (rt & 1); dy = -1; dx = -1; break;
+    case 6: want = CONN == 8 && ((bt >> (TS - 2)) & 1) && (rt >> (TS - 1)); dy = -1; dx = 1; break;
+    case 7: want = CONN == 8 && ((bb >> 1) & 1) && (rb & 1); dy = 1; dx = -1; break;
+    case 8: want = CONN == 8 && ((bb >> (TS - 2)) & 1) && (rb >> (TS - 1)); dy = 1; dx = 1; break;
+    default: break;
+    }
+    const int ny = ty + dy, nx = tx + dx;
+    want = want && ny >= 0 && ny < d.nty && nx >= 0 && nx < d.ntx;
+    nb = want ? (uint32_t)(d.tile_base + (int64_t)ny * d.ntx + nx) : 0u;
+    return want;
+}
+
+// The round path's marks: the wanted tiles get the next round in their
+// epoch flag; the atomic maximum lets exactly one marker list a tile: the
+// one that finds the flag below the next round. Returns the flag's previous
+// value (the next round itself where this lane marks nothing), so that
+// callers can compare it late and let the wait for the atomic overlap other
+// work; the tile's id is in nb.
+template <int CONN>
+__device__ __forceinline__ uint32_t mark_neighbours(const ImgDesc &d, int lane, int ty, int tx,
+                                                const uint32_t (&J)[TS], const uint32_t (&I)[TS],
+                                                const uint32_t (&IT)[TS], uint32_t JT, uint32_t JB,
+                                                uint32_t JL, uint32_t JR, uint32_t top_in,
+                                                uint32_t bot_in, uint64_t col_in,
+                                                uint64_t col_out, bool stable,
+                                                uint32_t (*tb)[TS + 1], uint32_t *flags,
+                                                uint32_t round, uint32_t &nb) {
+    const bool want = mark_decide<CONN>(d, lane, ty, tx, J, I, IT, JT, JB, JL, JR, top_in,
+                                        bot_in, col_in, col_out, stable, tb, nb);
+    const uint32_t nxt = round + 1;
+    return want ? atomicMax(flags + nb, nxt) : nxt;
+}
+
+// PIPE (the pipelined round kernel; implies a stage the caller has written
+// and synchronized): on the round path, after the marking atomics are issued
+// and before the stores, the visit issues the stage loads of the next tile
+// (*dn, tn) when has_next, and returns them; otherwise it returns zeros.
+template <typename T, int CONN, bool FILL, bool INITIAL, bool TAIL = false, bool PIPE = false>
+__device__ __forceinline__ StageWords visit_tile(const ImgDesc &d, int64_t t, int lane,
+                                                 uint32_t *__restrict__ flags, Appender &app,
+                                                 Ctrl *__restrict__ ctrl, uint32_t round,
+                                                 int max_iters, uint32_t (*tb)[TS + 1],
+                                                 const TailQ *tq = nullptr,
+                                                 const ImgDesc *dn = nullptr, int64_t tn = 0,
+                                                 bool has_next = false) {
+    constexpr bool STAGED = PIPE;
+    StageWords pre{};
     using P = Pix<T>;
     constexpr bool first = INITIAL;
     const int64_t lt = t - d.tile_base;
@@ -612,8 +812,12 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
     uint32_t J[TS], I[TS], IT[TS];
     uint32_t JL, JR; // loaded halo columns 0 and TS-1, lane = row
     bool it_done = false;
-    load_tile<T, FILL, INITIAL, TAIL>(d, gy0, (int64_t)tx * TI - 1, lane, J, I, IT, JL, JR,
-                                (uint8_t *)tb, it_done);
+    if (STAGED) // the caller has written and synchronized the stage
+        stage_read<T, FILL, INITIAL>(d, gy0, (int64_t)tx * TI - 1, lane, J, I, IT, JL, JR,
+                                     (const uint8_t *)tb, it_done);
+    else
+        load_tile<T, FILL, INITIAL, TAIL>(d, gy0, (int64_t)tx * TI - 1, lane, J, I, IT, JL, JR,
+                                          (uint8_t *)tb, it_done);
     if (!it_done) {
         // (before the mask transpose: fewer registers live)
         halo_cols(J, tb, lane, JL, JR);
@@ -696,67 +900,41 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
             }
         }
     }
-    if (!changed && stable) return;
-
-    const uint64_t col_out = col_prev;
-    const uint64_t bt = __ballot(in_lane && J[1] != top_in);
-    const uint64_t bb = __ballot(in_lane && J[TS - 2] != bot_in);
-    const uint64_t bc = __ballot(col_out != col_in);
-    // Can the final border still raise a halo pixel, i.e. is min(mask, max of
-    // its neighbours in this tile's interior) above the value the pixel held
-    // when this visit loaded it? Pixels only rise, so a halo pixel that passes
-    // against its loaded value passes against its current one too, and its
-    // tile need not be visited on this tile's account. Rows 0 and TS-1 in
-    // lanes 0..TS-1 (lane = column), then columns 0 and TS-1 in lanes 0..TS-1
-    // (lane = row), whose border columns 1 and TS-2 the last transpose left in
-    // LDS.
-    const uint32_t b1 = in_lane ? J[1] : 0u, b2 = in_lane ? J[TS - 2] : 0u;
-    const uint32_t c1 = in_lane ? tb[1][lane] : 0u, c2 = in_lane ? tb[TS - 2][lane] : 0u;
-    const uint32_t nbT = CONN == 8 ? max3_lanes(b1) : b1, nbB = CONN == 8 ? max3_lanes(b2) : b2;
-    const uint32_t nbL = CONN == 8 ? max3_lanes(c1) : c1, nbR = CONN == 8 ? max3_lanes(c2) : c2;
-    const uint64_t rt = __ballot(med3(JT, nbT, I[0]) > JT);
-    const uint64_t rb = __ballot(med3(JB, nbB, I[TS - 1]) > JB);
-    // (after a relaxation step that still changed pixels at the sweep cap,
-    // LDS holds the columns from before it: then every halo column counts)
-    const uint64_t rl = stable ? __ballot(med3(JL, nbL, IT[0]) > JL) : ~0ull;
-    const uint64_t rr = stable ? __ballot(med3(JR, nbR, IT[TS - 1]) > JR) : ~0ull;
-    constexpr uint64_t EDGE = ~(1ull | (1ull << (TS - 1))); // lanes 1..TS-2
-    // Lanes 0..8 each consider one tile to mark dirty for the next round:
-    // itself (if the sweep cap stopped it early) and the neighbours next to a
-    // changed border pixel that can raise one of their pixels. The atomic max
-    // on the flag lets exactly one marker put a tile on the next list.
-    const uint32_t nxt = round + 1;
-    bool want = false;
-    int dy = 0, dx = 0;
-    switch (lane) {
-    case 0: want = !stable; break;
-    case 1: want = bt != 0 && (rt & EDGE) != 0; dy = -1; break;
-    case 2: want = bb != 0 && (rb & EDGE) != 0; dy = 1; break;
-    case 3: want = ((bc >> 1) & 1) && (rl & EDGE) != 0; dx = -1; break;
-    case 4: want = ((bc >> (TS - 2)) & 1) && (rr & EDGE) != 0; dx = 1; break;
-    case 5: want = CONN == 8 && ((bt >> 1) & 1) && (rt & 1); dy = -1; dx = -1; break;
-    case 6: want = CONN == 8 && ((bt >> (TS - 2)) & 1) && (rt >> (TS - 1)); dy = -1; dx = 1; break;
-    case 7: want = CONN == 8 && ((bb >> 1) & 1) && (rb & 1); dy = 1; dx = -1; break;
-    case 8: want = CONN == 8 && ((bb >> (TS - 2)) & 1) && (rb >> (TS - 1)); dy = 1; dx = 1; break;
-    default: break;
+    // PIPE: the next tile's stage loads go out after this tile's stores and
+    // mark atomics (on every path, with no loads when there is no next tile),
+    // so that waiting for the marks does not wait for them, and they are in
+    // flight while the marks are waited for and the list is appended to.
+    // Nothing of the next tile may be loaded earlier (its registers would be
+    // live across the sweeps).
+    auto fetch_next = [&]() {
+        if (PIPE) {
+            asm volatile("" ::: "memory");
+            pre = stage_fetch<!(FILL && INITIAL)>(*dn, tn, lane, has_next);
+        }
+    };
+    if (!changed && stable) {
+        fetch_next();
+        return pre;
     }
-    const int ny = ty + dy, nx = tx + dx;
-    want = want && ny >= 0 && ny < d.nty && nx >= 0 && nx < d.ntx;
-    if (TAIL) {
-        // the visits these marks lead to must see this visit's stores
-        wait_vmem();
-        if (want) tail_mark(*tq, (uint32_t)(d.tile_base + (int64_t)ny * d.ntx + nx));
-        return;
+    if (!TAIL) {
+        uint32_t nb = 0;
+        const uint32_t old =
+            mark_neighbours<CONN>(d, lane, ty, tx, J, I, IT, JT, JB, JL, JR, top_in, bot_in,
+                                  col_in, col_prev, stable, tb, flags, round, nb);
+        fetch_next();
+        const bool fresh = old < round + 1;
+        const uint64_t fm = __ballot(fresh);
+        if (fresh) app.buf[app.cnt + __popcll(fm & ((1ull << lane) - 1))] = nb;
+        app.cnt += (uint32_t)__popcll(fm);
+        return pre;
     }
-    uint32_t nb = 0;
-    bool fresh = false;
-    if (want) {
-        nb = (uint32_t)(d.tile_base + (int64_t)ny * d.ntx + nx);
-        fresh = atomicMax(flags + nb, nxt) < nxt;
-    }
-    const uint64_t fm = __ballot(fresh);
-    if (fresh) app.buf[app.cnt + __popcll(fm & ((1ull << lane) - 1))] = nb;
-    app.cnt += (uint32_t)__popcll(fm);
+    uint32_t tnb = 0;
+    const bool want = mark_decide<CONN>(d, lane, ty, tx, J, I, IT, JT, JB, JL, JR, top_in, bot_in,
+                                        col_in, col_prev, stable, tb, tnb);
+    // the visits these marks lead to must see this visit's stores
+    wait_vmem();
+    if (want) tail_mark(*tq, tnb);
+    return pre;
 }
 
 // One tile round on a persistent grid (two waves per SIMD). Block b serves
@@ -766,6 +944,82 @@ __device__ __forceinline__ void visit_tile(const ImgDesc &d, int64_t t, int lane
 // lists at most one tile per block, but more in some band than that band has
 // blocks, deals across bands instead. A tile
 // builds its image's initial working values in the image's first round.
+// V selects the visit: -1 dispatches per tile on the image's op and first
+// round (mixed batches, the server); otherwise (FILL << 1) | INITIAL for
+// launches whose tiles all take the same visit, which keeps the other three
+// variants' code, and their registers, out of the kernel.
+// The tiles a block of a round visits: band `band`'s list (or, with
+// all_tiles, the whole band), entries local, local + per, ... below n, from
+// list_in (band start already applied). A round that lists no more tiles
+// than the grid has blocks, but more in some band than that band has blocks,
+// gives each tile a block of its own: the tail of a flood often sits in one
+// or two bands, whose blocks would otherwise visit its tiles one after
+// another while the rest of the grid idles. Block g takes entry g of the
+// band lists laid end to end. When every band fits its blocks, the bands'
+// dealing already gives each tile a block, and keeps neighbouring tiles on
+// one die's L2.
+struct RoundWork {
+    int band;
+    int64_t local, per, n, lo;
+    const uint32_t *list_in;
+    bool fwd;
+};
+
+__device__ __forceinline__ RoundWork round_work(int64_t n_tiles, const uint32_t *lists,
+                                                const uint32_t *counts_in, int all_tiles,
+                                                uint32_t round) {
+    RoundWork w;
+    w.band = blockIdx.x % NBANDS;
+    w.local = blockIdx.x / NBANDS;
+    w.per = gridDim.x / NBANDS;
+    if (all_tiles) {
+        w.n = band_lo(n_tiles, w.band + 1) - band_lo(n_tiles, w.band);
+    } else {
+        uint32_t c[NBANDS], total = 0, cmax = 0;
+#pragma unroll
+        for (int q = 0; q < NBANDS; ++q) {
+            c[q] = kconst(counts_in)[q];
+            total += c[q];
+            cmax = c[q] > cmax ? c[q] : cmax;
+        }
+        if (total <= gridDim.x && cmax > (uint32_t)w.per) {
+            uint32_t i = blockIdx.x, cb = c[0];
+            int b = 0;
+#pragma unroll
+            for (int q = 0; q < NBANDS - 1; ++q)
+                if (b == q && i >= c[q]) {
+                    i -= c[q];
+                    b = q + 1;
+                    cb = c[q + 1];
+                }
+            w.band = b;
+            w.local = i;
+            w.per = cb > 0 ? cb : 1; // one iteration: entry i (or n - 1 - i backward)
+            w.n = blockIdx.x < total ? cb : 0;
+        } else {
+            w.n = kconst(counts_in)[w.band];
+        }
+    }
+    w.lo = band_lo(n_tiles, w.band);
+    w.list_in = lists + (round & 1) * n_tiles + w.lo;
+    // Odd rounds walk the band forward, even rounds backward: a tile stored
+    // early in a round is read by tiles visited later in it, so information
+    // travels down the image within odd rounds and up it within even ones,
+    // as in a raster / anti-raster pair of scans.
+    w.fwd = (round & 1) != 0;
+    return w;
+}
+
+__device__ __forceinline__ int64_t round_tile(const RoundWork &w, int all_tiles, int64_t i) {
+    const int64_t k = w.fwd ? i : w.n - 1 - i;
+    return all_tiles ? w.lo + k : (int64_t)kconst(w.list_in)[k];
+}
+
+// One tile round on a persistent grid (two waves per SIMD). Block b serves
+// band b % NBANDS and visits either every tile of the band (all_tiles) or the
+// band's dirty list (see round_work). Tiles are dealt to the band's blocks by
+// static interleave, so no block gets more than one tile above another. A
+// tile builds its image's initial working values in the image's first round.
 // V selects the visit: -1 dispatches per tile on the image's op and first
 // round (mixed batches, the server); otherwise (FILL << 1) | INITIAL for
 // launches whose tiles all take the same visit, which keeps the other three
@@ -781,55 +1035,10 @@ __global__ __launch_bounds__(64, 2) void k_tile_round(Imgs imgs, int64_t n_tiles
     __shared__ uint32_t tb[TS][TS + 1]; // transpose buffer (and load stage)
     __shared__ uint32_t abuf[APP_CAP];
     const int lane = threadIdx.x;
-    int band = blockIdx.x % NBANDS;
-    int64_t local = blockIdx.x / NBANDS, per = gridDim.x / NBANDS, n;
-    if (all_tiles) {
-        n = band_lo(n_tiles, band + 1) - band_lo(n_tiles, band);
-    } else {
-        // A round that lists no more tiles than the grid has blocks, but more
-        // in some band than that band has blocks, gives each tile a block of
-        // its own: the tail of a flood often sits in one or two bands, whose
-        // blocks would otherwise visit its tiles one after another while the
-        // rest of the grid idles. Block g takes entry g of the band lists laid
-        // end to end. When every band fits its blocks, the bands' dealing
-        // already gives each tile a block, and keeps neighbouring tiles on one
-        // die's L2.
-        uint32_t c[NBANDS], total = 0, cmax = 0;
-#pragma unroll
-        for (int q = 0; q < NBANDS; ++q) {
-            c[q] = counts_in[q];
-            total += c[q];
-            cmax = c[q] > cmax ? c[q] : cmax;
-        }
-        if (total <= gridDim.x && cmax > (uint32_t)per) {
-            uint32_t i = blockIdx.x, cb = c[0];
-            int b = 0;
-#pragma unroll
-            for (int q = 0; q < NBANDS - 1; ++q)
-                if (b == q && i >= c[q]) {
-                    i -= c[q];
-                    b = q + 1;
-                    cb = c[q + 1];
-                }
-            band = b;
-            local = i;
-            per = cb > 0 ? cb : 1; // one iteration: entry i (or n - 1 - i backward)
-            n = blockIdx.x < total ? cb : 0;
-        } else {
-            n = counts_in[band];
-        }
-    }
-    const int64_t lo = band_lo(n_tiles, band);
+    const RoundWork w = round_work(n_tiles, lists, counts_in, all_tiles, round);
     Appender app{abuf, 0, lists + ((round + 1) & 1) * n_tiles, counts_out, n_tiles};
-    const uint32_t *list_in = lists + (round & 1) * n_tiles + lo;
-    // Odd rounds walk the band forward, even rounds backward: a tile stored
-    // early in a round is read by tiles visited later in it, so information
-    // travels down the image within odd rounds and up it within even ones,
-    // as in a raster / anti-raster pair of scans.
-    const bool fwd = (round & 1) != 0;
-    for (int64_t i = local; i < n; i += per) {
-        const int64_t k = fwd ? i : n - 1 - i;
-        const int64_t t = all_tiles ? lo + k : (int64_t)list_in[k];
+    for (int64_t i = w.local; i < w.n; i += w.per) {
+        const int64_t t = round_tile(w, all_tiles, i);
         const ImgDesc d = load_desc(imgs, t);
         if (V >= 0) {
             if (!d.done)
@@ -849,6 +1058,57 @@ __global__ __launch_bounds__(64, 2) void k_tile_round(Imgs imgs, int64_t n_tiles
             }
         }
         if (app.cnt > APP_CAP - 9) app_flush(app, lane);
+    }
+    app_flush(app, lane);
+}
+
+// The same round for launches whose images are all uint8 with 16-byte
+// aligned planes and pitches and take one visit kind V, software-pipelined
+// over the block's tiles: the stage loads of the next tile are issued during
+// the current visit, after its marking atomics and before its stores, so
+// that their memory latency (and that of the next list entry and
+// descriptor) overlaps the current tile's stores and the wait for its marks
+// instead of starting the next visit. The loads land in registers that the
+// sweeps no longer need; the next visit writes them to the stage.
+template <int CONN, int V>
+__global__ __launch_bounds__(64, 2) void k_tile_round_pf(Imgs imgs, int64_t n_tiles,
+                                                         uint32_t *__restrict__ flags,
+                                                         uint32_t *__restrict__ lists,
+                                                         const uint32_t *__restrict__ counts_in,
+                                                         uint32_t *__restrict__ counts_out,
+                                                         int all_tiles, Ctrl *__restrict__ ctrl,
+                                                         uint32_t round, int max_iters) {
+    constexpr bool FILL = (V >> 1) & 1, INITIAL = V & 1;
+    constexpr bool needJ = !(FILL && INITIAL);
+    __shared__ uint32_t tb[TS][TS + 1]; // transpose buffer and load stage
+    __shared__ uint32_t abuf[APP_CAP];
+    const int lane = threadIdx.x;
+    const RoundWork w = round_work(n_tiles, lists, counts_in, all_tiles, round);
+    Appender app{abuf, 0, lists + ((round + 1) & 1) * n_tiles, counts_out, n_tiles};
+    uint8_t *stage = (uint8_t *)tb;
+    if (w.local < w.n) {
+        int64_t i = w.local;
+        int64_t t = round_tile(w, all_tiles, i);
+        ImgDesc d = load_desc(imgs, t);
+        StageWords pre = stage_fetch<needJ>(d, t, lane);
+        while (true) {
+            // the fetched rows of tile t go to the stage; the previous visit's
+            // last reads of the transpose buffer are behind this barrier
+            __syncthreads();
+            stage_commit_words<needJ>(pre, lane, stage);
+            __syncthreads();
+            const int64_t in = i + w.per;
+            const bool has = in < w.n;
+            const int64_t tn = has ? round_tile(w, all_tiles, in) : t;
+            const ImgDesc dn = has ? load_desc(imgs, tn) : d;
+            pre = visit_tile<uint8_t, CONN, FILL, INITIAL, false, true>(
+                d, t, lane, flags, app, ctrl, round, max_iters, tb, nullptr, &dn, tn, has);
+            if (app.cnt > APP_CAP - 9) app_flush(app, lane);
+            if (!has) break;
+            i = in;
+            t = tn;
+            d = dn;
+        }
     }
     app_flush(app, lane);
 }
@@ -1337,8 +1597,12 @@ static hipError_t tile_round_v(const Imgs &imgs, int64_t n_tiles, uint32_t *flag
                                hipStream_t s) {
     const int64_t want = std::max<int64_t>(NBANDS, (n_tiles + NBANDS - 1) / NBANDS * NBANDS);
     const unsigned g = (unsigned)(std::min<int64_t>(grid, want) / NBANDS * NBANDS);
-    hipLaunchKernelGGL((k_tile_round<T, CONN, V>), dim3(g), dim3(64), 0, s, imgs, n_tiles, flags,
-                       lists, cin, cout, all, ctrl, round, max_iters);
+    if (sizeof(T) == 1 && V >= 0 && imgs.staged)
+        hipLaunchKernelGGL((k_tile_round_pf<CONN, (V < 0 ? 0 : V)>), dim3(g), dim3(64), 0, s, imgs,
+                           n_tiles, flags, lists, cin, cout, all, ctrl, round, max_iters);
+    else
+        hipLaunchKernelGGL((k_tile_round<T, CONN, V>), dim3(g), dim3(64), 0, s, imgs, n_tiles,
+                           flags, lists, cin, cout, all, ctrl, round, max_iters);
     return hipGetLastError();
 }
 
