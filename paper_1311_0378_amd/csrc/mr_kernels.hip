@@ -145,6 +145,16 @@ template <> struct Atom<uint8_t> {
 
 // ------------------------------------------------------------------ tiles
 
+// The tile kernels run one wave per block. LDS that some lanes write and
+// others read needs only program order there (a wave's LDS operations are
+// performed in the order they issue) and a compiler barrier; a workgroup
+// barrier would also wait for every global load and store in flight.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 
 // Buffer resource over one uint8 plane of `bytes` bytes, used only when the
 // plane base and pitch are multiples of 16, so every 16-byte chunk load is
@@ -302,7 +312,7 @@ __device__ __forceinline__ void store_j(gptr<T> p, uint32_t off, T v) {
 // From a stage that holds the tile's mask rows (stage) and working-image rows
 // (stage + STAGE_BYTES), written and synchronized: the register tile J, I
 // (lane = column), and for tiles inside the image the transposed mask IT and
-// the halo columns JL, JR (lane = row), with it_done set. Ends with a barrier:
+// the halo columns JL, JR (lane = row), with it_done set. Ends with a wave sync:
 // the stage's memory is the transpose buffer afterwards.
 template <typename T, bool FILL, bool INITIAL>
 __device__ __forceinline__ void stage_read(const ImgDesc &d, int64_t gy0, int64_t gx0, int lane,
@@ -366,7 +376,7 @@ __device__ __forceinline__ void stage_read(const ImgDesc &d, int64_t gy0, int64_
             I[r] = iv;
         }
     }
-    __syncthreads();
+    wave_sync();
 }
 
 template <typename T, bool FILL, bool INITIAL, bool COH = false>
@@ -392,7 +402,7 @@ __device__ __forceinline__ void load_tile(const ImgDesc &d, int64_t gy0, int64_t
         if (needJ)
             stage_u8<COH ? CPOL_DEVICE : 0>(plane_rsrc(d.J, (uint64_t)(H * d.pJ)), gy0, H,
                                             (uint32_t)d.pJ, a, lane, stJ);
-        __syncthreads();
+        wave_sync();
         stage_read<T, FILL, INITIAL>(d, gy0, gx0, lane, J, I, IT, JL, JR, stage, it_done);
         return;
     }
@@ -443,10 +453,10 @@ __device__ __forceinline__ void load_tile(const ImgDesc &d, int64_t gy0, int64_t
 __device__ __forceinline__ void transpose(uint32_t (&A)[TS], uint32_t (*tb)[TS + 1], int lane) {
 #pragma unroll
     for (int r = 0; r < TS; ++r) tb[r][lane] = A[r];
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int c = 0; c < TS; ++c) A[c] = tb[lane][c];
-    __syncthreads();
+    wave_sync();
 }
 
 // med3(j, n, i) = min(max(j, n), i) whenever j <= i, which holds for every
@@ -494,10 +504,10 @@ __device__ __forceinline__ void halo_cols(const uint32_t (&A)[TS], uint32_t (*tb
 #pragma unroll
         for (int r = 0; r < TS; ++r) dst[r] = A[r];
     }
-    __syncthreads();
+    wave_sync();
     cl = buf[lane];
     cr = buf[TS + lane];
-    __syncthreads();
+    wave_sync();
 }
 
 // Sweeps along the registers. With DIAG, A[r] takes the max over the three
@@ -584,7 +594,7 @@ struct Appender {
 // one counter update.
 __device__ __forceinline__ void app_flush(Appender &a, int lane) {
     if (a.cnt == 0) return;
-    __syncthreads();
+    wave_sync();
     const bool valid = (uint32_t)lane < a.cnt;
     const uint32_t e = valid ? a.buf[lane] : 0u;
     const int be = valid ? band_of(a.n_tiles, e) : -1;
@@ -601,7 +611,7 @@ __device__ __forceinline__ void app_flush(Appender &a, int lane) {
     if (lane < NBANDS && mine) base = atomicAdd(a.counter + lane, (uint32_t)__popcll(mine));
     const uint32_t my_base = __shfl(base, be < 0 ? 0 : be);
     if (valid) a.list_out[band_lo(a.n_tiles, be) + my_base + __popcll(under)] = e;
-    __syncthreads();
+    wave_sync();
     a.cnt = 0;
 }
 
@@ -1093,10 +1103,10 @@ __global__ __launch_bounds__(64, 2) void k_tile_round_pf(Imgs imgs, int64_t n_ti
         StageWords pre = stage_fetch<needJ>(d, t, lane);
         while (true) {
             // the fetched rows of tile t go to the stage; the previous visit's
-            // last reads of the transpose buffer are behind this barrier
-            __syncthreads();
+            // last reads of the transpose buffer are behind this sync
+            wave_sync();
             stage_commit_words<needJ>(pre, lane, stage);
-            __syncthreads();
+            wave_sync();
             const int64_t in = i + w.per;
             const bool has = in < w.n;
             const int64_t tn = has ? round_tile(w, all_tiles, in) : t;
