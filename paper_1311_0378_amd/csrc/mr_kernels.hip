@@ -796,7 +796,9 @@ __device__ __forceinline__ uint32_t mark_neighbours(const ImgDesc &d, int lane, 
     const bool want = mark_decide<CONN>(d, lane, ty, tx, J, I, IT, JT, JB, JL, JR, top_in,
                                         bot_in, col_in, col_out, stable, tb, nb);
     const uint32_t nxt = round + 1;
-    return want ? atomicMax(flags + nb, nxt) : nxt;
+    uint32_t old = nxt;
+    if (want) old = atomicMax(flags + nb, nxt);
+    return old;
 }
 
 // PIPE (the pipelined round kernel; implies a stage the caller has written
@@ -932,7 +934,11 @@ __device__ __forceinline__ StageWords visit_tile(const ImgDesc &d, int64_t t, in
             mark_neighbours<CONN>(d, lane, ty, tx, J, I, IT, JT, JB, JL, JR, top_in, bot_in,
                                   col_in, col_prev, stable, tb, flags, round, nb);
         fetch_next();
-        const bool fresh = old < round + 1;
+        // (an opaque use: the comparison stays here, behind the loads that
+        // fetch_next issued, rather than right after the atomic)
+        uint32_t o = old;
+        asm volatile("" : "+v"(o));
+        const bool fresh = o < round + 1;
         const uint64_t fm = __ballot(fresh);
         if (fresh) app.buf[app.cnt + __popcll(fm & ((1ull << lane) - 1))] = nb;
         app.cnt += (uint32_t)__popcll(fm);
