@@ -60,75 +60,121 @@ template <> struct K<int32_t> {
     __device__ static int32_t val(uint32_t k) { return (int32_t)(k ^ 0x80000000u); }
 };
 
-constexpr int ROW_SEG = 512; // pixels of one row per wave and step (8 per lane)
+// The streaming passes of the wrappers, one kind each:
+//  P_MARKER: m = f - h, saturating at the type's minimum (in key space: key -
+//            h floored at 0); *above |= 1 if some pixel is above the minimum;
+//  P_DOME:   f <- f - r (the h-dome; r <= f everywhere, so 0 <= f - r <= h);
+//  P_RMAX:   out = 255 where f > r (a dome of height 1), or everywhere when
+//            no pixel is above the minimum (*above == 0); else 0.
+// With WORDS every lane takes one 16-byte word of a row (planes whose base
+// and pitch are multiples of 16 bytes; the u8 output of P_RMAX likewise, in
+// 16 / sizeof(T)-byte pieces), else one pixel. A row's last word may be
+// partial and goes pixel by pixel. Grid-stride over a grid of at most
+// MAX_STREAM_BLOCKS blocks.
+enum { P_MARKER = 0, P_DOME = 1, P_RMAX = 2 };
+constexpr int64_t MAX_STREAM_BLOCKS = 4096;
 
-// marker = f - h, saturating at the type's minimum (in key space: key - h
-// floored at 0); *above |= 1 if some pixel is above the minimum.
-template <typename T>
-__global__ __launch_bounds__(256) void k_hdome_marker(const T *__restrict__ f, T *__restrict__ m,
-                                                      int64_t H, int64_t W, int64_t pitch,
-                                                      uint32_t h, uint32_t *above) {
-    const int lane = threadIdx.x & 63;
-    const int64_t segs = (W + ROW_SEG - 1) / ROW_SEG;
+template <typename T> struct alignas(16) Word {
+    T e[16 / sizeof(T)];
+};
+
+template <typename T, int KIND>
+__device__ __forceinline__ void pass_pixel(const T *f, const T *r, T *m, uint8_t *o, uint32_t h,
+                                           bool all_min, bool &any, int64_t i, int64_t oi) {
+    const uint32_t kf = K<T>::key(f[i]);
+    if (KIND == P_MARKER) {
+        any |= kf != 0;
+        m[i] = K<T>::val(kf > h ? kf - h : 0u);
+    } else if (KIND == P_DOME) {
+        m[i] = (T)(int32_t)(kf - K<T>::key(r[i])); // m aliases f here
+    } else {
+        o[oi] = (all_min || kf > K<T>::key(r[i])) ? 255 : 0;
+    }
+}
+
+template <typename T, int KIND, bool WORDS>
+__global__ __launch_bounds__(256) void k_stream_pass(const T *f, const T *r, T *m,
+                                                     uint8_t *__restrict__ o, int64_t H,
+                                                     int64_t W, int64_t pitch, int64_t out_pitch,
+                                                     uint32_t h, uint32_t *above) {
+    constexpr int EPW = WORDS ? 16 / (int)sizeof(T) : 1;
+    const int64_t wpr = (W + EPW - 1) / EPW; // items per row
+    const bool all_min = KIND == P_RMAX && *above == 0;
     bool any = false;
-    for (int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); it < H * segs;
-         it += (int64_t)gridDim.x * 4) {
-        const int64_t y = it / segs, x0 = (it - y * segs) * ROW_SEG;
+    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < H * wpr;
+         it += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t y = it / wpr, x0 = (it - y * wpr) * EPW;
+        const int64_t i0 = y * pitch + x0, o0 = y * out_pitch + x0;
+        if (WORDS && x0 + EPW <= W) {
+            const Word<T> wf = *(const Word<T> *)(f + i0);
+            if (KIND == P_MARKER) {
+                Word<T> wm;
 #pragma unroll
-        for (int k = 0; k < ROW_SEG / 64; ++k) {
-            const int64_t x = x0 + k * 64 + lane;
-            if (x < W) {
-                const uint32_t kf = K<T>::key(f[y * pitch + x]);
-                any |= kf != 0;
-                m[y * pitch + x] = K<T>::val(kf > h ? kf - h : 0u);
+                for (int e = 0; e < EPW; ++e) {
+                    const uint32_t kf = K<T>::key(wf.e[e]);
+                    any |= kf != 0;
+                    wm.e[e] = K<T>::val(kf > h ? kf - h : 0u);
+                }
+                *(Word<T> *)(m + i0) = wm;
+            } else {
+                const Word<T> wr = *(const Word<T> *)(r + i0);
+                if (KIND == P_DOME) {
+                    Word<T> wm;
+#pragma unroll
+                    for (int e = 0; e < EPW; ++e)
+                        wm.e[e] = (T)(int32_t)(K<T>::key(wf.e[e]) - K<T>::key(wr.e[e]));
+                    *(Word<T> *)(m + i0) = wm;
+                } else {
+                    uint8_t ob[EPW];
+#pragma unroll
+                    for (int e = 0; e < EPW; ++e)
+                        ob[e] = (all_min || K<T>::key(wf.e[e]) > K<T>::key(wr.e[e])) ? 255 : 0;
+                    if (EPW == 16) {
+                        *(Word<uint8_t> *)(o + o0) = *(const Word<uint8_t> *)ob;
+                    } else {
+                        uint32_t v = 0;
+#pragma unroll
+                        for (int e = 0; e < EPW; ++e) v |= (uint32_t)ob[e] << (8 * e);
+                        *(uint32_t *)(o + o0) = v;
+                    }
+                }
             }
+        } else {
+            for (int e = 0; e < EPW && x0 + e < W; ++e)
+                pass_pixel<T, KIND>(f, r, m, o, h, all_min, any, i0 + e, o0 + e);
         }
     }
-    if (__ballot(any) != 0 && lane == 0) atomicOr(above, 1u);
+    // one atomic per wave at most, and none once some wave has set the flag
+    if (KIND == P_MARKER && __ballot(any) != 0 && (threadIdx.x & 63) == 0 &&
+        __hip_atomic_load(above, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+        atomicOr(above, 1u);
 }
 
-// f <- f - R (the h-dome), R <= f everywhere.
-template <typename T>
-__global__ __launch_bounds__(256) void k_hdome_out(T *__restrict__ f, const T *__restrict__ r,
-                                                   int64_t H, int64_t W, int64_t pitch) {
-    const int lane = threadIdx.x & 63;
-    const int64_t segs = (W + ROW_SEG - 1) / ROW_SEG;
-    for (int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); it < H * segs;
-         it += (int64_t)gridDim.x * 4) {
-        const int64_t y = it / segs, x0 = (it - y * segs) * ROW_SEG;
-#pragma unroll
-        for (int k = 0; k < ROW_SEG / 64; ++k) {
-            const int64_t x = x0 + k * 64 + lane;
-            if (x < W) {
-                const uint32_t d = K<T>::key(f[y * pitch + x]) - K<T>::key(r[y * pitch + x]);
-                f[y * pitch + x] = (T)(int32_t)d; // 0 <= d <= h fits either type
-            }
-        }
-    }
+bool words_ok(const void *p, int64_t pitch_bytes) {
+    return ((uintptr_t)p & 15) == 0 && (pitch_bytes & 15) == 0;
 }
 
-// out = 255 where f > R (a dome of height 1), or everywhere when no pixel is
-// above the minimum; else 0.
-template <typename T>
-__global__ __launch_bounds__(256) void k_rmax_out(const T *__restrict__ f, const T *__restrict__ r,
-                                                  uint8_t *__restrict__ out, int64_t H, int64_t W,
-                                                  int64_t pitch, int64_t out_pitch,
-                                                  const uint32_t *above) {
-    const int lane = threadIdx.x & 63;
-    const int64_t segs = (W + ROW_SEG - 1) / ROW_SEG;
-    const bool all_min = *above == 0;
-    for (int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); it < H * segs;
-         it += (int64_t)gridDim.x * 4) {
-        const int64_t y = it / segs, x0 = (it - y * segs) * ROW_SEG;
-#pragma unroll
-        for (int k = 0; k < ROW_SEG / 64; ++k) {
-            const int64_t x = x0 + k * 64 + lane;
-            if (x < W) {
-                const bool top = all_min || K<T>::key(f[y * pitch + x]) > K<T>::key(r[y * pitch + x]);
-                out[y * out_pitch + x] = top ? 255 : 0;
-            }
-        }
-    }
+template <typename T, int KIND>
+hipError_t stream_pass(const T *f, const T *r, T *m, uint8_t *o, int64_t H, int64_t W,
+                       int64_t pitch, int64_t out_pitch, uint32_t h, uint32_t *above,
+                       hipStream_t s) {
+    const int64_t pb = pitch * (int64_t)sizeof(T);
+    bool words = words_ok(f, pb) && (KIND == P_MARKER || words_ok(r, pb)) &&
+                 (KIND == P_RMAX || words_ok(m, pb));
+    if (KIND == P_RMAX)
+        words = words && ((uintptr_t)o % (16 / sizeof(T))) == 0 &&
+                out_pitch % (int64_t)(16 / sizeof(T)) == 0;
+    const int64_t epw = words ? 16 / (int64_t)sizeof(T) : 1;
+    const int64_t items = H * ((W + epw - 1) / epw);
+    const unsigned g =
+        (unsigned)std::max<int64_t>(1, std::min<int64_t>((items + 255) / 256, MAX_STREAM_BLOCKS));
+    if (words)
+        hipLaunchKernelGGL((k_stream_pass<T, KIND, true>), dim3(g), dim3(256), 0, s, f, r, m, o,
+                           H, W, pitch, out_pitch, h, above);
+    else
+        hipLaunchKernelGGL((k_stream_pass<T, KIND, false>), dim3(g), dim3(256), 0, s, f, r, m, o,
+                           H, W, pitch, out_pitch, h, above);
+    return hipGetLastError();
 }
 
 __global__ void k_zero_u32(uint32_t *p) { *p = 0u; }
@@ -171,10 +217,8 @@ hipError_t hdome_marker(const void *f, void *m, int64_t H, int64_t W, int64_t pi
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, flag);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t items = H * ((W + ROW_SEG - 1) / ROW_SEG);
-    hipLaunchKernelGGL((k_hdome_marker<T>), dim3(grid_for(items, 4)), dim3(256), 0, s,
-                       (const T *)f, (T *)m, H, W, pitch, h, flag);
-    return hipGetLastError();
+    return stream_pass<T, P_MARKER>((const T *)f, nullptr, (T *)m, nullptr, H, W, pitch, 0, h,
+                                    flag, s);
 }
 
 // ------------------------------------------------------------------ RGB2Gray
@@ -424,14 +468,11 @@ int mr_hdome(void *img_inout, int64_t H, int64_t W, int64_t pitch, mr_dtype t, i
     if (e != hipSuccess) return ohip(e, "h-dome marker");
     rc = mr_recon_dilate(marker, img_inout, H, W, pitch, t, conn, ws, L.recon, tune, stream);
     if (rc != MR_OK) return rc;
-    const int64_t items = H * ((W + ROW_SEG - 1) / ROW_SEG);
-    if ((int)t == MR_U8)
-        hipLaunchKernelGGL(k_hdome_out<uint8_t>, dim3(grid_for(items, 4)), dim3(256), 0, s,
-                           (uint8_t *)img_inout, (const uint8_t *)marker, H, W, pitch);
-    else
-        hipLaunchKernelGGL(k_hdome_out<int32_t>, dim3(grid_for(items, 4)), dim3(256), 0, s,
-                           (int32_t *)img_inout, (const int32_t *)marker, H, W, pitch);
-    e = hipGetLastError();
+    e = (int)t == MR_U8
+        ? stream_pass<uint8_t, P_DOME>((const uint8_t *)img_inout, (const uint8_t *)marker,
+                                       (uint8_t *)img_inout, nullptr, H, W, pitch, 0, 0u, flag, s)
+        : stream_pass<int32_t, P_DOME>((const int32_t *)img_inout, (const int32_t *)marker,
+                                       (int32_t *)img_inout, nullptr, H, W, pitch, 0, 0u, flag, s);
     return e == hipSuccess ? MR_OK : ohip(e, "h-dome output");
 }
 
@@ -454,16 +495,11 @@ int mr_regional_maxima(const void *img, void *out_u8, int64_t H, int64_t W, int6
     if (e != hipSuccess) return ohip(e, "regional maxima marker");
     rc = mr_recon_dilate(marker, img, H, W, pitch, t, conn, ws, L.recon, tune, stream);
     if (rc != MR_OK) return rc;
-    const int64_t items = H * ((W + ROW_SEG - 1) / ROW_SEG);
-    if ((int)t == MR_U8)
-        hipLaunchKernelGGL(k_rmax_out<uint8_t>, dim3(grid_for(items, 4)), dim3(256), 0, s,
-                           (const uint8_t *)img, (const uint8_t *)marker, (uint8_t *)out_u8, H, W,
-                           pitch, out_pitch, (const uint32_t *)flag);
-    else
-        hipLaunchKernelGGL(k_rmax_out<int32_t>, dim3(grid_for(items, 4)), dim3(256), 0, s,
-                           (const int32_t *)img, (const int32_t *)marker, (uint8_t *)out_u8, H, W,
-                           pitch, out_pitch, (const uint32_t *)flag);
-    e = hipGetLastError();
+    e = (int)t == MR_U8
+        ? stream_pass<uint8_t, P_RMAX>((const uint8_t *)img, (const uint8_t *)marker, nullptr,
+                                       (uint8_t *)out_u8, H, W, pitch, out_pitch, 0u, flag, s)
+        : stream_pass<int32_t, P_RMAX>((const int32_t *)img, (const int32_t *)marker, nullptr,
+                                       (uint8_t *)out_u8, H, W, pitch, out_pitch, 0u, flag, s);
     return e == hipSuccess ? MR_OK : ohip(e, "regional maxima output");
 }
 

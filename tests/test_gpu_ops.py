@@ -64,6 +64,21 @@ def test_rmax_constant_min_and_pitched():
     check(d.cpu().numpy(), oracle.hdome(mask, 40, 8))
 
 
+@pytest.mark.parametrize("dt", ["u8", "i32"])
+def test_hdome_rmax_word_path_partial_words(dt):
+    # 16-byte aligned planes and pitch with a ragged last word per row: the
+    # streaming passes take whole 16-byte words and finish each row pixel by
+    # pixel; the output plane is aligned too, so regional maxima writes words
+    _, mask = synth.make_tile(150, 411, 30, 3, dt, 0.1)
+    d = to_dev(mask, pad=5)  # pitch 416
+    out = torch.full((150, 416), 7, dtype=torch.uint8, device=DEV)[:, :411]
+    ops.regional_maxima(d, 8, out=out)
+    check(out.cpu().numpy(), oracle.regional_maxima(mask, 8))
+    h = 40 if dt == "u8" else 40 * 257
+    ops.hdome(d, h, 8)
+    check(d.cpu().numpy(), oracle.hdome(mask, h, 8))
+
+
 @pytest.mark.parametrize("conn", [4, 8])
 def test_hdome_rmax_synthetic_4096(conn):
     _, mask, _ = synth.single_4096()
