@@ -594,6 +594,7 @@ struct Appender {
 // one counter update.
 __device__ __forceinline__ void app_flush(Appender &a, int lane) {
     if (a.cnt == 0) return;
+    asm volatile("" : "+v"(lane)); // (as in visit_tile)
     wave_sync();
     const bool valid = (uint32_t)lane < a.cnt;
     const uint32_t e = valid ? a.buf[lane] : 0u;
@@ -816,6 +817,10 @@ __device__ __forceinline__ StageWords visit_tile(const ImgDesc &d, int64_t t, in
     constexpr bool STAGED = PIPE;
     StageWords pre{};
     using P = Pix<T>;
+    // nothing derived from the lane id is hoisted out of the caller's tile
+    // loop: held across the sweeps, such values would be spilled, and their
+    // reloads would wait behind the stores of the visit
+    asm volatile("" : "+v"(lane));
     constexpr bool first = INITIAL;
     const int64_t lt = t - d.tile_base;
     const int ty = (int)(lt / d.ntx), tx = (int)(lt - (int64_t)ty * d.ntx);
