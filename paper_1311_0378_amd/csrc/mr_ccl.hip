@@ -102,7 +102,10 @@ __global__ __launch_bounds__(CT_THREADS) void k_ccl_local(const uint8_t *__restr
     for (int k = 0; k < CT_H / RSTEP; ++k) {
         const int ly = ly0 + k * RSTEP;
         const int64_t y = y0 + ly, x = x0 + lx;
-        fg[k] = y < H && x < W && img[y * pitch + x] != 0;
+        // (a clamped, unconditional load: loads under a branch are waited
+        // for one at a time)
+        const uint8_t px = img[(y < H ? y : H - 1) * pitch + (x < W ? x : W - 1)];
+        fg[k] = y < H && x < W && px != 0;
         P[ly * CT_W + lx] = fg[k] ? (uint32_t)(ly * CT_W + lx) : NONE;
     }
     __syncthreads();
@@ -210,20 +213,44 @@ __global__ __launch_bounds__(128) void k_ccl_merge(int64_t H, int64_t W, int64_t
 
 // ----------------------------------------------------------- flatten, write
 
+// A grid-stride walk over the H x W pixels of a pitched image in linear
+// order: (y, x) of this lane's pixel, advanced by the grid's stride without
+// a division per pixel (H * W < 2^31).
+struct PixelWalk {
+    uint32_t i, y, x, dy, dx, n, W;
+    __device__ PixelWalk(int64_t H, int64_t Wd, uint32_t first, uint32_t stride) {
+        W = (uint32_t)Wd;
+        n = (uint32_t)(H * Wd);
+        i = first;
+        y = first / W;
+        x = first - y * W;
+        dy = stride / W;
+        dx = stride - dy * W;
+    }
+    __device__ bool ok() const { return i < n; }
+    __device__ void next(uint32_t stride) {
+        i += stride;
+        y += dy;
+        x += dx;
+        if (x >= W) {
+            x -= W;
+            ++y;
+        }
+    }
+};
+
 __global__ __launch_bounds__(256) void k_ccl_flatten(int64_t H, int64_t W, uint32_t *__restrict__ F,
                                                      int32_t *__restrict__ labels,
                                                      int64_t lpitch) {
-    const int64_t n = H * W;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * 256) {
-        const uint32_t v = F[i];
+    const uint32_t stride = gridDim.x * 256u;
+    for (PixelWalk w(H, W, blockIdx.x * 256u + threadIdx.x, stride); w.ok(); w.next(stride)) {
+        const uint32_t v = F[w.i];
         int32_t l = 0;
         if (v != NONE) {
             const uint32_t r = gfind(F, v);
             l = (int32_t)r + 1;
         }
-        const int64_t y = i / W;
-        labels[y * lpitch + (i - y * W)] = l;
+        labels[(int64_t)w.y * lpitch + w.x] = l;
     }
 }
 
@@ -235,30 +262,33 @@ __global__ __launch_bounds__(256) void k_fill_i32(int32_t *p, int64_t n, int32_t
         p[i] = v;
 }
 
-constexpr int AREA_RUN = 16; // consecutive pixels of a row per lane
-
-// Count pixels per label: each lane walks AREA_RUN consecutive pixels of one
-// row and adds each run of equal labels with one atomic.
+// Count pixels per label: a wave reads 64 consecutive pixels of the image in
+// linear order (one per lane, coalesced); a lane whose label differs from
+// the previous pixel's (or that starts a row or the wave's chunk) heads a
+// run, and adds the run's length, up to the next head, with one atomic.
+// Background (0) and out-of-range labels are not counted. A run that spans
+// two chunks is added in two parts.
 __global__ __launch_bounds__(256) void k_area_count(const int32_t *__restrict__ labels,
                                                     int64_t H, int64_t W, int64_t pitch,
                                                     int32_t *__restrict__ area) {
-    const int64_t runs = (W + AREA_RUN - 1) / AREA_RUN, n = H * runs;
-    const int64_t N = H * W;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * 256) {
-        const int64_t y = i / runs, x0 = (i - y * runs) * AREA_RUN;
-        const int32_t *row = labels + y * pitch;
-        int32_t cur = 0, cnt = 0;
-        for (int k = 0; k < AREA_RUN && x0 + k < W; ++k) {
-            const int32_t l = row[x0 + k];
-            if (l != cur) {
-                if (cur > 0 && cnt) atomicAdd(area + cur, cnt);
-                cur = l;
-                cnt = 0;
-            }
-            cnt += (l > 0 && (int64_t)l <= N) ? 1 : 0;
+    const uint32_t N = (uint32_t)(H * W);
+    const int lane = threadIdx.x & 63;
+    const uint32_t wave = blockIdx.x * 4u + (threadIdx.x >> 6), waves = gridDim.x * 4u;
+    const uint32_t stride = waves * 64u;
+    // every lane of a wave stays in the loop while its chunk has pixels, so
+    // the cross-lane steps below see the whole wave
+    for (PixelWalk w(H, W, wave * 64u + lane, stride); w.i - lane < N; w.next(stride)) {
+        const bool in = w.ok();
+        const int32_t l = in ? labels[(int64_t)w.y * pitch + w.x] : 0;
+        const int32_t prev = __shfl_up(l, 1);
+        const bool head = in && (lane == 0 || w.x == 0 || l != prev);
+        const uint64_t heads = __ballot(head);
+        const uint64_t valid = __ballot(in);
+        if (head && l > 0 && (uint32_t)l <= N) {
+            const uint64_t later = lane == 63 ? 0ull : (heads >> (lane + 1)) << (lane + 1);
+            const int end = later ? __builtin_ctzll(later) : 64 - __builtin_clzll(valid);
+            atomicAdd(area + l, end - lane);
         }
-        if (cur > 0 && cnt) atomicAdd(area + cur, cnt);
     }
 }
 
@@ -266,11 +296,10 @@ __global__ __launch_bounds__(256) void k_area_filter(int32_t *__restrict__ label
                                                      int64_t W, int64_t pitch,
                                                      const int32_t *__restrict__ area,
                                                      int64_t lo, int64_t hi) {
-    const int64_t n = H * W, N = H * W;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * 256) {
-        const int64_t y = i / W;
-        int32_t *p = labels + y * pitch + (i - y * W);
+    const int64_t N = H * W;
+    const uint32_t stride = gridDim.x * 256u;
+    for (PixelWalk w(H, W, blockIdx.x * 256u + threadIdx.x, stride); w.ok(); w.next(stride)) {
+        int32_t *p = labels + (int64_t)w.y * pitch + w.x;
         const int32_t l = *p;
         if (l > 0 && (int64_t)l <= N) {
             const int64_t a = area[l];
@@ -355,8 +384,7 @@ int mr_area_threshold(void *labels_inout, int64_t H, int64_t W, int64_t pitch, i
     hipStream_t s = (hipStream_t)stream;
     int32_t *area = (int32_t *)ws;
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(H * W + 1)), dim3(256), 0, s, area, H * W + 1, 0);
-    const int64_t runs = H * ((W + AREA_RUN - 1) / AREA_RUN);
-    hipLaunchKernelGGL(k_area_count, dim3(grid_for(runs)), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_area_count, dim3(grid_for(H * W)), dim3(256), 0, s,
                        (const int32_t *)labels_inout, H, W, pitch, area);
     hipLaunchKernelGGL(k_area_filter, dim3(grid_for(H * W)), dim3(256), 0, s,
                        (int32_t *)labels_inout, H, W, pitch, (const int32_t *)area, min_area,

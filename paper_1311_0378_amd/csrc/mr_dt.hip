@@ -77,13 +77,21 @@ __device__ __forceinline__ uint32_t reach(uint32_t prev_row) {
     return m + 1u;
 }
 
+// (one wave per block: LDS hand-offs between its lanes need program order
+// and a compiler barrier, not a workgroup barrier)
+__device__ __forceinline__ void dt_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ void transpose(uint32_t (&A)[DS], uint32_t (*tb)[DS + 1], int lane) {
 #pragma unroll
     for (int r = 0; r < DS; ++r) tb[r][lane] = A[r];
-    __syncthreads();
+    dt_wave_sync();
 #pragma unroll
     for (int c = 0; c < DS; ++c) A[c] = tb[lane][c];
-    __syncthreads();
+    dt_wave_sync();
 }
 
 template <int CONN, bool FIRST>
@@ -104,25 +112,47 @@ __global__ __launch_bounds__(64) void k_dt_round(const uint8_t *__restrict__ img
     // the first round builds the tile from the image (background 0, else
     // not reached); later rounds read the distances stored so far. Pixels
     // outside the image are never reached and never lower anything.
+    // Every row is loaded from a clamped, in-bounds address and masked
+    // afterwards. All 64 loads are issued before any of them is used (the
+    // compiler otherwise placed each use, and a wait, right after its load).
+    // Rows are addressed from the tile's first in-image row (a uniform base)
+    // with 32-bit lane offsets, so a load in flight holds one address
+    // register rather than two.
     uint32_t D[DS];
     bool any_bg = false, any_fg = false;
+    const int64_t xc = gx < 0 ? 0 : (gx > W - 1 ? W - 1 : gx);
+    const int64_t y_first = gy0 < 0 ? 0 : gy0;
+    const uint8_t *ib = img + y_first * ipitch;
+    const int32_t *db = dist + y_first * dpitch;
 #pragma unroll
     for (int r = 0; r < DS; ++r) {
         const int64_t gy = gy0 + r;
-        uint32_t v = INF;
-        if (xin && gy >= 0 && gy < H) {
-            if (FIRST) {
-                v = img[gy * ipitch + gx] == 0 ? 0u : INF;
-                any_bg |= v == 0u;
-                any_fg |= v != 0u;
-            } else {
-                v = (uint32_t)dist[gy * dpitch + gx];
-            }
+        const int64_t yc = gy < 0 ? 0 : (gy > H - 1 ? H - 1 : gy);
+        const uint32_t rel = (uint32_t)(yc - y_first);
+        D[r] = FIRST ? (uint32_t)ib[rel * (uint32_t)ipitch + (uint32_t)xc]
+                     : (uint32_t)db[rel * (uint32_t)dpitch + (uint32_t)xc];
+    }
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int r = 0; r < DS; ++r) asm volatile("" : "+v"(D[r]));
+#pragma unroll
+    for (int r = 0; r < DS; ++r) {
+        const int64_t gy = gy0 + r;
+        const bool ok = xin && gy >= 0 && gy < H;
+        if (FIRST) {
+            any_bg |= ok && D[r] == 0;
+            any_fg |= ok && D[r] != 0;
+            D[r] = ok && D[r] == 0 ? 0u : INF;
+        } else {
+            D[r] = ok ? D[r] : INF;
         }
-        D[r] = v;
     }
     if (FIRST) {
-        if (__ballot(any_bg) != 0 && lane == 0) atomicOr(&ctrl->has_bg, 1u);
+        // (one atomic per wave at most, and none once some wave has set it:
+        // tens of thousands of them on the one word serialise)
+        if (__ballot(any_bg) != 0 && lane == 0 &&
+            __hip_atomic_load(&ctrl->has_bg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+            atomicOr(&ctrl->has_bg, 1u);
         // a tile whose pixels (halo included) are all background is final
         if (__ballot(any_fg) == 0) {
             if (in_lane && gx < W) {
