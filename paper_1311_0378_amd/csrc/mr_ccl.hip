@@ -13,7 +13,11 @@
 // one workgroup in LDS with LDS atomics (k_ccl_local), then the trees that
 // cross tile borders are merged in the global forest with device atomics
 // (k_ccl_merge), and finally every pixel follows its tree to the root
-// (k_ccl_flatten). A merge links the larger of two roots below the smaller
+// (k_ccl_flatten). The global forest holds parent index + 1 per pixel and 0
+// for the background, so a root's entry is its label: with unit-pitch label
+// rows the label plane itself is the forest, flattened in place (a pixel
+// whose entry becomes its root's label still points at that root), and the
+// background is written once. A merge links the larger of two roots below the smaller
 // with an atomic minimum on the larger's parent; if another merge got there
 // first, the atomic returns the new parent and the merge goes on from it.
 // Parents only ever decrease and stay below their children, so every walk
@@ -52,7 +56,7 @@ size_t up256(size_t n) { return (n + 255) / 256 * 256; }
 constexpr int CT_H = 32, CT_W = 64;     // tile of the local phase
 constexpr int CT_N = CT_H * CT_W;
 constexpr int CT_THREADS = 256;         // 8 pixels per lane
-constexpr uint32_t NONE = 0xFFFFFFFFu;  // background in the forest
+constexpr uint32_t NONE = 0xFFFFFFFFu;  // background in the tile's LDS forest
 
 // ------------------------------------------------------------- local phase
 
@@ -130,10 +134,10 @@ __global__ __launch_bounds__(CT_THREADS) void k_ccl_local(const uint8_t *__restr
         const int ly = ly0 + k * RSTEP;
         const int64_t y = y0 + ly, x = x0 + lx;
         if (y >= H || x >= W) continue;
-        uint32_t v = NONE;
+        uint32_t v = 0;
         if (fg[k]) {
             const uint32_t r = lfind(P, ly * CT_W + lx);
-            v = (uint32_t)((y0 + r / CT_W) * W + x0 + r % CT_W);
+            v = (uint32_t)((y0 + r / CT_W) * W + x0 + r % CT_W) + 1u;
         }
         forest[y * W + x] = v;
     }
@@ -145,11 +149,12 @@ __device__ __forceinline__ uint32_t gload(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Root index of x's tree in the global forest (entries: parent index + 1).
 __device__ __forceinline__ uint32_t gfind(const uint32_t *F, uint32_t x) {
-    uint32_t p = gload(F + x);
+    uint32_t p = gload(F + x) - 1u;
     while (p != x) {
         x = p;
-        p = gload(F + x);
+        p = gload(F + x) - 1u;
     }
     return x;
 }
@@ -165,7 +170,7 @@ __device__ __forceinline__ void gunion(uint32_t *F, uint32_t a, uint32_t b) {
             b = t;
         }
         const uint32_t old =
-            __hip_atomic_fetch_min(F + b, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_min(F + b, a + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - 1u;
         if (old == b) return;
         b = old;
     }
@@ -198,15 +203,15 @@ __global__ __launch_bounds__(128) void k_ccl_merge(int64_t H, int64_t W, int64_t
     }
     if (y >= H || x >= W) return;
     const uint32_t p = (uint32_t)(y * W + x);
-    if (gload(F + p) == NONE) return;
+    if (gload(F + p) == 0u) return;
     const bool first_row = y == y0, first_col = x == x0, last_col = x == x0 + CT_W - 1;
     // backward neighbours in another tile
-    if (first_col && x > 0 && gload(F + p - 1) != NONE) gunion(F, p, p - 1);
-    if (first_row && y > 0 && gload(F + p - W) != NONE) gunion(F, p, p - (uint32_t)W);
+    if (first_col && x > 0 && gload(F + p - 1) != 0u) gunion(F, p, p - 1);
+    if (first_row && y > 0 && gload(F + p - W) != 0u) gunion(F, p, p - (uint32_t)W);
     if (CONN == 8 && y > 0) {
-        if ((first_row || first_col) && x > 0 && gload(F + p - W - 1) != NONE)
+        if ((first_row || first_col) && x > 0 && gload(F + p - W - 1) != 0u)
             gunion(F, p, p - (uint32_t)W - 1);
-        if ((first_row || last_col) && x + 1 < W && gload(F + p - W + 1) != NONE)
+        if ((first_row || last_col) && x + 1 < W && gload(F + p - W + 1) != 0u)
             gunion(F, p, p - (uint32_t)W + 1);
     }
 }
@@ -239,18 +244,22 @@ struct PixelWalk {
     }
 };
 
-__global__ __launch_bounds__(256) void k_ccl_flatten(int64_t H, int64_t W, uint32_t *__restrict__ F,
-                                                     int32_t *__restrict__ labels,
-                                                     int64_t lpitch) {
+// IN_PLACE: F is the label plane (unit-pitch rows); background entries are
+// already 0 and only foreground pixels are rewritten, each to its root's
+// entry (its label). Otherwise every pixel's label goes to `labels`.
+template <bool IN_PLACE>
+__global__ __launch_bounds__(256) void k_ccl_flatten(int64_t H, int64_t W, uint32_t *F,
+                                                     int32_t *labels, int64_t lpitch) {
     const uint32_t stride = gridDim.x * 256u;
     for (PixelWalk w(H, W, blockIdx.x * 256u + threadIdx.x, stride); w.ok(); w.next(stride)) {
-        const uint32_t v = F[w.i];
-        int32_t l = 0;
-        if (v != NONE) {
-            const uint32_t r = gfind(F, v);
-            l = (int32_t)r + 1;
+        const uint32_t v = gload(F + w.i);
+        if (IN_PLACE) {
+            if (v != 0u)
+                __hip_atomic_store(F + w.i, gfind(F, v - 1u) + 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            labels[(int64_t)w.y * lpitch + w.x] = v != 0u ? (int32_t)(gfind(F, v - 1u) + 1u) : 0;
         }
-        labels[(int64_t)w.y * lpitch + w.x] = l;
     }
 }
 
@@ -345,7 +354,9 @@ int mr_ccl(const void *img, void *labels, int64_t H, int64_t W, int64_t pitch,
     if (ws_bytes < need)
         return cfail(MR_ENOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
     hipStream_t s = (hipStream_t)stream;
-    uint32_t *F = (uint32_t *)ws;
+    // unit-pitch label rows: the label plane is the forest
+    const bool in_place = label_pitch == W;
+    uint32_t *F = in_place ? (uint32_t *)labels : (uint32_t *)ws;
     const int64_t tx = (W + CT_W - 1) / CT_W, ty = (H + CT_H - 1) / CT_H;
     const unsigned tiles = (unsigned)(tx * ty);
     if (conn == 8) {
@@ -357,8 +368,12 @@ int mr_ccl(const void *img, void *labels, int64_t H, int64_t W, int64_t pitch,
                            (const uint8_t *)img, H, W, pitch, tx, F);
         hipLaunchKernelGGL(k_ccl_merge<4>, dim3(tiles), dim3(128), 0, s, H, W, tx, F);
     }
-    hipLaunchKernelGGL(k_ccl_flatten, dim3(grid_for(H * W)), dim3(256), 0, s, H, W, F,
-                       (int32_t *)labels, label_pitch);
+    if (in_place)
+        hipLaunchKernelGGL(k_ccl_flatten<true>, dim3(grid_for(H * W)), dim3(256), 0, s, H, W, F,
+                           (int32_t *)labels, label_pitch);
+    else
+        hipLaunchKernelGGL(k_ccl_flatten<false>, dim3(grid_for(H * W)), dim3(256), 0, s, H, W, F,
+                           (int32_t *)labels, label_pitch);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? MR_OK : chip(e, "ccl");
 }

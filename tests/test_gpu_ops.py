@@ -191,7 +191,12 @@ def test_ccl_snakes_and_edges(conn):
     from test_oracle_pins import serpentine
     _, mask = serpentine(301, 257, 3)
     img = (mask > 0).astype(np.uint8)
-    check(ops.ccl(to_dev(img, pad=9), conn).cpu().numpy(), oracle.ccl(img, conn))
+    want = oracle.ccl(img, conn)
+    check(ops.ccl(to_dev(img, pad=9), conn).cpu().numpy(), want)
+    # label rows with a pitch: the forest lives in the workspace, not in place
+    out = torch.full((301, 257 + 7), 5, dtype=torch.int32, device=DEV)[:, :257]
+    ops.ccl(to_dev(img), conn, out=out)
+    check(out.cpu().numpy(), want, "pitched labels: ")
     for img in (np.zeros((70, 130), np.uint8), np.ones((70, 130), np.uint8)):
         check(ops.ccl(to_dev(img), conn).cpu().numpy(), oracle.ccl(img, conn))
     # stripes one pixel wide joined at alternate ends: one component that
