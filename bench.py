@@ -896,6 +896,48 @@ def leg_ops(args, dev, mask) -> dict:
     return out
 
 
+def queue_planes(args, torch, mrecon, dev, reps: int = 3) -> dict:
+    """The queue phase on uint8 pixels with the dword compare-and-swap
+    (workspace sized by the default tune) against the widened 32-bit plane
+    (workspace sized by the queue tune): whole mr_recon_dilate calls after
+    1, 2 and 4 tile rounds, min of `reps` after a warm-up, each result
+    compared with the oracle."""
+    import oracle
+    from paper_1311_0378_amd import synth
+    S = args.size
+    marker, mask = synth.make_tile(S, S, 12800 if S == 16384 else synth.density_disks(S, S), 0,
+                                   "u8", 0.0)
+    want = torch.from_numpy(oracle.recon_dilate(marker, mask, args.conn)[0]).to(dev)
+    d_mask = torch.from_numpy(mask).to(dev)
+    d_src = torch.from_numpy(marker).to(dev)
+    out = {"workload": f"recon_dilate {S}x{S} u8 conn{args.conn}, 12800 disks, seed 0",
+           "cases": []}
+    for rounds in (1, 2, 4):
+        tune = {"sweep_rounds": rounds}
+        for label, sized in (("dword CAS", None), ("widened plane", tune)):
+            nb = mrecon.workspace_bytes(mrecon.MR_OP_RECON, S, S, torch.uint8, args.conn, sized)
+            ws = mrecon.alloc_workspace(nb, dev)
+            w = d_src.clone()
+            mrecon.recon_dilate(w, d_mask, args.conn, tune=tune, workspace=ws)
+            times = []
+            for _ in range(reps):
+                w.copy_(d_src)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                mrecon.recon_dilate(w, d_mask, args.conn, tune=tune, workspace=ws)
+                torch.cuda.synchronize()
+                times.append((time.perf_counter() - t0) * 1e3)
+            c = mrecon.read_counters(ws)
+            out["cases"].append({"rounds_before_queue": rounds, "raise": label,
+                                 "ms_per_call": round(min(times), 3),
+                                 "workspace_mb": round(nb / 1e6, 1), "pops": c["pops"],
+                                 "pushes": c["pushes"], "cas_retries": c["cas_retries"],
+                                 "bit_exact": bool(torch.equal(w, want))})
+            log(f"queue planes: {out['cases'][-1]}")
+            del ws, w
+    return out
+
+
 def atomic_probe(torch, mrecon, dev, reps: int = 5) -> dict:
     """Relaxed device-scope atomics on pseudo-random words, every wave slot of
     the GPU busy: the ceiling the queue phase's atomics are measured against."""
@@ -962,6 +1004,9 @@ def main():
     ap.add_argument("--atomic-probe", action="store_true",
                     help="time the device atomic-rate probe (mr_probe_atomics) on a 256 MiB and "
                          "a 4 GiB buffer, print one JSON line and exit")
+    ap.add_argument("--queue-planes", action="store_true",
+                    help="time the queue phase with the dword compare-and-swap and with the "
+                         "widened plane (uint8, 1/2/4 rounds first), print one JSON line and exit")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE) of a "
                          "--calibrate-copy run into "
@@ -986,6 +1031,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.atomic_probe:
         print(json.dumps(atomic_probe(torch, mrecon, dev)), flush=True)
+        return
+    if args.queue_planes:
+        print(json.dumps(queue_planes(args, torch, mrecon, dev)), flush=True)
         return
     S, dt, conn = args.size, args.dtype, args.conn
     tune = None

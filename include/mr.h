@@ -117,7 +117,14 @@ void mr_default_tune(mr_tune *out);
 
 /* Workspace bytes needed by one mr_recon_dilate (op = MR_OP_RECON) or
  * mr_fill_holes (op = MR_OP_FILL) call on an H x W image. Returns 0 for
- * invalid arguments (see mr_last_error). */
+ * invalid arguments (see mr_last_error).
+ * For uint8 pixels and a tune with sweep_rounds > 0 (a queue phase) the size
+ * includes a plane of H x W 32-bit keys at its end: the queue phase then
+ * raises a pixel with one atomic maximum there instead of a compare-and-swap
+ * on the dword four pixels share, and the plane is copied in before and out
+ * after it. A workspace sized without that plane (by the default tune) is
+ * still accepted and takes the compare-and-swap. Same for
+ * mr_batch_workspace_bytes, per tile. */
 size_t mr_workspace_bytes(int op, int64_t H, int64_t W, mr_dtype t, int conn,
                           const mr_tune *tune);
 

@@ -51,10 +51,11 @@ struct Layout {
     uint64_t ring_cap = 0;
     size_t off_desc = 0, off_flags = 0, off_lists = 0, off_qflag = 0, off_bitmap = 0, off_ring = 0, off_plane = 0, total = 0;
     int64_t plane_pitch = 0;
+    size_t off_wide = 0; // the queue phase's widened uint8 planes, last (0 bytes when absent)
 };
 
 Layout layout_for(int64_t n_tiles, int64_t fill_plane_bytes, int64_t plane_pitch,
-                  int64_t n_imgs = 1) {
+                  int64_t n_imgs = 1, size_t wide_bytes = 0) {
     Layout L;
     L.n_tiles = n_tiles;
     L.ring_cap = next_pow2((uint64_t)n_tiles + (uint64_t)RING_SLACK);
@@ -73,6 +74,8 @@ Layout layout_for(int64_t n_tiles, int64_t fill_plane_bytes, int64_t plane_pitch
     o = align_up(o + (size_t)L.ring_cap * 4, 256);
     L.off_plane = o;
     o = align_up(o + (size_t)fill_plane_bytes, 256);
+    L.off_wide = o;
+    o = align_up(o + wide_bytes, 256);
     L.total = o;
     L.plane_pitch = plane_pitch;
     return L;
@@ -123,14 +126,23 @@ int check_image(int op, int64_t H, int64_t W, int64_t pitch, int t, int conn) {
     return MR_OK;
 }
 
-Layout single_layout(int op, int64_t H, int64_t W, int t) {
+// A schedule with a queue phase on uint8 pixels asks for widened planes
+// (one 32-bit key per pixel); a call uses them when its workspace holds them,
+// else the queue raises pixels with a compare-and-swap on their dword.
+bool wants_wide(int t, const mr_tune *tune) {
+    return t == MR_U8 && tune && tune->sweep_rounds > 0;
+}
+
+size_t wide_plane_bytes(int64_t H, int64_t W) { return align_up((size_t)H * (size_t)W * 4, 256); }
+
+Layout single_layout(int op, int64_t H, int64_t W, int t, bool wide = false) {
     const int64_t nt = tiles_across(H) * tiles_across(W);
     int64_t plane = 0, pp = 0;
     if (op == MR_OP_FILL) {
         pp = (int64_t)align_up((size_t)W, 64);
         plane = H * pp * t;
     }
-    return layout_for(nt, plane, pp);
+    return layout_for(nt, plane, pp, 1, wide ? wide_plane_bytes(H, W) : 0);
 }
 
 mr_tune effective_tune(const mr_tune *tn) {
@@ -335,12 +347,17 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
         const int maxb = queue_max_blocks(tbytes, conn);
         if (maxb <= 0) return fail(MR_EHIP, "cannot size the queue launch");
         if (blocks == 0 || blocks > maxb) blocks = maxb;
+        // uint8 images with widened planes: the queue works on 32-bit keys
+        if (imgs.wide && (e = launch_widen(imgs, L.n_tiles, true, s)) != hipSuccess)
+            return hip_fail(e, "widen");
         {
             LaunchTimer lt(s, MR_K_QUEUE, 0);
             e = launch_queue(tbytes, conn, imgs, ctrl, bitmap, qflag, ring, L.ring_cap, blocks,
                              QUEUE_WAIT_US, s);
         }
         if (e != hipSuccess) return hip_fail(e, "queue");
+        if (imgs.wide && (e = launch_widen(imgs, L.n_tiles, false, s)) != hipSuccess)
+            return hip_fail(e, "narrow");
         return MR_OK;
     };
     if (tn.sweep_rounds > 0) {
@@ -459,10 +476,12 @@ int run_single(int op, void *J_io, const void *I, int64_t H, int64_t W, int64_t 
     if ((uintptr_t)ws % 256) return fail(MR_EINVAL, "workspace must be 256-byte aligned");
     if ((uintptr_t)J_io % t || (I && (uintptr_t)I % t))
         return fail(MR_EINVAL, "image pointers must be aligned to the pixel size");
-    const Layout L = single_layout(op, H, W, t);
+    Layout L = single_layout(op, H, W, t, wants_wide(t, tune));
+    if (ws_bytes < L.total) L = single_layout(op, H, W, t); // (no room for the widened plane)
     if (ws_bytes < L.total)
         return fail(MR_ENOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes,
                     L.total);
+    const bool wide = L.total > L.off_wide;
     if (pitch == 0) pitch = W;
     ImgDesc d{};
     d.H = H;
@@ -486,12 +505,14 @@ int run_single(int op, void *J_io, const void *I, int64_t H, int64_t W, int64_t 
         d.pJ = L.plane_pitch;
         d.pI = pitch;
     }
+    d.wide = wide ? (uint32_t *)((char *)ws + L.off_wide) : nullptr;
     const mr_tune tn = effective_tune(tune);
     Imgs imgs{};
     imgs.n = 1;
     imgs.owner = nullptr;
     imgs.d = (const ImgDesc *)((char *)ws + L.off_desc);
     imgs.staged = staged_planes(t, d) ? 1 : 0;
+    imgs.wide = wide ? 1 : 0;
     hipError_t e = launch_put_desc((ImgDesc *)imgs.d, d, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "descriptor");
     return run_sequence(t, conn, imgs, L, ws, tn, (hipStream_t)stream, op == MR_OP_FILL, op);
@@ -512,9 +533,11 @@ struct BatchPlan {
 
 // Checks every image and lays the batch out in a workspace (ws may be null
 // when only the size is wanted).
-int plan_batch(const mr_tile *tiles, int32_t n, int t, int conn, void *ws, BatchPlan &bp) {
+int plan_batch(const mr_tile *tiles, int32_t n, int t, int conn, void *ws, BatchPlan &bp,
+               bool wide = false) {
     if (!tiles || n < 1) return fail(MR_EINVAL, "need at least one tile");
     int64_t n_tiles = 0, fill_bytes = 0;
+    size_t wide_bytes = 0;
     bp.descs.resize((size_t)n);
     for (int32_t i = 0; i < n; ++i) {
         const mr_tile &tl = tiles[i];
@@ -550,14 +573,21 @@ int plan_batch(const mr_tile *tiles, int32_t n, int t, int conn, void *ws, Batch
             bp.any_fill = true;
         }
         d.first_round = 1;
+        if (wide) {
+            d.wide = (uint32_t *)(uintptr_t)wide_bytes; // offset for now, based below
+            wide_bytes += wide_plane_bytes(tl.H, tl.W);
+        }
         n_tiles += (int64_t)d.ntx * d.nty;
         bp.data_bytes += align_up((size_t)tl.H * tl.W * t, 256);
         if (n_tiles >= (1ll << 31) - 1) return fail(MR_EINVAL, "batch too large");
     }
-    bp.L = layout_for(n_tiles, fill_bytes, 0, n);
-    for (auto &d : bp.descs)
+    bp.L = layout_for(n_tiles, fill_bytes, 0, n, wide_bytes);
+    for (auto &d : bp.descs) {
         if (d.op == MR_OP_FILL)
             d.J = ws ? (void *)((char *)ws + bp.L.off_plane + (uintptr_t)d.J) : nullptr;
+        if (wide)
+            d.wide = ws ? (uint32_t *)((char *)ws + bp.L.off_wide + (uintptr_t)d.wide) : nullptr;
+    }
     return MR_OK;
 }
 
@@ -568,14 +598,19 @@ int run_batch(const mr_tile *tiles, int32_t n, int t, int conn, void *ws, size_t
     if (!ws) return fail(MR_EINVAL, "null workspace");
     if ((uintptr_t)ws % 256) return fail(MR_EINVAL, "workspace must be 256-byte aligned");
     BatchPlan bp;
-    if ((rc = plan_batch(tiles, n, t, conn, ws, bp)) != MR_OK) return rc;
+    bool wide = wants_wide(t, tune);
+    if ((rc = plan_batch(tiles, n, t, conn, ws, bp, wide)) != MR_OK) return rc;
+    if (wide && ws_bytes < bp.L.total) { // no room for the widened planes
+        wide = false;
+        if ((rc = plan_batch(tiles, n, t, conn, ws, bp)) != MR_OK) return rc;
+    }
     if (ws_bytes < bp.L.total)
         return fail(MR_ENOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes,
                     bp.L.total);
     ImgDesc *dd = (ImgDesc *)((char *)ws + bp.L.off_desc);
     hipError_t e = launch_put_descs(dd, bp.descs.data(), n, s);
     if (e != hipSuccess) return hip_fail(e, "descriptors");
-    Imgs imgs{dd, n, nullptr, 1};
+    Imgs imgs{dd, n, nullptr, 1, wide ? 1 : 0};
     for (const auto &d : bp.descs)
         if (!staged_planes(t, d)) imgs.staged = 0;
     const int op_all = bp.any_fill ? (bp.any_recon ? -1 : MR_OP_FILL) : MR_OP_RECON;
@@ -656,7 +691,7 @@ size_t mr_workspace_bytes(int op, int64_t H, int64_t W, mr_dtype t, int conn, co
     g_err.clear();
     if (check_image(op, H, W, 0, (int)t, conn) != MR_OK) return 0;
     if (check_tune(tune) != MR_OK) return 0;
-    return single_layout(op, H, W, (int)t).total;
+    return single_layout(op, H, W, (int)t, wants_wide((int)t, tune)).total;
 }
 
 int mr_recon_dilate(void *marker_inout, const void *mask, int64_t H, int64_t W, int64_t pitch,
@@ -677,7 +712,8 @@ size_t mr_batch_workspace_bytes(const mr_tile *tiles, int32_t n, mr_dtype t, int
     g_err.clear();
     if (check_tune(tune) != MR_OK) return 0;
     BatchPlan bp;
-    if (plan_batch(tiles, n, (int)t, conn, nullptr, bp) != MR_OK) return 0;
+    if (plan_batch(tiles, n, (int)t, conn, nullptr, bp, wants_wide((int)t, tune)) != MR_OK)
+        return 0;
     return bp.L.total;
 }
 
@@ -805,7 +841,9 @@ int mr_autotune(const mr_tile *tiles, int32_t n, mr_dtype t, int conn, void *ws,
         for (int rep = 0; rep < 2 && rc == MR_OK; ++rep) {
             if ((e = copy_all(false)) != hipSuccess) { rc = hip_fail(e, "restore"); break; }
             if ((e = hipEventRecord(a, s)) != hipSuccess) { rc = hip_fail(e, "event"); break; }
-            rc = run_batch(tiles, n, ti, conn, ws, ws_bytes, &tn, s);
+            // (the bytes past bp.L.total hold the backup: the candidate runs
+            // in the plain batch layout, without widened planes)
+            rc = run_batch(tiles, n, ti, conn, ws, bp.L.total, &tn, s);
             if (rc != MR_OK) break;
             if ((e = hipEventRecord(b, s)) != hipSuccess) { rc = hip_fail(e, "event"); break; }
             if ((e = hipEventSynchronize(b)) != hipSuccess) { rc = hip_fail(e, "sync"); break; }

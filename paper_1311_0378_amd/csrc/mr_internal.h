@@ -30,6 +30,10 @@ struct ImgDesc {
     int32_t ntx, nty;    // tiles across and down
     int32_t op;          // MR_OP_RECON or MR_OP_FILL
     int32_t done;        // serving: 1 once the image needs no more device work
+    // uint8 queue phase: the working image widened to one 32-bit key per
+    // pixel (row pitch W), so that a raise is one atomic maximum instead of a
+    // compare-and-swap on the dword four pixels share; null: no such plane
+    uint32_t *wide;
 };
 
 // Device control block at the start of every workspace. Contended words sit
@@ -77,6 +81,8 @@ struct Imgs {
     // 1 when every image is uint8 with 16-byte aligned planes and pitches
     // (both J and I): the tile rounds may then use the pipelined kernel
     int32_t staged;
+    // 1 when the images have widened planes for the queue phase
+    int32_t wide;
 };
 
 constexpr uint32_t Q_EMPTY = 0xFFFFFFFFu;
@@ -126,6 +132,9 @@ hipError_t launch_tile_queue(int tbytes, int conn, const Imgs &imgs, int64_t n_t
                              const uint32_t *lists, uint32_t round, Ctrl *ctrl, uint32_t *state,
                              uint32_t *ring, uint64_t cap, int max_iters, int grid,
                              unsigned long long wait_us, hipStream_t s, int op_all);
+// The queue phase's widened planes: copy every tile interior of J into
+// `wide` (to_wide), or back (from wide to J).
+hipError_t launch_widen(const Imgs &imgs, int64_t n_tiles, bool to_wide, hipStream_t s);
 hipError_t launch_fill_output(int tbytes, const Imgs &imgs, int64_t n_tiles, hipStream_t s,
                               int64_t t0 = 0);
 hipError_t launch_store_u64(unsigned long long *p, unsigned long long v, hipStream_t s);

@@ -81,8 +81,10 @@ __device__ __forceinline__ ImgDesc desc_at(kptr<ImgDesc> d, int64_t k) {
     r.nty = d[k].nty;
     r.op = d[k].op;
     r.done = d[k].done;
+    r.wide = d[k].wide;
     return r;
 }
+static_assert(sizeof(ImgDesc) == 96, "desc_at copies every field of ImgDesc");
 
 // Descriptor of the image that owns `tile` (owner table, else binary search
 // on tile_base).
@@ -1319,7 +1321,21 @@ __device__ __forceinline__ void relax_pixel(const ImgDesc &d, int64_t y, int64_t
     T *Jw = (T *)d.J;
     cgptr<T> Ip = (cgptr<T>)d.I;
     const bool fill = d.op == MR_OP_FILL;
-    const uint32_t jp = Atom<T>::load_key(Jw, y * d.pJ + x);
+    // uint8 images with a widened plane raise 32-bit keys there
+    uint32_t *Wd = sizeof(T) == 1 ? d.wide : nullptr;
+    auto load_key = [&](int64_t yy, int64_t xx) -> uint32_t {
+        if (Wd)
+            return __hip_atomic_load(Wd + yy * d.W + xx, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+        return Atom<T>::load_key(Jw, yy * d.pJ + xx);
+    };
+    auto raise = [&](int64_t yy, int64_t xx, uint32_t k) -> bool {
+        if (Wd)
+            return __hip_atomic_fetch_max(Wd + yy * d.W + xx, k, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT) < k;
+        return Atom<T>::raise(Jw, yy * d.pJ + xx, k, retries);
+    };
+    const uint32_t jp = load_key(y, x);
 #pragma unroll
     for (int k = 0; k < CONN; ++k) {
         // edge neighbours first, then diagonals
@@ -1327,13 +1343,13 @@ __device__ __forceinline__ void relax_pixel(const ImgDesc &d, int64_t y, int64_t
         const int dx = (k < 2) ? 0 : (k == 2) ? -1 : (k == 3) ? 1 : ((k & 1) ? 1 : -1);
         const int64_t yy = y + dy, xx = x + dx;
         if (yy < 0 || yy >= d.H || xx < 0 || xx >= d.W) continue;
-        const uint32_t jq = Atom<T>::load_key(Jw, yy * d.pJ + xx);
+        const uint32_t jq = load_key(yy, xx);
         if (jq >= jp) continue;
         uint32_t iq = P::key(Ip[yy * d.pI + xx]);
         if (fill) iq = P::KMAX - iq;
         if (jq >= iq) continue;
         const uint32_t v = min(jp, iq);
-        if (!Atom<T>::raise(Jw, yy * d.pJ + xx, v, retries)) continue;
+        if (!raise(yy, xx, v)) continue;
         // push: set the pixel's frontier bit, enqueue its tile once
         const int tyq = (int)(yy / TI), txq = (int)(xx / TI);
         const int rq = (int)(yy - (int64_t)tyq * TI) + 1, lq = (int)(xx - (int64_t)txq * TI) + 1;
@@ -1489,6 +1505,27 @@ __global__ void k_clear_start(Ctrl *c, int64_t n_tiles, uint32_t *flags, uint32_
     }
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ring_cap; i += stride)
         ring[i] = Q_EMPTY;
+}
+
+// The queue phase's widened planes (uint8 images): block t copies tile t's
+// interior between J and the image's 32-bit plane, lane = column.
+template <bool TO_WIDE>
+__global__ __launch_bounds__(64) void k_widen(Imgs imgs, int64_t t0) {
+    const int64_t t = t0 + blockIdx.x;
+    const ImgDesc d = load_desc(imgs, t);
+    if (!d.wide) return;
+    const int lane = threadIdx.x;
+    const int64_t lt = t - d.tile_base;
+    const int64_t ty = lt / d.ntx, tx = lt - ty * d.ntx;
+    const int64_t x = tx * TI + lane - 1;
+    if (lane < 1 || lane > TI || x >= d.W) return;
+    uint8_t *J = (uint8_t *)d.J;
+    for (int64_t y = ty * TI, ye = std::min<int64_t>(y + TI, d.H); y < ye; ++y) {
+        if (TO_WIDE)
+            d.wide[y * d.W + x] = J[y * d.pJ + x];
+        else
+            J[y * d.pJ + x] = (uint8_t)d.wide[y * d.W + x];
+    }
 }
 
 // Fill-holes epilogue: out = NOT J over the interior of every tile of the
@@ -1783,6 +1820,17 @@ hipError_t launch_queue(int tbytes, int conn, const Imgs &imgs, Ctrl *ctrl, uint
                          : queue_t<uint8_t, 4>(imgs, ctrl, bitmap, qflag, ring, cap, blocks, wait_us, s);
     return conn == 8 ? queue_t<int32_t, 8>(imgs, ctrl, bitmap, qflag, ring, cap, blocks, wait_us, s)
                      : queue_t<int32_t, 4>(imgs, ctrl, bitmap, qflag, ring, cap, blocks, wait_us, s);
+}
+
+hipError_t launch_widen(const Imgs &imgs, int64_t n_tiles, bool to_wide, hipStream_t s) {
+    for (int64_t t0 = 0; t0 < n_tiles; t0 += (int64_t)1 << 30) {
+        const unsigned g = (unsigned)std::min<int64_t>(n_tiles - t0, (int64_t)1 << 30);
+        if (to_wide)
+            hipLaunchKernelGGL(k_widen<true>, dim3(g), dim3(64), 0, s, imgs, t0);
+        else
+            hipLaunchKernelGGL(k_widen<false>, dim3(g), dim3(64), 0, s, imgs, t0);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_output(int tbytes, const Imgs &imgs, int64_t n_tiles, hipStream_t s,

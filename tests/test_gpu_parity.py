@@ -167,6 +167,44 @@ def test_counters():
     assert c["pops"] >= c["seeds"] > 0
 
 
+@pytest.mark.parametrize("conn", [4, 8])
+def test_queue_widened_plane_and_dword_cas(conn):
+    # uint8 queue phase: with a workspace sized by the queue tune the pixels
+    # are raised on a widened 32-bit plane (no compare-and-swap retries);
+    # sized by the default tune, the same call raises them with the dword
+    # compare-and-swap. Both must give the oracle's result, on a synthetic
+    # tile and on a serpentine corridor, pitched rows included.
+    from gpu_util import to_dev
+    from paper_1311_0378_amd import mrecon
+    from test_oracle_pins import serpentine
+    tune = dict(sweep_rounds=1, max_sweeps=1)
+    for marker, mask in (synth.make_tile(300, 411, 40, 2, "u8", 0.0), serpentine(127, 129, 7)):
+        want, _ = oracle.recon_dilate(marker, mask, conn)
+        for sized, pad in ((tune, 0), (None, 0), (tune, 13)):
+            m, k = to_dev(marker, pad), to_dev(mask, pad)
+            nb = mrecon.workspace_bytes(mrecon.MR_OP_RECON, *marker.shape, m.dtype, conn, sized)
+            ws = mrecon.alloc_workspace(nb, m.device)
+            print(f"[gpu] queue plane {marker.shape} conn{conn} sized={sized} pad={pad}",
+                  flush=True)
+            mrecon.recon_dilate(m, k, conn, tune=tune, workspace=ws)
+            c = mrecon.read_counters(ws)
+            check(m.cpu().numpy(), want)
+            assert c["pops"] > 0
+            if sized is not None:
+                assert c["cas_retries"] == 0
+    # fill-holes and a batch on widened planes
+    img = synth.binary_from_mask(synth.make_tile(257, 300, 30, 4, "u8", 0.2)[1])
+    wantf, _ = oracle.fill_holes(img, conn)
+    check(gpu_fill(img, conn, tune=tune), wantf)
+    items = [synth.make_tile(h, w, 10, 5 + i, "u8", 0.0) for i, (h, w) in
+             enumerate([(130, 200), (64, 64), (311, 97)])]
+    ms = [torch.from_numpy(a).cuda() for a, _ in items]
+    ks = [torch.from_numpy(b).cuda() for _, b in items]
+    mrecon.batch([(a, b, mrecon.MR_OP_RECON) for a, b in zip(ms, ks)], conn, tune=tune)
+    for (a, b), got in zip(items, ms):
+        check(got.cpu().numpy(), oracle.recon_dilate(a, b, conn)[0])
+
+
 # ---------------------------------------------------------- workload sizes
 
 def test_workload_1024():
