@@ -293,7 +293,7 @@ int mr_server_submit(mr_server *s, const mr_job *job, uint64_t *id);
  * Blocks until the previous step's rounds have completed. */
 int mr_server_step(mr_server *s);
 /* Tile rounds each step launches before its one status read-back (1..64,
- * default 2): more rounds per step mean fewer host round trips, at the cost
+ * default 8): more rounds per step mean fewer host round trips, at the cost
  * of noticing a finished job up to that many rounds later. Takes effect at
  * the next step. Errors: MR_EINVAL. */
 int mr_server_set_rounds_per_step(mr_server *s, int32_t k);

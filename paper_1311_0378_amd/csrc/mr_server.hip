@@ -141,7 +141,7 @@ struct mr_server {
     hipEvent_t ev_round[2] = {nullptr, nullptr};
     uint32_t *h_busy = nullptr; // pinned, [2][max_jobs]: busy after the last step of each parity
     uint32_t round = 1;         // the round the next step launches first
-    int32_t rounds_per_step = 2;
+    int32_t rounds_per_step = 8;
     uint64_t steps = 0;         // steps that launched rounds
     uint32_t inflight = 0;      // last round of the step launched, not yet retired (0: none)
     int inflight_buf = 0;       // its status buffer and event

@@ -2,7 +2,8 @@
 times (library defaults), and at the largest plane the interface accepts.
 
 * 16384 x 16384 reconstruction, u8 and i32 (values scaled to 0..65535),
-  8-connectivity: every pixel against the oracle.
+  8-connectivity: every pixel against the oracle; and the int32 copy of the
+  u8 workload with every value times 257 against 257 times the u8 result.
 * 65535 x 65535 u8 (H * pitch just below 2^32): the mask carries walls of
   zeros every 4096 rows and columns. Under 4- or 8-connectivity nothing can
   propagate through a zero-mask wall one pixel thick (the wall pixels stay at
@@ -37,6 +38,20 @@ def test_16384_full_image(dt):
     got = gpu_recon(marker, mask, 8)
     want, _ = oracle.recon_dilate(marker, mask, 8)
     assert np.array_equal(got, want), first_mismatch(got, want)
+
+
+def test_16384_i32_copy_of_u8_is_257_times():
+    # the int32 copy of the uint8 workload with every value times 257: the
+    # order of values is the same, so R(257 M, 257 I) = 257 R(M, I) (both
+    # runs on the GPU, then the uint8 one against the oracle as well)
+    marker, mask = synth.single_16384("u8")
+    print("[gpu] 16384x16384 u8 and its x257 int32 copy, conn8", flush=True)
+    got8 = gpu_recon(marker, mask, 8)
+    got32 = gpu_recon(marker.astype(np.int32) * 257, mask.astype(np.int32) * 257, 8)
+    want = got8.astype(np.int32) * 257
+    assert np.array_equal(got32, want), first_mismatch(got32, want)
+    want8, _ = oracle.recon_dilate(marker, mask, 8)
+    assert np.array_equal(got8, want8), first_mismatch(got8, want8)
 
 
 def _walled_inputs(H, W, step, seed):
