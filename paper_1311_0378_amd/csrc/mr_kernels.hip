@@ -960,17 +960,6 @@ __device__ __forceinline__ StageWords visit_tile(const ImgDesc &d, int64_t t, in
     return pre;
 }
 
-// One tile round on a persistent grid (two waves per SIMD). Block b serves
-// band b % NBANDS and visits either every tile of the band (all_tiles) or the
-// band's dirty list. Tiles are dealt to the band's blocks by static
-// interleave, so no block gets more than one tile above another. A round that
-// lists at most one tile per block, but more in some band than that band has
-// blocks, deals across bands instead. A tile
-// builds its image's initial working values in the image's first round.
-// V selects the visit: -1 dispatches per tile on the image's op and first
-// round (mixed batches, the server); otherwise (FILL << 1) | INITIAL for
-// launches whose tiles all take the same visit, which keeps the other three
-// variants' code, and their registers, out of the kernel.
 // The tiles a block of a round visits: band `band`'s list (or, with
 // all_tiles, the whole band), entries local, local + per, ... below n, from
 // list_in (band start already applied). A round that lists no more tiles
@@ -986,8 +975,22 @@ struct RoundWork {
     int64_t local, per, n, lo;
     const uint32_t *list_in;
     bool fwd;
+    // walk the band's tiles in order (static interleave, as in an all-tiles
+    // round) and visit those whose epoch flag holds this round, instead of
+    // reading the list
+    bool walk;
 };
 
+// all_tiles: 1 visits every tile (an image's first round), 0 the dirty
+// lists, 2 the dirty lists or, for a band that lists at least half its
+// tiles, the walk. A list is built in marking order, which scatters the
+// tiles visited at one time over the band; the walk visits neighbouring
+// tiles together, so they share the cache lines their rows straddle.
+// The walk relies on what launch sequences that start at round 1 guarantee:
+// a tile is listed for round r exactly when its flag reached r in round
+// r - 1. A flag raised again (to r + 1) before the walk reads it means the
+// tile is in the next round's list as well, so leaving it to that round
+// loses nothing.
 __device__ __forceinline__ RoundWork round_work(int64_t n_tiles, const uint32_t *lists,
                                                 const uint32_t *counts_in, int all_tiles,
                                                 uint32_t round) {
@@ -995,7 +998,8 @@ __device__ __forceinline__ RoundWork round_work(int64_t n_tiles, const uint32_t 
     w.band = blockIdx.x % NBANDS;
     w.local = blockIdx.x / NBANDS;
     w.per = gridDim.x / NBANDS;
-    if (all_tiles) {
+    w.walk = false;
+    if (all_tiles == 1) {
         w.n = band_lo(n_tiles, w.band + 1) - band_lo(n_tiles, w.band);
     } else {
         uint32_t c[NBANDS], total = 0, cmax = 0;
@@ -1021,6 +1025,11 @@ __device__ __forceinline__ RoundWork round_work(int64_t n_tiles, const uint32_t 
             w.n = blockIdx.x < total ? cb : 0;
         } else {
             w.n = kconst(counts_in)[w.band];
+            const int64_t nb = band_lo(n_tiles, w.band + 1) - band_lo(n_tiles, w.band);
+            if (all_tiles == 2 && w.n > 0 && 2 * w.n >= nb) {
+                w.walk = true;
+                w.n = nb;
+            }
         }
     }
     w.lo = band_lo(n_tiles, w.band);
@@ -1035,7 +1044,49 @@ __device__ __forceinline__ RoundWork round_work(int64_t n_tiles, const uint32_t 
 
 __device__ __forceinline__ int64_t round_tile(const RoundWork &w, int all_tiles, int64_t i) {
     const int64_t k = w.fwd ? i : w.n - 1 - i;
-    return all_tiles ? w.lo + k : (int64_t)kconst(w.list_in)[k];
+    return all_tiles == 1 || w.walk ? w.lo + k : (int64_t)kconst(w.list_in)[k];
+}
+
+// The block's tiles of a round, in order: band entries local, local + per,
+// ... below n. A walk reads the epoch flags of 64 entries at once and keeps
+// those that hold the round.
+struct TileCursor {
+    int64_t i;     // next entry; walk: first entry of the next batch
+    int64_t wi;    // walk: first entry of the current batch
+    uint64_t mask; // walk: bit j set if entry wi + j * per is to be visited
+};
+
+__device__ __forceinline__ TileCursor cursor_start(const RoundWork &w) {
+    return TileCursor{w.local, w.local, 0ull};
+}
+
+// The next tile, or -1 when the block has none left (wave-uniform).
+__device__ __forceinline__ int64_t cursor_next(TileCursor &c, const RoundWork &w, int all_tiles,
+                                               const uint32_t *flags, uint32_t round, int lane) {
+    if (!w.walk) {
+        if (c.i >= w.n) return -1;
+        const int64_t t = round_tile(w, all_tiles, c.i);
+        c.i += w.per;
+        return t;
+    }
+    while (c.mask == 0) {
+        if (c.i >= w.n) return -1;
+        uint32_t ln = (uint32_t)lane;
+        asm volatile("" : "+v"(ln));
+        const int64_t e = c.i + (int64_t)ln * w.per;
+        bool take = false;
+        if (e < w.n) {
+            const int64_t t = w.lo + (w.fwd ? e : w.n - 1 - e);
+            take = __hip_atomic_load(flags + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                   round;
+        }
+        c.mask = __ballot(take);
+        c.wi = c.i;
+        c.i += 64 * w.per;
+    }
+    const int j = __builtin_ctzll(c.mask);
+    c.mask &= c.mask - 1;
+    return round_tile(w, all_tiles, c.wi + (int64_t)j * w.per);
 }
 
 // One tile round on a persistent grid (two waves per SIMD). Block b serves
@@ -1060,8 +1111,8 @@ __global__ __launch_bounds__(64, 2) void k_tile_round(Imgs imgs, int64_t n_tiles
     const int lane = threadIdx.x;
     const RoundWork w = round_work(n_tiles, lists, counts_in, all_tiles, round);
     Appender app{abuf, 0, lists + ((round + 1) & 1) * n_tiles, counts_out, n_tiles};
-    for (int64_t i = w.local; i < w.n; i += w.per) {
-        const int64_t t = round_tile(w, all_tiles, i);
+    TileCursor cur = cursor_start(w);
+    for (int64_t t; (t = cursor_next(cur, w, all_tiles, flags, round, lane)) >= 0;) {
         const ImgDesc d = load_desc(imgs, t);
         if (V >= 0) {
             if (!d.done)
@@ -1109,9 +1160,9 @@ __global__ __launch_bounds__(64, 2) void k_tile_round_pf(Imgs imgs, int64_t n_ti
     const RoundWork w = round_work(n_tiles, lists, counts_in, all_tiles, round);
     Appender app{abuf, 0, lists + ((round + 1) & 1) * n_tiles, counts_out, n_tiles};
     uint8_t *stage = (uint8_t *)tb;
-    if (w.local < w.n) {
-        int64_t i = w.local;
-        int64_t t = round_tile(w, all_tiles, i);
+    TileCursor cur = cursor_start(w);
+    int64_t t = cursor_next(cur, w, all_tiles, flags, round, lane);
+    if (t >= 0) {
         ImgDesc d = load_desc(imgs, t);
         StageWords pre = stage_fetch<needJ>(d, t, lane);
         while (true) {
@@ -1120,15 +1171,14 @@ __global__ __launch_bounds__(64, 2) void k_tile_round_pf(Imgs imgs, int64_t n_ti
             wave_sync();
             stage_commit_words<needJ>(pre, lane, stage);
             wave_sync();
-            const int64_t in = i + w.per;
-            const bool has = in < w.n;
-            const int64_t tn = has ? round_tile(w, all_tiles, in) : t;
+            int64_t tn = cursor_next(cur, w, all_tiles, flags, round, lane);
+            const bool has = tn >= 0;
+            if (!has) tn = t;
             const ImgDesc dn = has ? load_desc(imgs, tn) : d;
             pre = visit_tile<uint8_t, CONN, FILL, INITIAL, false, true>(
                 d, t, lane, flags, app, ctrl, round, max_iters, tb, nullptr, &dn, tn, has);
             if (app.cnt > APP_CAP - 9) app_flush(app, lane);
             if (!has) break;
-            i = in;
             t = tn;
             d = dn;
         }
@@ -1704,9 +1754,15 @@ hipError_t launch_tile_round(int tbytes, int conn, const Imgs &imgs, int64_t n_t
     // every image starts in round 1 here, so with one op for all of them the
     // visit is known for the whole launch
     const int variant = op_all < 0 ? -1 : ((op_all == MR_OP_FILL ? 2 : 0) | (round == 1 ? 1 : 0));
+    // Round 1 visits every tile. Later int32 rounds may walk dense bands
+    // (the lists of a sequence that starts at round 1 allow it): their
+    // visits are bound by memory traffic, which the walk's order lowers.
+    // uint8 visits are bound by issue and latency instead; there the walk
+    // only adds visits (neighbours visited together see each other's halos
+    // stale more often), so uint8 rounds keep the lists.
     return tile_round_any(tbytes, conn, imgs, n_tiles, flags, lists, ctrl->round_tiles[round],
-                          ctrl->round_tiles[round + 1], round == 1, ctrl, round, max_iters, grid,
-                          s, variant);
+                          ctrl->round_tiles[round + 1], round == 1 ? 1 : (tbytes == 4 ? 2 : 0), ctrl, round,
+                          max_iters, grid, s, variant);
 }
 
 template <typename T, int CONN, int V>
