@@ -411,7 +411,7 @@ def leg_batched(args, dev) -> dict:
     t1 = time.time()
     tune = mrecon.autotune(items, 8, stream=stream)
     tuned = {"sweep_rounds": tune.sweep_rounds, "max_sweeps": tune.max_sweeps,
-             "tail_rounds": tune.tail_rounds}
+             "tail_rounds": tune.tail_rounds, "first_sweeps": tune.first_sweeps}
     log(f"batched: autotune {tuned} in {time.time() - t1:.1f}s")
     wsb = mrecon.alloc_workspace(mrecon.batch_workspace_bytes(items, 8, tune), dev)
     graph = (mrecon.BatchGraph(items, 8, tune, wsb)
@@ -914,6 +914,7 @@ def queue_planes(args, torch, mrecon, dev, reps: int = 3) -> dict:
            "cases": []}
     for rounds in (1, 2, 4):
         tune = {"sweep_rounds": rounds}
+        nb_cas = mrecon.workspace_bytes(mrecon.MR_OP_RECON, S, S, torch.uint8, args.conn, None)
         for label, sized in (("dword CAS", None), ("widened plane", tune)):
             nb = mrecon.workspace_bytes(mrecon.MR_OP_RECON, S, S, torch.uint8, args.conn, sized)
             ws = mrecon.alloc_workspace(nb, dev)
@@ -932,6 +933,9 @@ def queue_planes(args, torch, mrecon, dev, reps: int = 3) -> dict:
                                  "ms_per_call": round(min(times), 3),
                                  "workspace_mb": round(nb / 1e6, 1), "pops": c["pops"],
                                  "pushes": c["pushes"], "cas_retries": c["cas_retries"],
+                                 # (the library sizes widened planes only for
+                                 # schedules of one or two rounds)
+                                 "widened_plane_in_workspace": nb > nb_cas,
                                  "bit_exact": bool(torch.equal(w, want))})
             log(f"queue planes: {out['cases'][-1]}")
             del ws, w

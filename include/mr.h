@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define MR_ABI_VERSION 3 /* 2: mr_tune.tail_rounds; 3: mr_job.flags */
+#define MR_ABI_VERSION 4 /* 2: mr_tune.tail_rounds; 3: mr_job.flags; 4: mr_tune.first_sweeps */
 
 typedef enum { MR_U8 = 1, MR_I32 = 4 } mr_dtype; /* value = bytes per pixel */
 
@@ -91,6 +91,12 @@ typedef struct {
                                   waits for the device (0..1000, default 8;
                                   0 = rounds until no tile is dirty, polled
                                   by the host, and converge_rounds applies) */
+    int32_t first_sweeps;      /* cap on sweep iterations per tile visit in
+                                  the first tile round (1..1024, default 1).
+                                  Its halos are mostly stale, and nearly every
+                                  tile is visited again; a visit stopped at
+                                  this cap lists its tile for the next round
+                                  without checking its fixed point */
 } mr_tune;
 
 /* Work counters of the last call that used a workspace. */

@@ -104,6 +104,8 @@ int check_tune(const mr_tune *tn) {
         return fail(MR_EINVAL, "tune.converge_rounds must be in 0..%d", MAX_ROUNDS);
     if (tn->tail_rounds < 0 || tn->tail_rounds > MAX_ROUNDS)
         return fail(MR_EINVAL, "tune.tail_rounds must be in 0..%d", MAX_ROUNDS);
+    if (tn->first_sweeps < 1 || tn->first_sweeps > 1024)
+        return fail(MR_EINVAL, "tune.first_sweeps must be in 1..1024 (got %d)", tn->first_sweeps);
     return MR_OK;
 }
 
@@ -126,11 +128,14 @@ int check_image(int op, int64_t H, int64_t W, int64_t pitch, int t, int conn) {
     return MR_OK;
 }
 
-// A schedule with a queue phase on uint8 pixels asks for widened planes
-// (one 32-bit key per pixel); a call uses them when its workspace holds them,
-// else the queue raises pixels with a compare-and-swap on their dword.
+// A schedule whose queue phase follows one or two tile rounds on uint8
+// pixels asks for widened planes (one 32-bit key per pixel); a call uses them
+// when its workspace holds them, else the queue raises pixels with a
+// compare-and-swap on their dword. The planes cost a copy of every tile each
+// way, which pays only while the queue does most of the raising: after four
+// rounds the compare-and-swap measured faster.
 bool wants_wide(int t, const mr_tune *tune) {
-    return t == MR_U8 && tune && tune->sweep_rounds > 0;
+    return t == MR_U8 && tune && tune->sweep_rounds > 0 && tune->sweep_rounds <= 2;
 }
 
 size_t wide_plane_bytes(int64_t H, int64_t W) { return align_up((size_t)H * (size_t)W * 4, 256); }
@@ -323,9 +328,12 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
     RoundSpan span(s); // span-mode timing of consecutive rounds
     span.begin(round);
     {
+        // The first round's visits have their own sweep cap: their halos
+        // are mostly stale (the neighbours have not been visited yet), and
+        // nearly every tile is visited again in round 2.
         LaunchTimer lt(s, MR_K_TILE_ROUND, (int32_t)round);
         e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl, round,
-                              tn.max_sweeps, grid, s, op_all);
+                              tn.first_sweeps, grid, s, op_all);
     }
     if (e != hipSuccess) return hip_fail(e, "tile round");
     span.add();
@@ -685,6 +693,7 @@ void mr_default_tune(mr_tune *out) {
     out->persistent_blocks = 0;
     out->converge_rounds = 0;
     out->tail_rounds = 8;
+    out->first_sweeps = 1;
 }
 
 size_t mr_workspace_bytes(int op, int64_t H, int64_t W, mr_dtype t, int conn, const mr_tune *tune) {
@@ -816,11 +825,12 @@ int mr_autotune(const mr_tile *tiles, int32_t n, mr_dtype t, int conn, void *ws,
     };
     hipError_t e = copy_all(true);
     if (e != hipSuccess) return hip_fail(e, "backup");
-    // {sweep_rounds, max_sweeps, tail_rounds}
-    static const int cand[][3] = {{-1, 16, 0}, {-1, 3, 0}, {-1, 16, 4}, {-1, 16, 6},
-                                  {-1, 16, 8}, {-1, 16, 12}, {4, 16, 0}, {8, 16, 0},
-                                  {12, 16, 0}, {16, 16, 0}, {24, 16, 0}, {32, 16, 0},
-                                  {48, 16, 0}, {16, 3, 0}};
+    // {sweep_rounds, max_sweeps, tail_rounds, first_sweeps}
+    static const int cand[][4] = {{-1, 16, 0, 1},  {-1, 3, 0, 1},   {-1, 16, 4, 1},  {-1, 16, 6, 1},
+                                  {-1, 16, 8, 1},  {-1, 16, 12, 1}, {-1, 16, 4, 16}, {-1, 16, 6, 16},
+                                  {-1, 16, 8, 16}, {-1, 16, 12, 16}, {4, 16, 0, 1},  {8, 16, 0, 1},
+                                  {12, 16, 0, 1},  {16, 16, 0, 1},  {24, 16, 0, 1},  {32, 16, 0, 1},
+                                  {48, 16, 0, 1},  {16, 3, 0, 1}};
     hipEvent_t a = nullptr, b = nullptr;
     if ((e = hipEventCreate(&a)) != hipSuccess || (e = hipEventCreate(&b)) != hipSuccess) {
         if (a) (void)hipEventDestroy(a);
@@ -837,6 +847,7 @@ int mr_autotune(const mr_tile *tiles, int32_t n, mr_dtype t, int conn, void *ws,
         tn.sweep_rounds = c[0];
         tn.max_sweeps = c[1];
         tn.tail_rounds = c[2];
+        tn.first_sweeps = c[3];
         float t_best = 1e30f;
         for (int rep = 0; rep < 2 && rc == MR_OK; ++rep) {
             if ((e = copy_all(false)) != hipSuccess) { rc = hip_fail(e, "restore"); break; }

@@ -881,8 +881,10 @@ __device__ __forceinline__ StageWords visit_tile(const ImgDesc &d, int64_t t, in
         }
         changed = true;
         // (int32 visits start checking after the second iteration, which
-        // measures faster for them)
+        // measures faster for them; a first visit at its sweep cap leaves
+        // the check out: the tile is left unstable, and so listed again)
         if (sizeof(T) == 4 && it < 2) continue;
+        if (INITIAL && it >= max_iters) break;
         relax_once<CONN>(J, I);
         col_now = col_sum<T>(J);
         ch = in_lane && col_now != col_prev;

@@ -15,7 +15,7 @@ import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmrecon.so")
-ABI_VERSION = 3  # the layout of the structs below (include/mr.h MR_ABI_VERSION)
+ABI_VERSION = 4  # the layout of the structs below (include/mr.h MR_ABI_VERSION)
 HEADER = os.path.join(HERE, "..", "include", "mr.h")
 
 MR_U8, MR_I32 = 1, 4
@@ -36,7 +36,7 @@ class MrError(RuntimeError):
 class Tune(ctypes.Structure):
     _fields_ = [("sweep_rounds", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("persistent_blocks", ctypes.c_int32), ("converge_rounds", ctypes.c_int32),
-                ("tail_rounds", ctypes.c_int32)]
+                ("tail_rounds", ctypes.c_int32), ("first_sweeps", ctypes.c_int32)]
 
 
 class Tile(ctypes.Structure):

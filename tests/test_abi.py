@@ -20,13 +20,13 @@ def test_exports_every_declared_function(L):
 
 
 def test_abi_version(L):
-    assert L.mr_abi_version() == mrecon.ABI_VERSION == 3
+    assert L.mr_abi_version() == mrecon.ABI_VERSION == 4
 
 
 def test_default_tune():
     t = mrecon.default_tune()
     assert t.sweep_rounds != 0 and 1 <= t.max_sweeps <= 1024 and t.converge_rounds == 0
-    assert 0 <= t.tail_rounds <= 1000
+    assert 0 <= t.tail_rounds <= 1000 and 1 <= t.first_sweeps <= 1024
 
 
 def test_workspace_bytes_grows_with_size():
@@ -80,7 +80,8 @@ def test_recon_rejects(L, kw, code):
                                          ("max_sweeps", 5000), ("persistent_blocks", -1),
                                          ("converge_rounds", -1),
                                          ("converge_rounds", 1001), ("tail_rounds", -1),
-                                         ("tail_rounds", 1001)])
+                                         ("tail_rounds", 1001), ("first_sweeps", 0),
+                                         ("first_sweeps", 1025)])
 def test_recon_rejects_bad_tune(L, field, value):
     t = mrecon.default_tune()
     setattr(t, field, value)

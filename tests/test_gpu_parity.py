@@ -27,7 +27,9 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 TUNES = [None, dict(sweep_rounds=1, max_sweeps=1), dict(sweep_rounds=2, max_sweeps=3),
          dict(sweep_rounds=-1), dict(sweep_rounds=8, persistent_blocks=3),
          dict(sweep_rounds=-1, converge_rounds=2), dict(sweep_rounds=-1, tail_rounds=1),
-         dict(sweep_rounds=-1, tail_rounds=2, max_sweeps=1)]
+         dict(sweep_rounds=-1, tail_rounds=2, max_sweeps=1),
+         dict(sweep_rounds=-1, first_sweeps=16), dict(sweep_rounds=-1, tail_rounds=2, first_sweeps=3),
+         dict(sweep_rounds=3, first_sweeps=1024)]
 
 
 def check(got, want):
