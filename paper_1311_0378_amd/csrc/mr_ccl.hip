@@ -91,16 +91,28 @@ __device__ __forceinline__ void lunion(uint32_t *P, uint32_t a, uint32_t b) {
     }
 }
 
+// One wave holds one tile row per step (lane = column), so a ballot is the
+// row's foreground mask. A pixel starts pointing at the first pixel of its
+// horizontal run, which links every run without an atomic. A run then needs
+// one union per run above it that it touches, made at the first of its
+// pixels that reaches that run: with 4-connectivity a pixel whose
+// above-neighbour is foreground unless its left neighbour (in the same run)
+// reached the same above run through the column before; with 8-connectivity
+// a run's first pixel takes each run among its three above-neighbours, and
+// every later pixel only the column it adds on the right.
 template <int CONN>
 __global__ __launch_bounds__(CT_THREADS) void k_ccl_local(const uint8_t *__restrict__ img,
                                                           int64_t H, int64_t W, int64_t pitch,
                                                           int64_t tiles_x,
                                                           uint32_t *__restrict__ forest) {
     __shared__ uint32_t P[CT_N];
+    __shared__ uint64_t rowfg[CT_H];
+    static_assert(CT_W == 64 && CT_THREADS % 64 == 0, "a wave holds one tile row");
     const int64_t ty = blockIdx.x / tiles_x, tx = blockIdx.x - ty * tiles_x;
     const int64_t y0 = ty * CT_H, x0 = tx * CT_W;
     const int lx = threadIdx.x & (CT_W - 1), ly0 = threadIdx.x / CT_W;
     constexpr int RSTEP = CT_THREADS / CT_W; // rows between a lane's pixels
+    const uint64_t below = (1ull << lx) - 1; // lanes left of this one
     bool fg[CT_H / RSTEP];
 #pragma unroll
     for (int k = 0; k < CT_H / RSTEP; ++k) {
@@ -110,21 +122,32 @@ __global__ __launch_bounds__(CT_THREADS) void k_ccl_local(const uint8_t *__restr
         // for one at a time)
         const uint8_t px = img[(y < H ? y : H - 1) * pitch + (x < W ? x : W - 1)];
         fg[k] = y < H && x < W && px != 0;
-        P[ly * CT_W + lx] = fg[k] ? (uint32_t)(ly * CT_W + lx) : NONE;
+        const uint64_t m = __ballot(fg[k]);
+        // the run starts after the last background pixel to the left
+        const uint64_t z = ~m & below;
+        const int start = z ? 64 - __builtin_clzll(z) : 0;
+        P[ly * CT_W + lx] = fg[k] ? (uint32_t)(ly * CT_W + start) : NONE;
+        if (lx == 0) rowfg[ly] = m;
     }
     __syncthreads();
-    // merge with the backward neighbours inside the tile (left, up, and for
-    // 8-connectivity up-left and up-right): every adjacent pair once
 #pragma unroll
     for (int k = 0; k < CT_H / RSTEP; ++k) {
-        if (!fg[k]) continue;
         const int ly = ly0 + k * RSTEP;
+        if (!fg[k] || ly == 0) continue;
+        const uint64_t m = rowfg[ly], up = rowfg[ly - 1];
         const uint32_t p = ly * CT_W + lx;
-        if (lx > 0 && lds_load(P + p - 1) != NONE) lunion(P, p, p - 1);
-        if (ly > 0 && lds_load(P + p - CT_W) != NONE) lunion(P, p, p - CT_W);
-        if (CONN == 8 && ly > 0) {
-            if (lx > 0 && lds_load(P + p - CT_W - 1) != NONE) lunion(P, p, p - CT_W - 1);
-            if (lx < CT_W - 1 && lds_load(P + p - CT_W + 1) != NONE) lunion(P, p, p - CT_W + 1);
+        const bool left = lx > 0 && ((m >> (lx - 1)) & 1);
+        const bool aL = lx > 0 && ((up >> (lx - 1)) & 1);
+        const bool aC = (up >> lx) & 1;
+        const bool aR = lx < CT_W - 1 && ((up >> (lx + 1)) & 1);
+        if (CONN == 4) {
+            if (aC && !(left && aL)) lunion(P, p, p - CT_W);
+        } else {
+            if (!left) {
+                if (aL) lunion(P, p, p - CT_W - 1);
+                if (aC && !aL) lunion(P, p, p - CT_W);
+            }
+            if (aR && !aC) lunion(P, p, p - CT_W + 1);
         }
     }
     __syncthreads();
