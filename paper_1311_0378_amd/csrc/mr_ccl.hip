@@ -151,6 +151,18 @@ __global__ __launch_bounds__(CT_THREADS) void k_ccl_local(const uint8_t *__restr
         }
     }
     __syncthreads();
+    // every run's first pixel takes its root (only first pixels were ever
+    // linked, so the other pixels of a run still point at it)
+#pragma unroll
+    for (int k = 0; k < CT_H / RSTEP; ++k) {
+        const int ly = ly0 + k * RSTEP;
+        const uint32_t p = ly * CT_W + lx;
+        if (fg[k] && (lx == 0 || !((rowfg[ly] >> (lx - 1)) & 1))) {
+            const uint32_t r = lfind(P, p);
+            if (r != p) __hip_atomic_store(P + p, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+    __syncthreads();
     // each pixel points at its tile-local root, as a global linear index
 #pragma unroll
     for (int k = 0; k < CT_H / RSTEP; ++k) {
@@ -159,7 +171,7 @@ __global__ __launch_bounds__(CT_THREADS) void k_ccl_local(const uint8_t *__restr
         if (y >= H || x >= W) continue;
         uint32_t v = 0;
         if (fg[k]) {
-            const uint32_t r = lfind(P, ly * CT_W + lx);
+            const uint32_t r = P[P[ly * CT_W + lx]];
             v = (uint32_t)((y0 + r / CT_W) * W + x0 + r % CT_W) + 1u;
         }
         forest[y * W + x] = v;
@@ -228,14 +240,32 @@ __global__ __launch_bounds__(128) void k_ccl_merge(int64_t H, int64_t W, int64_t
     const uint32_t p = (uint32_t)(y * W + x);
     if (gload(F + p) == 0u) return;
     const bool first_row = y == y0, first_col = x == x0, last_col = x == x0 + CT_W - 1;
+    const uint32_t Wu = (uint32_t)W;
     // backward neighbours in another tile
     if (first_col && x > 0 && gload(F + p - 1) != 0u) gunion(F, p, p - 1);
-    if (first_row && y > 0 && gload(F + p - W) != 0u) gunion(F, p, p - (uint32_t)W);
-    if (CONN == 8 && y > 0) {
-        if ((first_row || first_col) && x > 0 && gload(F + p - W - 1) != 0u)
-            gunion(F, p, p - (uint32_t)W - 1);
-        if ((first_row || last_col) && x + 1 < W && gload(F + p - W + 1) != 0u)
-            gunion(F, p, p - (uint32_t)W + 1);
+    if (first_row && y > 0) {
+        // The row above is the last row of the tiles above, whose adjacent
+        // foreground pixels within one tile the local phase connected; a
+        // left neighbour in this tile's row is in this pixel's local tree.
+        // So, as in the local phase, a run of this row needs one union per
+        // run above it that it touches (runs above that straddle a tile
+        // border are joined by the column rules of the tiles above).
+        const bool aC = gload(F + p - Wu) != 0u;
+        const bool aL = x > 0 && gload(F + p - Wu - 1) != 0u;
+        const bool aR = x + 1 < W && gload(F + p - Wu + 1) != 0u;
+        const bool left = x > x0 && gload(F + p - 1) != 0u;
+        if (CONN == 4) {
+            if (aC && !(left && aL)) gunion(F, p, p - Wu);
+        } else {
+            if (!left) {
+                if (aL) gunion(F, p, p - Wu - 1);
+                if (aC && !aL) gunion(F, p, p - Wu);
+            }
+            if (aR && !aC) gunion(F, p, p - Wu + 1);
+        }
+    } else if (CONN == 8 && y > 0) {
+        if (first_col && x > 0 && gload(F + p - Wu - 1) != 0u) gunion(F, p, p - Wu - 1);
+        if (last_col && x + 1 < W && gload(F + p - Wu + 1) != 0u) gunion(F, p, p - Wu + 1);
     }
 }
 
