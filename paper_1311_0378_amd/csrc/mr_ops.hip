@@ -92,6 +92,14 @@ __device__ __forceinline__ void pass_pixel(const T *f, const T *r, T *m, uint8_t
     }
 }
 
+// 0xFF in every byte of x that is nonzero, 0 in the others: the low seven
+// bits of a byte plus 0x7F carry into its top bit iff they are nonzero, and
+// the byte's own top bit covers the rest; no carry leaves a byte.
+__device__ __forceinline__ uint32_t bytes_nonzero(uint32_t x) {
+    const uint32_t top = (((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
+    return (top >> 7) * 0xFFu;
+}
+
 template <typename T, int KIND, bool WORDS>
 __global__ __launch_bounds__(256) void k_stream_pass(const T *f, const T *r, T *m,
                                                      uint8_t *__restrict__ o, int64_t H,
@@ -105,7 +113,19 @@ __global__ __launch_bounds__(256) void k_stream_pass(const T *f, const T *r, T *
          it += (int64_t)gridDim.x * blockDim.x) {
         const int64_t y = it / wpr, x0 = (it - y * wpr) * EPW;
         const int64_t i0 = y * pitch + x0, o0 = y * out_pitch + x0;
-        if (WORDS && x0 + EPW <= W) {
+        if (WORDS && sizeof(T) == 1 && KIND != P_MARKER && x0 + EPW <= W) {
+            // uint8 dome and maxima on whole dwords: r <= f in every byte, so
+            // f - r as 32-bit words subtracts byte by byte without borrows
+            const uint4 wf = *(const uint4 *)(f + i0), wr = *(const uint4 *)(r + i0);
+            uint4 d = {wf.x - wr.x, wf.y - wr.y, wf.z - wr.z, wf.w - wr.w};
+            if (KIND == P_DOME) {
+                *(uint4 *)(m + i0) = d;
+            } else {
+                *(uint4 *)(o + o0) = all_min ? uint4{~0u, ~0u, ~0u, ~0u}
+                                             : uint4{bytes_nonzero(d.x), bytes_nonzero(d.y),
+                                                     bytes_nonzero(d.z), bytes_nonzero(d.w)};
+            }
+        } else if (WORDS && x0 + EPW <= W) {
             const Word<T> wf = *(const Word<T> *)(f + i0);
             if (KIND == P_MARKER) {
                 Word<T> wm;
