@@ -328,36 +328,42 @@ template <bool MIN>
 __global__ __launch_bounds__(DK_THREADS) void k_disk13(const uint8_t *__restrict__ in,
                                                        uint8_t *__restrict__ out, int64_t H,
                                                        int64_t W, int64_t pitch, int64_t tiles_x) {
-    __shared__ uint32_t st[DK_ROWS * (DK_SW / 4)];
+    // the staged rows of one step of 13 (the accumulator ring's period)
+    __shared__ uint32_t st[13 * (DK_SW / 4)];
     const uint32_t ident = MIN ? 0xFFu : 0u;
     const uint32_t ident4 = MIN ? 0xFFFFFFFFu : 0u;
     const int64_t tile = blockIdx.x;
     const int64_t ty = tile / tiles_x, tx = tile - ty * tiles_x;
     const int64_t y0 = ty * DK_TH, x0 = tx * DK_TW;
-    // stage rows y0-6 .. y0+DK_TH+5, columns x0-8 .. x0+DK_TW+7, one word per
-    // lane and step; a word is gathered byte by byte at the image edges
     constexpr int WPR = DK_SW / 4; // words per staged row
-    for (int i = threadIdx.x; i < DK_ROWS * WPR; i += DK_THREADS) {
-        const int r = i / WPR, wc = i - r * WPR;
-        const int64_t gy = y0 - 6 + r, gx = x0 - 8 + 4 * (int64_t)wc;
-        uint32_t v = ident4;
-        if (gy >= 0 && gy < H) {
-            const uint8_t *row = in + gy * pitch;
-            if (gx >= 0 && gx + 3 < W && (((uintptr_t)(row + gx)) & 3) == 0) {
-                v = *(const uint32_t *)(row + gx);
-            } else {
-                v = 0u;
+    // stage rows y0-6+r0 .. y0-6+r0+12, columns x0-8 .. x0+DK_TW+7, one word
+    // per lane and step; a word is gathered byte by byte at the image edges.
+    // Staging 13 rows at a time (instead of the tile's 76) keeps a
+    // workgroup's LDS at 7 KB, so that LDS no longer limits the waves per
+    // SIMD.
+    auto stage = [&](int r0) {
+        for (int i = threadIdx.x; i < 13 * WPR; i += DK_THREADS) {
+            const int rl = i / WPR, wc = i - rl * WPR;
+            if (r0 + rl >= DK_ROWS) break;
+            const int64_t gy = y0 - 6 + r0 + rl, gx = x0 - 8 + 4 * (int64_t)wc;
+            uint32_t v = ident4;
+            if (gy >= 0 && gy < H) {
+                const uint8_t *row = in + gy * pitch;
+                if (gx >= 0 && gx + 3 < W && (((uintptr_t)(row + gx)) & 3) == 0) {
+                    v = *(const uint32_t *)(row + gx);
+                } else {
+                    v = 0u;
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int64_t x = gx + b;
-                    const uint32_t byte = (x >= 0 && x < W) ? row[x] : ident;
-                    v |= byte << (8 * b);
+                    for (int b = 0; b < 4; ++b) {
+                        const int64_t x = gx + b;
+                        const uint32_t byte = (x >= 0 && x < W) ? row[x] : ident;
+                        v |= byte << (8 * b);
+                    }
                 }
             }
+            st[i] = v;
         }
-        st[i] = v;
-    }
-    __syncthreads();
+    };
 
     const int lx = threadIdx.x * 4; // first of this lane's columns, tile-relative
     // 13 accumulators per column in a ring: output row o (tile-relative) lives
@@ -372,6 +378,9 @@ __global__ __launch_bounds__(DK_THREADS) void k_disk13(const uint8_t *__restrict
     constexpr int HWID[7] = {6, 5, 5, 5, 4, 3, 0}; // half-width of the disk row |dy|
 #pragma unroll 1
     for (int r0 = 0; r0 < DK_ROWS; r0 += 13) {
+        __syncthreads(); // the previous step's reads of the stage are done
+        stage(r0);
+        __syncthreads();
 #pragma unroll
         for (int rr = 0; rr < 13; ++rr) {
             const int r = r0 + rr;
@@ -379,7 +388,7 @@ __global__ __launch_bounds__(DK_THREADS) void k_disk13(const uint8_t *__restrict
             // staged row r starts 8 columns left of the tile, so column
             // lx - 6 + j (j = 0..15) is staged byte lx + 2 + j: the 5 words
             // from staged byte lx hold them
-            const uint32_t *w = st + r * WPR + (lx >> 2);
+            const uint32_t *w = st + rr * WPR + (lx >> 2);
             uint32_t wd[5];
 #pragma unroll
             for (int k = 0; k < 5; ++k) wd[k] = w[k];
