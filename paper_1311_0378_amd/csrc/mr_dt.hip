@@ -124,29 +124,59 @@ __global__ __launch_bounds__(64) void k_dt_round(const uint8_t *__restrict__ img
     const int64_t y_first = gy0 < 0 ? 0 : gy0;
     const uint8_t *ib = img + y_first * ipitch;
     const int32_t *db = dist + y_first * dpitch;
+    if (gy0 >= 0 && gy0 + DS <= H) {
+        // every row inside the image: the row offset lives in a vector
+        // register, stepped by one pitch per row, so that the 64 row offsets
+        // are not all held (in scalar registers, which spill)
+        const uint32_t pitch = (uint32_t)(FIRST ? ipitch : dpitch);
+        uint32_t off = (uint32_t)xc;
 #pragma unroll
-    for (int r = 0; r < DS; ++r) {
-        const int64_t gy = gy0 + r;
-        const int64_t yc = gy < 0 ? 0 : (gy > H - 1 ? H - 1 : gy);
-        const uint32_t rel = (uint32_t)(yc - y_first);
-        D[r] = FIRST ? (uint32_t)ib[rel * (uint32_t)ipitch + (uint32_t)xc]
-                     : (uint32_t)db[rel * (uint32_t)dpitch + (uint32_t)xc];
+        for (int r = 0; r < DS; ++r) {
+            asm volatile("" : "+v"(off));
+            D[r] = FIRST ? (uint32_t)ib[off] : (uint32_t)db[off];
+            off += pitch;
+        }
+    } else {
+        // the top or bottom tile row: rows outside the image read the
+        // nearest row inside it (masked below); the clamp is vector
+        // arithmetic for the same reason
+        int32_t g0 = (int32_t)(gy0 - y_first), hm = (int32_t)(H - 1 - y_first);
+        asm volatile("" : "+v"(g0), "+v"(hm));
+        const uint32_t pitch = (uint32_t)(FIRST ? ipitch : dpitch);
+#pragma unroll
+        for (int r = 0; r < DS; ++r) {
+            const int32_t rel = min(max(g0 + r, 0), hm);
+            const uint32_t off = (uint32_t)rel * pitch + (uint32_t)xc;
+            D[r] = FIRST ? (uint32_t)ib[off] : (uint32_t)db[off];
+        }
     }
     asm volatile("" ::: "memory");
 #pragma unroll
     for (int r = 0; r < DS; ++r) asm volatile("" : "+v"(D[r]));
+    // rows r_lo .. r_hi of the tile lie in the image; compared in vector
+    // registers (as 64 scalar conditions they would be held and spilled)
+    uint32_t r_lo = (uint32_t)(gy0 < 0 ? -gy0 : 0);
+    uint32_t r_hi = (uint32_t)(H - 1 - gy0 < DS - 1 ? H - 1 - gy0 : DS - 1);
+    asm volatile("" : "+v"(r_lo), "+v"(r_hi));
+    // (0/1 arithmetic rather than comparisons: 64 rows of comparison masks
+    // are held in scalar registers and spill)
+    const uint32_t xin1 = xin ? 1u : 0u;
+    uint32_t bg_seen = 0, fg_seen = 0;
 #pragma unroll
     for (int r = 0; r < DS; ++r) {
-        const int64_t gy = gy0 + r;
-        const bool ok = xin && gy >= 0 && gy < H;
+        // 1 for a row inside the image: neither r - r_lo nor r_hi - r is negative
+        const uint32_t ok = xin1 & ~(((uint32_t)r - r_lo) | (r_hi - (uint32_t)r)) >> 31;
         if (FIRST) {
-            any_bg |= ok && D[r] == 0;
-            any_fg |= ok && D[r] != 0;
-            D[r] = ok && D[r] == 0 ? 0u : INF;
+            const uint32_t bg = ok & ((D[r] - 1u) >> 31); // pixel 0 (an 8-bit value)
+            bg_seen |= bg;
+            fg_seen |= ok & ~bg;
+            D[r] = INF & (bg - 1u); // 0 for background, else unreached
         } else {
             D[r] = ok ? D[r] : INF;
         }
     }
+    any_bg = bg_seen != 0;
+    any_fg = fg_seen != 0;
     if (FIRST) {
         // (one atomic per wave at most, and none once some wave has set it:
         // tens of thousands of them on the one word serialise)
@@ -156,9 +186,14 @@ __global__ __launch_bounds__(64) void k_dt_round(const uint8_t *__restrict__ img
         // a tile whose pixels (halo included) are all background is final
         if (__ballot(any_fg) == 0) {
             if (in_lane && gx < W) {
+                int32_t *drow = dist + (gy0 + 1) * dpitch;
+                uint32_t off = (uint32_t)gx;
 #pragma unroll
-                for (int r = 1; r < DS - 1; ++r)
-                    if (gy0 + r < H) dist[(gy0 + r) * dpitch + gx] = 0;
+                for (int r = 1; r < DS - 1; ++r) {
+                    asm volatile("" : "+v"(off));
+                    if ((uint32_t)r <= r_hi) drow[off] = 0;
+                    off += (uint32_t)dpitch;
+                }
             }
             return;
         }
@@ -172,10 +207,20 @@ __global__ __launch_bounds__(64) void k_dt_round(const uint8_t *__restrict__ img
     const bool col_ok = in_lane && xin;
     const int64_t rows_left = H - gy0 - 1; // interior rows inside the image
     const int last_row = rows_left < DS - 2 ? (int)rows_left : DS - 2;
+    // (the bottom tile row compares each row with last_row in vector
+    // registers: as scalar conditions the compiler keeps all 62 of them live
+    // across the sweep loop, and they spill)
     auto vsum = [&]() {
         uint64_t sm = 0;
+        if (last_row == DS - 2) {
 #pragma unroll
-        for (int r = 1; r < DS - 1; ++r) sm += r <= last_row ? D[r] : 0u;
+            for (int r = 1; r < DS - 1; ++r) sm += D[r];
+        } else {
+            uint32_t lr = (uint32_t)last_row;
+            asm volatile("" : "+v"(lr));
+#pragma unroll
+            for (int r = 1; r < DS - 1; ++r) sm += (uint32_t)r <= lr ? D[r] : 0u;
+        }
         return col_ok ? sm : 0ull;
     };
     // border rows as loaded (what the neighbours' halos hold), and each
@@ -212,10 +257,14 @@ __global__ __launch_bounds__(64) void k_dt_round(const uint8_t *__restrict__ img
     }
     if (changed || FIRST) {
         if (in_lane && gx < W) {
+            // rows gy0 + 1 .. are all >= 0; only the bottom may leave the image
+            int32_t *drow = dist + (gy0 + 1) * dpitch;
+            uint32_t off = (uint32_t)gx;
 #pragma unroll
             for (int r = 1; r < DS - 1; ++r) {
-                const int64_t gy = gy0 + r;
-                if (gy < H) dist[gy * dpitch + gx] = (int32_t)D[r];
+                asm volatile("" : "+v"(off));
+                if (r <= last_row) drow[off] = (int32_t)D[r];
+                off += (uint32_t)dpitch;
             }
         }
     }
