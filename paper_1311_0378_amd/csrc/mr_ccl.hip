@@ -354,6 +354,46 @@ __global__ __launch_bounds__(256) void k_area_count(const int32_t *__restrict__ 
     }
 }
 
+// The same count on rows of whole 16-byte words (W and pitch multiples of 4,
+// 16-byte aligned plane): a lane takes 4 labels, a wave's chunk is 64 words.
+// Run heads are marked per label; a head's run ends at the next head in its
+// lane, else at the first head of the next lane that has one, else at the
+// chunk's end.
+__global__ __launch_bounds__(256) void k_area_count4(const int32_t *__restrict__ labels,
+                                                     int64_t H, int64_t W, int64_t pitch,
+                                                     int32_t *__restrict__ area) {
+    const uint32_t N = (uint32_t)(H * W), NQ = (uint32_t)(H * (W / 4));
+    const int lane = threadIdx.x & 63;
+    const uint32_t wave = blockIdx.x * 4u + (threadIdx.x >> 6), waves = gridDim.x * 4u;
+    const uint32_t stride = waves * 64u;
+    for (PixelWalk w(H, W / 4, wave * 64u + lane, stride); w.i - lane < NQ; w.next(stride)) {
+        const bool in = w.ok();
+        int4 q = {0, 0, 0, 0};
+        if (in) q = *(const int4 *)(labels + (int64_t)w.y * pitch + 4 * (int64_t)w.x);
+        const int32_t prev = __shfl_up(q.w, 1);
+        uint32_t hm = 0; // bit j: label j of this lane starts a run
+        if (in) {
+            hm = (lane == 0 || w.x == 0 || q.x != prev) ? 1u : 0u;
+            hm |= (q.y != q.x ? 2u : 0u) | (q.z != q.y ? 4u : 0u) | (q.w != q.z ? 8u : 0u);
+        }
+        const int first = hm ? __builtin_ctz(hm) : 4;
+        const uint64_t with_head = __ballot(hm != 0);
+        const uint64_t valid = __ballot(in);
+        const uint64_t later = lane == 63 ? 0ull : (with_head >> (lane + 1)) << (lane + 1);
+        const int ln = later ? __builtin_ctzll(later) : lane;
+        const int fn = __shfl(first, ln);
+        const int next = later ? 4 * ln + fn : 4 * (64 - __builtin_clzll(valid));
+        const int32_t lv[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (!((hm >> j) & 1u)) continue;
+            const uint32_t rest = hm >> (j + 1);
+            const int end = rest ? 4 * lane + j + 1 + __builtin_ctz(rest) : next;
+            if (lv[j] > 0 && (uint32_t)lv[j] <= N) atomicAdd(area + lv[j], end - (4 * lane + j));
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_area_filter(int32_t *__restrict__ labels, int64_t H,
                                                      int64_t W, int64_t pitch,
                                                      const int32_t *__restrict__ area,
@@ -367,6 +407,29 @@ __global__ __launch_bounds__(256) void k_area_filter(int32_t *__restrict__ label
             const int64_t a = area[l];
             if (a < lo || a > hi) *p = 0;
         }
+    }
+}
+
+// The same on rows of whole 16-byte words (W and pitch multiples of 4,
+// 16-byte aligned plane): a lane takes 4 labels at once, so their 4 counter
+// reads are in flight together, and writes the word back only if it cleared
+// one of them.
+__global__ __launch_bounds__(256) void k_area_filter4(int32_t *__restrict__ labels, int64_t H,
+                                                      int64_t W, int64_t pitch,
+                                                      const int32_t *__restrict__ area,
+                                                      int64_t lo, int64_t hi) {
+    const int64_t N = H * W;
+    const uint32_t stride = gridDim.x * 256u;
+    auto keep = [&](int32_t l) -> int32_t {
+        if (l <= 0 || (int64_t)l > N) return l;
+        const int64_t a = area[l];
+        return a < lo || a > hi ? 0 : l;
+    };
+    for (PixelWalk w(H, W / 4, blockIdx.x * 256u + threadIdx.x, stride); w.ok(); w.next(stride)) {
+        int4 *p = (int4 *)(labels + (int64_t)w.y * pitch + 4 * (int64_t)w.x);
+        const int4 l = *p;
+        const int4 o = {keep(l.x), keep(l.y), keep(l.z), keep(l.w)};
+        if (o.x != l.x || o.y != l.y || o.z != l.z || o.w != l.w) *p = o;
     }
 }
 
@@ -452,11 +515,19 @@ int mr_area_threshold(void *labels_inout, int64_t H, int64_t W, int64_t pitch, i
     hipStream_t s = (hipStream_t)stream;
     int32_t *area = (int32_t *)ws;
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(H * W + 1)), dim3(256), 0, s, area, H * W + 1, 0);
-    hipLaunchKernelGGL(k_area_count, dim3(grid_for(H * W)), dim3(256), 0, s,
-                       (const int32_t *)labels_inout, H, W, pitch, area);
-    hipLaunchKernelGGL(k_area_filter, dim3(grid_for(H * W)), dim3(256), 0, s,
-                       (int32_t *)labels_inout, H, W, pitch, (const int32_t *)area, min_area,
-                       max_area);
+    if (W % 4 == 0 && pitch % 4 == 0 && (uintptr_t)labels_inout % 16 == 0) {
+        hipLaunchKernelGGL(k_area_count4, dim3(grid_for(H * W / 4)), dim3(256), 0, s,
+                           (const int32_t *)labels_inout, H, W, pitch, area);
+        hipLaunchKernelGGL(k_area_filter4, dim3(grid_for(H * W / 4)), dim3(256), 0, s,
+                           (int32_t *)labels_inout, H, W, pitch, (const int32_t *)area, min_area,
+                           max_area);
+    } else {
+        hipLaunchKernelGGL(k_area_count, dim3(grid_for(H * W)), dim3(256), 0, s,
+                           (const int32_t *)labels_inout, H, W, pitch, area);
+        hipLaunchKernelGGL(k_area_filter, dim3(grid_for(H * W)), dim3(256), 0, s,
+                           (int32_t *)labels_inout, H, W, pitch, (const int32_t *)area,
+                           min_area, max_area);
+    }
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? MR_OK : chip(e, "area threshold");
 }

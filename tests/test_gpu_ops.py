@@ -224,12 +224,14 @@ def test_ccl_area_synthetic_4096(conn):
         assert np.array_equal(got_areas, areas.astype(np.int32))
 
 
-def test_area_threshold_random_labels():
-    rng = np.random.default_rng(5)
-    H, W = 97, 131
-    lab = rng.integers(0, 40, (H, W)).astype(np.int32)
+@pytest.mark.parametrize("H,W,pad", [(97, 131, 3), (64, 128, 4), (33, 200, 0), (5, 4, 0)])
+def test_area_threshold_random_labels(H, W, pad):
+    # (widths and pitches that are multiples of 4 take the 16-byte word path)
+    rng = np.random.default_rng(5 + W)
+    lab = rng.integers(0, min(40, H * W + 1), (H, W)).astype(np.int32)
     lab[rng.random((H, W)) < 0.3] = 0
-    for lo, hi in [(0, 10**9), (60, 90), (100, 100), (5, 4)]:
-        d = to_dev(lab, pad=3)
+    lab[0, 0] = H * W  # the largest label a plane can hold
+    for lo, hi in [(0, 10**9), (60, 90), (100, 100), (5, 4), (1, 1)]:
+        d = to_dev(lab, pad=pad)
         ops.area_threshold(d, lo, hi)
         check(d.cpu().numpy(), oracle.area_threshold(lab, lo, hi)[0], f"[{lo},{hi}]: ")
