@@ -316,6 +316,20 @@ __global__ __launch_bounds__(256) void k_ccl_flatten(int64_t H, int64_t W, uint3
     }
 }
 
+// In place on a plane of whole 16-byte words (H * W a multiple of 4,
+// 16-byte aligned): a lane takes 4 entries, walks each foreground one to its
+// root, and writes the word back only if an entry changed. A reader of an
+// entry that another lane rewrites finds either its old parent or its root,
+// and both lead to the same root.
+__global__ __launch_bounds__(256) void k_ccl_flatten4(int64_t n4, uint32_t *F) {
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n4; i += (int64_t)gridDim.x * 256) {
+        const uint4 v = ((const uint4 *)F)[i];
+        const uint4 o = {v.x ? gfind(F, v.x - 1u) + 1u : 0u, v.y ? gfind(F, v.y - 1u) + 1u : 0u,
+                         v.z ? gfind(F, v.z - 1u) + 1u : 0u, v.w ? gfind(F, v.w - 1u) + 1u : 0u};
+        if (o.x != v.x || o.y != v.y || o.z != v.z || o.w != v.w) ((uint4 *)F)[i] = o;
+    }
+}
+
 // --------------------------------------------------------------- area phase
 
 __global__ __launch_bounds__(256) void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
@@ -484,7 +498,10 @@ int mr_ccl(const void *img, void *labels, int64_t H, int64_t W, int64_t pitch,
                            (const uint8_t *)img, H, W, pitch, tx, F);
         hipLaunchKernelGGL(k_ccl_merge<4>, dim3(tiles), dim3(128), 0, s, H, W, tx, F);
     }
-    if (in_place)
+    if (in_place && (H * W) % 4 == 0 && (uintptr_t)labels % 16 == 0)
+        hipLaunchKernelGGL(k_ccl_flatten4, dim3(grid_for(H * W / 4)), dim3(256), 0, s,
+                           H * W / 4, F);
+    else if (in_place)
         hipLaunchKernelGGL(k_ccl_flatten<true>, dim3(grid_for(H * W)), dim3(256), 0, s, H, W, F,
                            (int32_t *)labels, label_pitch);
     else
