@@ -312,6 +312,8 @@ constexpr int DK_TH = 64;                // output rows per workgroup
 constexpr int DK_ROWS = DK_TH + 12;      // staged input rows
 constexpr int DK_SW = DK_TW + 16;        // staged row bytes: 8 left, 8 right (6 used)
 
+typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+
 template <bool MIN> __device__ __forceinline__ uint32_t ext(uint32_t a, uint32_t b) {
     return MIN ? min(a, b) : max(a, b);
 }
@@ -370,11 +372,13 @@ __global__ __launch_bounds__(DK_THREADS) void k_disk13(const uint8_t *__restrict
     // in slot o mod 13. Input row r reaches output rows r - 12 .. r (offsets
     // dy = 6 .. -6), which sit in slots (r + 1 + k) mod 13, k = 0..12; the
     // rows are walked 13 at a time so that every slot index is a constant.
-    uint32_t acc[13][4];
+    // Two columns per accumulator, one in each 16-bit half (the pixels are
+    // 8-bit), folded with packed 16-bit extrema: half the fold instructions
+    // and accumulator registers.
+    const u16x2 identp = {(uint16_t)ident, (uint16_t)ident};
+    u16x2 acc[13][2];
 #pragma unroll
-    for (int k = 0; k < 13; ++k)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[k][c] = ident;
+    for (int k = 0; k < 13; ++k) acc[k][0] = acc[k][1] = identp;
     constexpr int HWID[7] = {6, 5, 5, 5, 4, 3, 0}; // half-width of the disk row |dy|
 #pragma unroll 1
     for (int r0 = 0; r0 < DK_ROWS; r0 += 13) {
@@ -420,11 +424,15 @@ __global__ __launch_bounds__(DK_THREADS) void k_disk13(const uint8_t *__restrict
                 const int hw = HWID[ady];
                 const int slot = (rr + 1 + k) % 13;
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const int j = c + 6;
-                    const uint32_t v = hw == 6 ? e6[c] : hw == 5 ? e5[j] : hw == 4 ? e4[j]
-                                     : hw == 3 ? e3[j] : b[j];
-                    acc[slot][c] = ext<MIN>(acc[slot][c], v);
+                for (int h = 0; h < 2; ++h) {
+                    auto pick = [&](int c) -> uint32_t {
+                        const int j = c + 6;
+                        return hw == 6 ? e6[c] : hw == 5 ? e5[j] : hw == 4 ? e4[j]
+                             : hw == 3 ? e3[j] : b[j];
+                    };
+                    const u16x2 v = {(uint16_t)pick(2 * h), (uint16_t)pick(2 * h + 1)};
+                    acc[slot][h] = MIN ? __builtin_elementwise_min(acc[slot][h], v)
+                                       : __builtin_elementwise_max(acc[slot][h], v);
                 }
             }
             // output row r - 12 has all 13 of its input rows: store it, and
@@ -434,17 +442,18 @@ __global__ __launch_bounds__(DK_THREADS) void k_disk13(const uint8_t *__restrict
             if (r >= 12 && oy < H) {
                 const int64_t ox = x0 + lx;
                 uint8_t *orow = out + oy * pitch;
+                const uint32_t o4 = (uint32_t)acc[done][0].x | ((uint32_t)acc[done][0].y << 8) |
+                                    ((uint32_t)acc[done][1].x << 16) |
+                                    ((uint32_t)acc[done][1].y << 24);
                 if (ox + 3 < W && (((uintptr_t)(orow + ox)) & 3) == 0) {
-                    *(uint32_t *)(orow + ox) = acc[done][0] | (acc[done][1] << 8) |
-                                               (acc[done][2] << 16) | (acc[done][3] << 24);
+                    *(uint32_t *)(orow + ox) = o4;
                 } else {
 #pragma unroll
                     for (int c = 0; c < 4; ++c)
-                        if (ox + c < W) orow[ox + c] = (uint8_t)acc[done][c];
+                        if (ox + c < W) orow[ox + c] = (uint8_t)(o4 >> (8 * c));
                 }
             }
-#pragma unroll
-            for (int c = 0; c < 4; ++c) acc[done][c] = ident;
+            acc[done][0] = acc[done][1] = identp;
         }
     }
 }
