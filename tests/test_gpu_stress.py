@@ -30,7 +30,7 @@ if not torch.cuda.is_available():
 from gpu_util import DEV, first_mismatch  # noqa: E402
 from paper_1311_0378_amd import mrecon  # noqa: E402
 
-# rounds before the queue phase / tile queue, sweep caps, grid sizes
+# rounds before the queue phase / tile queue, sweep caps, grid sizes, first-round caps
 STRESS_TUNES = [
     None,
     dict(sweep_rounds=1, max_sweeps=1),
@@ -44,6 +44,10 @@ STRESS_TUNES = [
     dict(sweep_rounds=-1, tail_rounds=8),
     dict(sweep_rounds=-1, tail_rounds=0),
     dict(sweep_rounds=-1, tail_rounds=0, converge_rounds=2),
+    # first-round caps (the default is 1): full first visits, and two
+    # iterations with the tile queue right after
+    dict(sweep_rounds=-1, tail_rounds=8, first_sweeps=16),
+    dict(sweep_rounds=-1, tail_rounds=2, first_sweeps=2, max_sweeps=3),
 ]
 
 
