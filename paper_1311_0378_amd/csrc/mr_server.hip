@@ -71,6 +71,21 @@ struct RangeAlloc {
         }
         return false;
     }
+    // First fit inside [lo, hi) only.
+    bool alloc_in(size_t n, size_t lo, size_t hi, size_t &off) {
+        n = up(std::max<size_t>(n, 1), align);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            const size_t a = std::max(it->first, lo), e = std::min(it->first + it->second, hi);
+            if (a >= e || e - a < n) continue;
+            const size_t f = it->first, len = it->second;
+            free_.erase(it);
+            if (a > f) free_[f] = a - f;
+            if (f + len > a + n) free_[a + n] = f + len - (a + n);
+            off = a;
+            return true;
+        }
+        return false;
+    }
     void release(size_t off, size_t n) {
         n = up(std::max<size_t>(n, 1), align);
         auto it = free_.emplace(off, n).first;
@@ -102,6 +117,7 @@ struct Job {
     size_t plane;      // bytes of one plane
     size_t mem_off, mem_len;
     int64_t tile_base, n_tiles;
+    int band;
     uint32_t first_round;
     ImgDesc d;
 };
@@ -111,6 +127,7 @@ struct Returning {
     int32_t slot;
     size_t mem_off, mem_len;
     int64_t tile_base, n_tiles;
+    int band;
 };
 
 } // namespace
@@ -133,6 +150,7 @@ struct mr_server {
     size_t data_off = 0;
     // host state
     RangeAlloc mem, tiles;
+    int64_t band_tiles[NBANDS] = {}; // resident tiles whose ids start in each band
     std::vector<int32_t> free_slots;
     std::map<int32_t, Job> resident;  // slot -> job still working
     std::deque<Returning> returning;  // finished, result copy in flight
@@ -187,6 +205,34 @@ int hip_err(hipError_t e, const char *what) {
 // Moves returning jobs whose result copies have completed to `done`, in
 // order (the download stream completes them in order), and gives their
 // arena space, tile ids and slots back; with `wait`, all of them.
+// The tile rounds split the tile-id space into NBANDS bands (band b: ids
+// b * n / NBANDS up to (b + 1) * n / NBANDS) and serve band b with the
+// workgroups of one die. A first fit over the whole space would put every
+// resident job in the first band or two and leave the other dies' workgroups
+// idle, so a job's tiles go into the band with the fewest resident tiles
+// that has room, and anywhere only if no band has.
+int64_t band_start(int64_t n, int b) { return (int64_t)b * n / NBANDS; }
+
+int band_of_tile(int64_t n, int64_t t) {
+    int b = 0;
+    while (b + 1 < NBANDS && t >= band_start(n, b + 1)) ++b;
+    return b;
+}
+
+bool alloc_tiles(mr_server *s, int64_t n, size_t &to) {
+    int order[NBANDS];
+    for (int b = 0; b < NBANDS; ++b) order[b] = b;
+    std::stable_sort(order, order + NBANDS,
+                     [&](int a, int b) { return s->band_tiles[a] < s->band_tiles[b]; });
+    for (int k = 0; k < NBANDS; ++k) {
+        const int b = order[k];
+        if (s->tiles.alloc_in((size_t)n, (size_t)band_start(s->n_tiles, b),
+                              (size_t)band_start(s->n_tiles, b + 1), to))
+            return true;
+    }
+    return s->tiles.alloc((size_t)n, to);
+}
+
 int collect(mr_server *s, bool wait) {
     while (!s->returning.empty()) {
         const Returning r = s->returning.front();
@@ -196,6 +242,7 @@ int collect(mr_server *s, bool wait) {
         s->done.push_back(r.id);
         s->mem.release(r.mem_off, r.mem_len);
         s->tiles.release((size_t)r.tile_base, (size_t)r.n_tiles);
+        s->band_tiles[r.band] -= r.n_tiles;
         s->free_slots.push_back(r.slot);
         s->returning.pop_front();
     }
@@ -311,10 +358,12 @@ int mr_server_submit(mr_server *s, const mr_job *job, uint64_t *id) {
     j.n_tiles = job_tiles(*job);
     size_t mo = 0, to = 0;
     if (!s->mem.alloc(need, mo)) return sfail(MR_EAGAIN, "no room in the arena now");
-    if (!s->tiles.alloc((size_t)j.n_tiles, to)) {
+    if (!alloc_tiles(s, j.n_tiles, to)) {
         s->mem.release(mo, need);
         return sfail(MR_EAGAIN, "no free tile ids now");
     }
+    j.band = band_of_tile(s->n_tiles, (int64_t)to);
+    s->band_tiles[j.band] += j.n_tiles;
     j.mem_off = mo;
     j.mem_len = need;
     j.tile_base = (int64_t)to;
@@ -362,6 +411,7 @@ int mr_server_submit(mr_server *s, const mr_job *job, uint64_t *id) {
         // an unknown state, and the error is reported
         s->mem.release(mo, need);
         s->tiles.release(to, (size_t)j.n_tiles);
+        s->band_tiles[j.band] -= j.n_tiles;
         return hip_err(e, "admit");
     }
     s->free_slots.pop_back();
@@ -445,7 +495,7 @@ int mr_server_step(mr_server *s) {
                 (e = hipEventRecord(s->ev_out[slot], s->down)) != hipSuccess)
                 return hip_err(e, "result copy");
             s->returning.push_back(
-                Returning{j.id, slot, j.mem_off, j.mem_len, j.tile_base, j.n_tiles});
+                Returning{j.id, slot, j.mem_off, j.mem_len, j.tile_base, j.n_tiles, j.band});
             s->resident.erase(slot);
         }
     }
