@@ -123,6 +123,60 @@ def load_traffic(workload_key: str, path: str):
     return rec.get("hbm_bytes_per_launch")
 
 
+def summarize_served_trace(trace_dir: str) -> None:
+    """Busy time per server pass from a rocprofv3 kernel + memory-copy trace
+    of the served leg. The passes are the stretches of k_server_* launches
+    (gaps over 50 ms split them); for each: the window, the host<->device
+    copies (memory-copy trace; device-to-device copies are kernels), the
+    tile-round launches and the union of all activity. Prints one JSON line."""
+    import csv
+
+    def rows(name):
+        path = os.path.join(trace_dir, name)
+        return list(csv.DictReader(open(path))) if os.path.exists(path) else []
+
+    def union_ms(iv):
+        tot, cur = 0, None
+        for a, b in sorted(iv):
+            if cur is None or a > cur[1]:
+                if cur:
+                    tot += cur[1] - cur[0]
+                cur = [a, b]
+            else:
+                cur[1] = max(cur[1], b)
+        if cur:
+            tot += cur[1] - cur[0]
+        return round(tot / 1e6, 2)
+
+    span = lambda r: (int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
+    K, M = rows("run_kernel_trace.csv"), rows("run_memory_copy_trace.csv")
+    starts = sorted(span(r)[0] for r in K if "k_server_" in r["Kernel_Name"])
+    if not starts:
+        sys.exit(f"no k_server_* launches in {trace_dir}/run_kernel_trace.csv")
+    passes, cur = [], [starts[0]]
+    for t in starts[1:]:
+        if t - cur[-1] > 50e6:
+            passes.append(cur)
+            cur = [t]
+        else:
+            cur.append(t)
+    passes.append(cur)
+    out = []
+    for p in passes:
+        lo, hi = p[0], p[-1]
+        k = [r for r in K if lo <= span(r)[0] <= hi]
+        m = [r for r in M if lo <= span(r)[0] <= hi]
+        rounds = [r for r in k if "k_tile_round" in r["Kernel_Name"]]
+        out.append({"window_ms": round((hi - lo) / 1e6, 1), "host_copies": len(m),
+                    "host_copy_busy_ms": union_ms([span(r) for r in m]),
+                    "round_launches": len(rounds),
+                    "round_busy_ms": union_ms([span(r) for r in rounds]),
+                    "round_avg_us": round(sum(b - a for a, b in map(span, rounds))
+                                          / max(1, len(rounds)) / 1e3, 1),
+                    "any_busy_ms": union_ms([span(r) for r in k + m])})
+    print(json.dumps({"served_trace": out}))
+
+
 def summarize_traffic(fetch_csv: str, write_csv: str, args) -> None:
     """HBM traffic per tile-round launch: the FETCH_SIZE and WRITE_SIZE
     counters (KiB per dispatch) of the tile-round dispatches, each scaled by
@@ -1015,8 +1069,14 @@ def main():
                     help="turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE) of a "
                          "--calibrate-copy run into "
                          "profiles/tile_round_traffic_<size>_<dtype>_conn<conn>.json and exit")
+    ap.add_argument("--served-trace", metavar="TRACE_DIR",
+                    help="summarise a rocprofv3 --kernel-trace --memory-copy-trace run of the "
+                         "served leg (busy time per server pass), print one JSON line and exit")
     args = ap.parse_args()
 
+    if args.served_trace:
+        summarize_served_trace(args.served_trace)
+        return
     if args.traffic_from:
         summarize_traffic(*args.traffic_from, args)
         return
