@@ -330,7 +330,7 @@ int run_sequence(int tbytes, int conn, const Imgs &imgs, const Layout &L, void *
     {
         // The first round's visits have their own sweep cap: their halos
         // are mostly stale (the neighbours have not been visited yet), and
-        // nearly every tile is visited again in round 2.
+        // nearly every tile is visited again in the second tile round.
         LaunchTimer lt(s, MR_K_TILE_ROUND, (int32_t)round);
         e = launch_tile_round(tbytes, conn, imgs, L.n_tiles, flags, lists, ctrl, round,
                               tn.first_sweeps, grid, s, op_all);
