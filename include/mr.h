@@ -118,7 +118,12 @@ typedef struct {
                              iteration = down, up, right and left sweeps) */
 } mr_counters;
 
-/* Fills *out with the default knobs. */
+/* Fills *out with the default knobs. A set environment variable
+ * MR_TUNE_SWEEP_ROUNDS, MR_TUNE_MAX_SWEEPS, MR_TUNE_PERSISTENT_BLOCKS,
+ * MR_TUNE_CONVERGE_ROUNDS, MR_TUNE_TAIL_ROUNDS or MR_TUNE_FIRST_SWEEPS
+ * replaces that field's default when it is a whole number in the field's
+ * valid range (it is ignored otherwise). Calls given a NULL mr_tune* use
+ * these defaults too. */
 void mr_default_tune(mr_tune *out);
 
 /* Workspace bytes needed by one mr_recon_dilate (op = MR_OP_RECON) or

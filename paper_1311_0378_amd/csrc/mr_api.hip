@@ -1,6 +1,7 @@
 // mr_api.hip -- host side of libmrecon: argument checks, workspace layout and
 // the launch sequence behind the C ABI declared in include/mr.h.
 #include <algorithm>
+#include <cstdlib>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -694,6 +695,22 @@ void mr_default_tune(mr_tune *out) {
     out->converge_rounds = 0;
     out->tail_rounds = 8;
     out->first_sweeps = 1;
+    // MR_TUNE_<FIELD> environment overrides, each taken only when it is a
+    // whole number inside the field's valid range
+    auto env = [](const char *name, int32_t lo, int32_t hi, bool nonzero, int32_t &field) {
+        const char *v = std::getenv(name);
+        if (!v || !*v) return;
+        char *end = nullptr;
+        const long x = std::strtol(v, &end, 10);
+        if (*end || x < lo || x > hi || (nonzero && x == 0)) return;
+        field = (int32_t)x;
+    };
+    env("MR_TUNE_SWEEP_ROUNDS", -1, MAX_ROUNDS, true, out->sweep_rounds);
+    env("MR_TUNE_MAX_SWEEPS", 1, 1024, false, out->max_sweeps);
+    env("MR_TUNE_PERSISTENT_BLOCKS", 0, 1 << 20, false, out->persistent_blocks);
+    env("MR_TUNE_CONVERGE_ROUNDS", 0, MAX_ROUNDS, false, out->converge_rounds);
+    env("MR_TUNE_TAIL_ROUNDS", 0, MAX_ROUNDS, false, out->tail_rounds);
+    env("MR_TUNE_FIRST_SWEEPS", 1, 1024, false, out->first_sweeps);
 }
 
 size_t mr_workspace_bytes(int op, int64_t H, int64_t W, mr_dtype t, int conn, const mr_tune *tune) {

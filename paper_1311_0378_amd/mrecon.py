@@ -371,9 +371,30 @@ class BatchGraph:
             pass
 
 
-def autotune(items, conn: int = 8, stream=None) -> Tune:
+def tune_cache_key(items, conn: int) -> str:
+    """The autotuner cache's key for a batch: pixel type, connectivity, the
+    number of images and the total pixel count, each bucketed to a power of 2."""
+    dt = "u8" if items[0][0].dtype == torch.uint8 else "i32"
+    px = sum(int(a.shape[0]) * int(a.shape[1]) for a, *_ in items)
+    return f"{dt}-conn{conn}-n{max(len(items), 1).bit_length()}-px{max(px, 1).bit_length()}"
+
+
+def autotune(items, conn: int = 8, stream=None, cache=None) -> Tune:
     """Time candidate tunings of ``batch`` on these items (their data are
-    restored) and return the fastest."""
+    restored) and return the fastest.
+
+    ``cache`` (default: the MR_TUNE_CACHE environment variable, if set) names
+    a JSON file of tunes keyed by tune_cache_key: a batch whose key is in it
+    takes the stored tune without timing anything, and a newly timed tune is
+    added to it."""
+    import json
+    cache = cache if cache is not None else os.environ.get("MR_TUNE_CACHE")
+    key = tune_cache_key(items, conn)
+    if cache and os.path.exists(cache):
+        with open(cache) as f:
+            stored = json.load(f).get(key)
+        if stored is not None:
+            return make_tune(**stored)
     arr, n, t, _ = make_tiles(items)
     nb = lib().mr_autotune_workspace_bytes(arr, n, t, conn)
     if nb == 0:
@@ -382,6 +403,16 @@ def autotune(items, conn: int = 8, stream=None) -> Tune:
     out = Tune()
     _check(lib().mr_autotune(arr, n, t, conn, ws.data_ptr(), ws.numel(), _stream_ptr(stream),
                              ctypes.byref(out)))
+    if cache:
+        entries = {}
+        if os.path.exists(cache):
+            with open(cache) as f:
+                entries = json.load(f)
+        entries[key] = {k: int(getattr(out, k)) for k, _ in Tune._fields_}
+        tmp = f"{cache}.tmp{os.getpid()}"
+        with open(tmp, "w") as f:
+            json.dump(entries, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
     return out
 
 

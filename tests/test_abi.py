@@ -230,3 +230,34 @@ def test_job_struct_layout():
     assert ctypes.sizeof(mrecon.Job) == 3 * 8 + 4 * 8 + 2 * 4
     assert mrecon.Job.flags.offset == 3 * 8 + 4 * 8 + 4
     assert mrecon.MR_JOB_DEVICE == 1
+
+
+def test_default_tune_environment_overrides(monkeypatch):
+    base = mrecon.default_tune()
+    monkeypatch.setenv("MR_TUNE_TAIL_ROUNDS", "5")
+    monkeypatch.setenv("MR_TUNE_FIRST_SWEEPS", "16")
+    monkeypatch.setenv("MR_TUNE_MAX_SWEEPS", "0")        # out of range: ignored
+    monkeypatch.setenv("MR_TUNE_SWEEP_ROUNDS", "3x")     # not a number: ignored
+    t = mrecon.default_tune()
+    assert t.tail_rounds == 5 and t.first_sweeps == 16
+    assert t.max_sweeps == base.max_sweeps and t.sweep_rounds == base.sweep_rounds
+    monkeypatch.delenv("MR_TUNE_TAIL_ROUNDS")
+    monkeypatch.delenv("MR_TUNE_FIRST_SWEEPS")
+    assert mrecon.default_tune().tail_rounds == base.tail_rounds
+
+
+def test_autotune_cache_hit_times_nothing(tmp_path):
+    # a batch whose key is in the cache takes the stored tune without any
+    # device work (these tensors are on the host, which the timing path
+    # would reject)
+    import json
+    import torch
+    items = [(torch.zeros(70, 90, dtype=torch.uint8), torch.zeros(70, 90, dtype=torch.uint8),
+              mrecon.MR_OP_RECON)] * 3
+    key = mrecon.tune_cache_key(items, 8)
+    assert key == mrecon.tune_cache_key(items, 8) != mrecon.tune_cache_key(items, 4)
+    path = tmp_path / "tunes.json"
+    path.write_text(json.dumps({key: {"sweep_rounds": -1, "max_sweeps": 3, "tail_rounds": 6,
+                                      "first_sweeps": 16}}))
+    t = mrecon.autotune(items, 8, cache=str(path))
+    assert (t.sweep_rounds, t.max_sweeps, t.tail_rounds, t.first_sweeps) == (-1, 3, 6, 16)

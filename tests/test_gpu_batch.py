@@ -106,3 +106,20 @@ def test_autotune_restores_and_tunes():
     mrecon.batch(items, 8, tune=t)
     for i, (job, (d, _, _)) in enumerate(zip(jobs, items)):
         assert np.array_equal(d.cpu().numpy(), oracle_of(job, 8)), f"image {i}"
+
+
+def test_autotune_cache_stores_then_reuses(tmp_path):
+    import json
+    jobs = make_batch(6, "u8", seed=9)
+    items = to_items(jobs)
+    path = str(tmp_path / "tunes.json")
+    t1 = mrecon.autotune(items, 8, cache=path)          # timed, then stored
+    stored = json.load(open(path))
+    key = mrecon.tune_cache_key(items, 8)
+    assert stored[key]["tail_rounds"] == t1.tail_rounds
+    assert stored[key]["first_sweeps"] == t1.first_sweeps
+    t2 = mrecon.autotune(items, 8, cache=path)          # taken from the cache
+    assert all(getattr(t1, f) == getattr(t2, f) for f, _ in mrecon.Tune._fields_)
+    mrecon.batch(items, 8, tune=t2)
+    for i, (job, (d, _, _)) in enumerate(zip(jobs, items)):
+        assert np.array_equal(d.cpu().numpy(), oracle_of(job, 8)), f"image {i}"
