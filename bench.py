@@ -58,6 +58,14 @@ reaches, beside the 8 TB/s peak the rooflines use.
 (``mr_probe_atomics``: relaxed device-scope add, and load + compare-and-swap,
 on pseudo-random words of a 256 MiB and a 4 GiB buffer, every wave slot busy)
 and prints its own JSON line: the ceiling for the queue phase's atomics.
+
+``--random-probe`` times the random-access probe (``mr_probe_random``, the
+paper's micro-benchmark for irregular access, Sec. V-A / Table III): plain
+random reads and writes of 32-bit words of a 4K x 4K matrix (the paper's
+64 MiB) and of a 4 GiB one (past the 256 MiB Infinity Cache), 10 million
+operations (the paper's count) and 2^28, at positions drawn on the host into
+an index vector. It prints its own JSON line in MB/s of 4-byte words, the
+paper's unit, and in G operations/s.
 """
 from __future__ import annotations
 
@@ -1030,6 +1038,60 @@ def atomic_probe(torch, mrecon, dev, reps: int = 5) -> dict:
             "cases": cases}
 
 
+def random_probe(torch, mrecon, dev, reps: int = 5) -> dict:
+    """Plain random reads and writes of 32-bit words at host-drawn positions
+    (the index vector streams in order; only the matrix accesses scatter).
+    For each case the best launch shape of a small sweep is kept."""
+    import numpy as np
+    cases = []
+    rng = np.random.default_rng(1311)
+    for log2_words in (24, 30):  # 4K x 4K int32 (64 MiB), 4 GiB
+        words = torch.zeros(1 << log2_words, dtype=torch.int32, device=dev)
+        words.copy_(torch.arange(1 << log2_words, dtype=torch.int32, device=dev) * -1640531535)
+        mask = (1 << log2_words) - 1
+        for n_ops in (10_000_000, 1 << 28):
+            idx_np = rng.integers(0, 1 << log2_words, n_ops, dtype=np.uint32)
+            idx = torch.from_numpy(idx_np.view(np.int32)).to(dev)
+            del idx_np
+            for kind, name in ((mrecon.MR_RANDOM_READ, "read"), (mrecon.MR_RANDOM_WRITE, "write")):
+                best = None
+                for waves in (2048, 8192, 32768):
+                    sums = torch.empty(waves * 64, dtype=torch.int32, device=dev)
+                    mrecon.probe_random(words, idx, kind, waves, sums)  # warm-up
+                    times = []
+                    for _ in range(reps):
+                        a = torch.cuda.Event(enable_timing=True)
+                        b = torch.cuda.Event(enable_timing=True)
+                        a.record()
+                        mrecon.probe_random(words, idx, kind, waves, sums)
+                        b.record()
+                        b.synchronize()
+                        times.append(a.elapsed_time(b))
+                    ms = sorted(times)[len(times) // 2]
+                    if kind == mrecon.MR_RANDOM_READ:
+                        # the kernel's sums against torch's own gather (mod 2^32)
+                        got = int(sums.to(torch.int64).sum()) & 0xFFFFFFFF
+                        ref = int(words[idx.to(torch.int64) & mask].to(torch.int64).sum()) \
+                            & 0xFFFFFFFF
+                        if got != ref:
+                            raise RuntimeError(f"random read probe: sums {got} != {ref}")
+                    if best is None or ms < best[0]:
+                        best = (ms, waves)
+                    del sums
+                ms, waves = best
+                cases.append({"kind": name, "matrix_mib": (4 << log2_words) >> 20, "ops": n_ops,
+                              "waves": waves, "ms_median": round(ms, 4),
+                              "g_ops_s": round(n_ops / ms / 1e6, 2),
+                              "mb_s": round(4 * n_ops / ms / 1e3, 0)})
+                log(f"random {name} {(4 << log2_words) >> 20} MiB, {n_ops} ops, {waves} waves: "
+                    f"{ms:.3f} ms, {n_ops / ms / 1e6:.2f} G ops/s, {4 * n_ops / ms / 1e3:.0f} MB/s")
+            del idx
+        del words
+    return {"probe": "plain random reads and writes of 32-bit words at host-drawn positions",
+            "unit_mb_s": "MB/s of 4-byte words (10^6 B/s)", "cases": cases,
+            "paper_table3_gpu_mb_s": {"read": 895, "write": 126}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -1062,6 +1124,9 @@ def main():
     ap.add_argument("--atomic-probe", action="store_true",
                     help="time the device atomic-rate probe (mr_probe_atomics) on a 256 MiB and "
                          "a 4 GiB buffer, print one JSON line and exit")
+    ap.add_argument("--random-probe", action="store_true",
+                    help="time the random-access probe (mr_probe_random) on a 64 MiB and a 4 GiB "
+                         "matrix, print one JSON line and exit")
     ap.add_argument("--queue-planes", action="store_true",
                     help="time the queue phase with the dword compare-and-swap and with the "
                          "widened plane (uint8, 1/2/4 rounds first), print one JSON line and exit")
@@ -1095,6 +1160,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.atomic_probe:
         print(json.dumps(atomic_probe(torch, mrecon, dev)), flush=True)
+        return
+    if args.random_probe:
+        print(json.dumps(random_probe(torch, mrecon, dev)), flush=True)
         return
     if args.queue_planes:
         print(json.dumps(queue_planes(args, torch, mrecon, dev)), flush=True)

@@ -394,6 +394,31 @@ enum { MR_PROBE_ADD = 0, MR_PROBE_CAS = 1 };
 int mr_probe_atomics(void *words, size_t n_words, int kind, int32_t per_lane, int32_t waves,
                      uint32_t seed, void *stream);
 
+/* Random-access probe (measurement support; the paper's micro-benchmark for
+ * irregular access, Sec. V-A, whose figures Table III gives in MB/s). Enqueues
+ * on `stream` one launch of `waves` 64-lane waves that performs n_ops plain
+ * (non-atomic) accesses to 32-bit words of `words` (device memory, n_words
+ * values, caller-owned), operation i at position indices[i] mod n_words, where
+ * `indices` (device memory, n_ops uint32 values, caller-owned, read only) is
+ * filled by the caller, as the paper fills its index vector on the host.
+ * Lane g of the grid (g < waves * 64) performs the operations g, g + S,
+ * g + 2S, ... with S = waves * 64.
+ *   MR_RANDOM_READ   lane g writes the 32-bit wrapping sum of the words it
+ *                    read to sums[g] (device memory, waves * 64 uint32 values,
+ *                    caller-owned); `words` is not written.
+ *   MR_RANDOM_WRITE  operation i stores the low 32 bits of i at its position;
+ *                    where several operations share a position, which of them
+ *                    lands is unspecified. `sums` is ignored.
+ * The index vector is read once, in order; the accesses to `words` scatter.
+ * Time it with events on the same stream.
+ * Errors: MR_EINVAL (words null or not 4-byte aligned; n_words not a power of
+ * two in [64, 2^32]; kind unknown; indices null or not 4-byte aligned; n_ops
+ * outside [1, 2^34]; waves outside [1, 2^20]; a read with sums null or not
+ * 4-byte aligned), MR_EHIP (launch failure). Nothing is enqueued on error. */
+enum { MR_RANDOM_READ = 0, MR_RANDOM_WRITE = 1 };
+int mr_probe_random(void *words, size_t n_words, const void *indices, size_t n_ops, int kind,
+                    int32_t waves, void *sums, void *stream);
+
 /* Message for the last error returned to the calling thread ("" if none). */
 const char *mr_last_error(void);
 

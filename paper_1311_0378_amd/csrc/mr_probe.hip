@@ -1,5 +1,6 @@
-// mr_probe.hip -- device atomic-rate probe of libmrecon (mr_probe_atomics in
-// include/mr.h).
+// mr_probe.hip -- device probes of libmrecon: the atomic-rate probe
+// (mr_probe_atomics) and the random-access probe (mr_probe_random), both in
+// include/mr.h.
 //
 // The queue phase spends its time in device-scope atomics on scattered
 // addresses: a load of a pixel's word, then a compare-and-swap whose result
@@ -15,8 +16,15 @@
 //    lands (the queue's raise pattern: each lane waits for its result).
 // Both add exactly one to some word per operation, so the buffer's sum grows
 // by waves * 64 * per_lane and the caller can check that every operation
-// happened. The probe is measurement support; no call of the reconstruction
-// uses it.
+// happened.
+//
+// The random-access probe follows the paper's micro-benchmark for irregular
+// access (Sec. V-A, Table III): plain reads or writes of 32-bit words of a
+// matrix at positions that a separate index vector holds, filled on the host.
+// The index vector streams in order; only the matrix accesses scatter, as the
+// queue phase's and the distance transform's plain loads of pixels do.
+// Neither probe is used by any call of the reconstruction: they are
+// measurement support.
 #include "mr_internal.h"
 
 using namespace mr;
@@ -53,7 +61,79 @@ __global__ __launch_bounds__(64) void k_probe_atomics(uint32_t *__restrict__ wor
     }
 }
 
+// Lane g of the grid takes the operations g, g + S, g + 2S, ... (S = the
+// grid's lane count), eight at a time while all eight exist so that eight
+// index loads and then eight scattered accesses are in flight per lane.
+// Reads add the words they fetch into the lane's 32-bit sum (wrapping), which
+// the lane writes to sums[g]; writes store the operation's number i (the
+// low 32 bits) at its position. Positions are the indices modulo the matrix
+// size, a power of two, so every access stays inside the matrix.
+template <int KIND>
+__global__ __launch_bounds__(64) void k_probe_random(uint32_t *__restrict__ words, uint32_t mask,
+                                                     const uint32_t *__restrict__ idx, uint64_t n,
+                                                     uint32_t *__restrict__ sums) {
+    constexpr int U = 8;
+    const uint64_t g = (uint64_t)blockIdx.x * 64u + threadIdx.x;
+    const uint64_t S = (uint64_t)gridDim.x * 64u;
+    uint32_t acc = 0;
+    uint64_t i = g;
+    for (; i + (U - 1) * S < n; i += U * S) {
+        uint32_t p[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) p[u] = idx[i + u * S] & mask;
+        if (KIND == MR_RANDOM_READ) {
+            uint32_t v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = words[p[u]];
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc += v[u];
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) words[p[u]] = (uint32_t)(i + u * S);
+        }
+    }
+    for (; i < n; i += S) {
+        const uint32_t p = idx[i] & mask;
+        if (KIND == MR_RANDOM_READ)
+            acc += words[p];
+        else
+            words[p] = (uint32_t)i;
+    }
+    if (KIND == MR_RANDOM_READ) sums[g] = acc;
+}
+
 } // namespace
+
+extern "C" int mr_probe_random(void *words, size_t n_words, const void *indices, size_t n_ops,
+                               int kind, int32_t waves, void *sums, void *stream) {
+    clear_error();
+    if (!words || ((uintptr_t)words & 3) != 0 || n_words < 64 || (n_words & (n_words - 1)) != 0 ||
+        n_words > (1ull << 32))
+        return set_error(MR_EINVAL, "probe: words must be non-null and 4-byte aligned, n_words a "
+                                    "power of two in [64, 2^32]");
+    if (kind != MR_RANDOM_READ && kind != MR_RANDOM_WRITE)
+        return set_error(MR_EINVAL, "probe: kind must be MR_RANDOM_READ or MR_RANDOM_WRITE");
+    if (!indices || ((uintptr_t)indices & 3) != 0 || n_ops < 1 || n_ops > (1ull << 34))
+        return set_error(MR_EINVAL, "probe: indices must be non-null and 4-byte aligned, n_ops "
+                                    "in [1, 2^34]");
+    if (waves < 1 || waves > (1 << 20))
+        return set_error(MR_EINVAL, "probe: waves must be in [1, 2^20]");
+    if (kind == MR_RANDOM_READ && (!sums || ((uintptr_t)sums & 3) != 0))
+        return set_error(MR_EINVAL, "probe: a read needs sums (4-byte aligned, waves * 64 words)");
+    const uint32_t mask = (uint32_t)(n_words - 1);
+    hipStream_t s = (hipStream_t)stream;
+    if (kind == MR_RANDOM_READ)
+        hipLaunchKernelGGL((k_probe_random<MR_RANDOM_READ>), dim3((unsigned)waves), dim3(64), 0, s,
+                           (uint32_t *)words, mask, (const uint32_t *)indices, (uint64_t)n_ops,
+                           (uint32_t *)sums);
+    else
+        hipLaunchKernelGGL((k_probe_random<MR_RANDOM_WRITE>), dim3((unsigned)waves), dim3(64), 0,
+                           s, (uint32_t *)words, mask, (const uint32_t *)indices,
+                           (uint64_t)n_ops, (uint32_t *)nullptr);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(MR_EHIP, hipGetErrorString(e));
+    return MR_OK;
+}
 
 extern "C" int mr_probe_atomics(void *words, size_t n_words, int kind, int32_t per_lane,
                                 int32_t waves, uint32_t seed, void *stream) {

@@ -22,6 +22,7 @@ MR_U8, MR_I32 = 1, 4
 MR_OK, MR_EINVAL, MR_ENOMEM, MR_EHIP, MR_EAGAIN = 0, -1, -2, -3, -4
 MR_OP_RECON, MR_OP_FILL = 0, 1
 MR_PROBE_ADD, MR_PROBE_CAS = 0, 1
+MR_RANDOM_READ, MR_RANDOM_WRITE = 0, 1
 MR_JOB_DEVICE = 1
 
 _DTYPES = {torch.uint8: MR_U8, torch.int32: MR_I32}
@@ -147,6 +148,8 @@ def lib():
         L.mr_timing_collect.restype = c_int
         L.mr_probe_atomics.argtypes = [vp, sz, c_int, i32, i32, ctypes.c_uint32, vp]
         L.mr_probe_atomics.restype = c_int
+        L.mr_probe_random.argtypes = [vp, sz, vp, sz, c_int, i32, vp, vp]
+        L.mr_probe_random.restype = c_int
         L.mr_last_error.argtypes = []
         L.mr_last_error.restype = ctypes.c_char_p
         L.mr_abi_version.argtypes = []
@@ -602,3 +605,24 @@ def probe_atomics(words: torch.Tensor, kind: int, per_lane: int, waves: int, see
         raise TypeError("words must be a contiguous int32 or uint32 device tensor")
     _check(lib().mr_probe_atomics(words.data_ptr(), words.numel(), int(kind), int(per_lane),
                                   int(waves), int(seed) & 0xFFFFFFFF, _stream_ptr(stream)))
+
+
+def probe_random(words: torch.Tensor, indices: torch.Tensor, kind: int, waves: int,
+                 sums: torch.Tensor | None = None, stream=None) -> None:
+    """Enqueue the random-access probe: ``indices.numel()`` plain reads
+    (``MR_RANDOM_READ``, per-lane wrapping sums into ``sums``, ``waves * 64``
+    32-bit words) or writes (``MR_RANDOM_WRITE``, operation i stores i) of
+    ``words`` (a contiguous 32-bit device tensor whose length is a power of
+    two) at the positions ``indices`` (contiguous 32-bit device tensor) holds,
+    taken modulo ``words.numel()``."""
+    for name, t in (("words", words), ("indices", indices)) + ((("sums", sums),)
+                                                               if sums is not None else ()):
+        if (t.dtype not in (torch.int32, torch.uint32) or not t.is_contiguous()
+                or not t.is_cuda):
+            raise TypeError(f"{name} must be a contiguous int32 or uint32 device tensor")
+    if sums is not None and sums.numel() < int(waves) * 64:
+        raise ValueError(f"sums holds {sums.numel()} words; the launch writes {int(waves) * 64}")
+    _check(lib().mr_probe_random(words.data_ptr(), words.numel(), indices.data_ptr(),
+                                 indices.numel(), int(kind), int(waves),
+                                 sums.data_ptr() if sums is not None else None,
+                                 _stream_ptr(stream)))

@@ -184,6 +184,20 @@ def test_probe_atomics_rejects(L, words, n, kind, per_lane, waves):
     assert L.mr_last_error().startswith(b"probe:")
 
 
+@pytest.mark.parametrize("words,n,idx,n_ops,kind,waves,sums", [
+    (0, 1 << 16, FAKE, 10, 0, 1, FAKE), (FAKE + 2, 1 << 16, FAKE, 10, 0, 1, FAKE),
+    (FAKE, 1000, FAKE, 10, 0, 1, FAKE), (FAKE, 32, FAKE, 10, 1, 1, 0),
+    (FAKE, 1 << 16, FAKE, 10, 2, 1, FAKE), (FAKE, 1 << 16, 0, 10, 1, 1, 0),
+    (FAKE, 1 << 16, FAKE + 1, 10, 1, 1, 0), (FAKE, 1 << 16, FAKE, 0, 0, 1, FAKE),
+    (FAKE, 1 << 16, FAKE, (1 << 34) + 1, 1, 1, 0), (FAKE, 1 << 16, FAKE, 10, 1, 0, 0),
+    (FAKE, 1 << 16, FAKE, 10, 0, (1 << 20) + 1, FAKE), (FAKE, 1 << 16, FAKE, 10, 0, 1, 0),
+    (FAKE, 1 << 16, FAKE, 10, 0, 1, FAKE + 2)])
+def test_probe_random_rejects(L, words, n, idx, n_ops, kind, waves, sums):
+    assert L.mr_probe_random(ctypes.c_void_p(words), n, ctypes.c_void_p(idx), n_ops, kind, waves,
+                             ctypes.c_void_p(sums), None) == mrecon.MR_EINVAL
+    assert L.mr_last_error().startswith(b"probe:")
+
+
 def test_erode_workspace_bytes():
     import torch
     r = mrecon.workspace_bytes(mrecon.MR_OP_RECON, 100, 100, torch.uint8, 8)
