@@ -75,7 +75,8 @@ struct RangeAlloc {
     bool alloc_in(size_t n, size_t lo, size_t hi, size_t &off) {
         n = up(std::max<size_t>(n, 1), align);
         for (auto it = free_.begin(); it != free_.end(); ++it) {
-            const size_t a = std::max(it->first, lo), e = std::min(it->first + it->second, hi);
+            const size_t a = up(std::max(it->first, lo), align);
+            const size_t e = std::min(it->first + it->second, hi);
             if (a >= e || e - a < n) continue;
             const size_t f = it->first, len = it->second;
             free_.erase(it);

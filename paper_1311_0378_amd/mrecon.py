@@ -375,11 +375,14 @@ class BatchGraph:
 
 
 def tune_cache_key(items, conn: int) -> str:
-    """The autotuner cache's key for a batch: pixel type, connectivity, the
-    number of images and the total pixel count, each bucketed to a power of 2."""
+    """The autotuner cache's key for a batch: the ABI version (a tune stored by
+    a library whose mr_tune differs is not reused), pixel type, connectivity,
+    the number of images and the total pixel count, each bucketed to a power
+    of 2."""
     dt = "u8" if items[0][0].dtype == torch.uint8 else "i32"
     px = sum(int(a.shape[0]) * int(a.shape[1]) for a, *_ in items)
-    return f"{dt}-conn{conn}-n{max(len(items), 1).bit_length()}-px{max(px, 1).bit_length()}"
+    return (f"abi{ABI_VERSION}-{dt}-conn{conn}-n{max(len(items), 1).bit_length()}"
+            f"-px{max(px, 1).bit_length()}")
 
 
 def autotune(items, conn: int = 8, stream=None, cache=None) -> Tune:

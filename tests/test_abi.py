@@ -270,6 +270,7 @@ def test_autotune_cache_hit_times_nothing(tmp_path):
               mrecon.MR_OP_RECON)] * 3
     key = mrecon.tune_cache_key(items, 8)
     assert key == mrecon.tune_cache_key(items, 8) != mrecon.tune_cache_key(items, 4)
+    assert key.startswith(f"abi{mrecon.ABI_VERSION}-u8-conn8-")
     path = tmp_path / "tunes.json"
     path.write_text(json.dumps({key: {"sweep_rounds": -1, "max_sweeps": 3, "tail_rounds": 6,
                                       "first_sweeps": 16}}))
