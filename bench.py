@@ -45,11 +45,12 @@ More legs are added to the same line (``--legs``):
 * ``erode``: reconstruction by erosion (``mr_recon_erode``) on a 16384 x
   16384 u8 image, 8-conn, the same mask with the marker raised by 30: a
   complement pass, the reconstruction by dilation, the complement back.
-  Checked against the oracle.
+  Checked against the oracle, whose time on one core is reported beside it.
 * ``ops``: the other Table II operations on the same 16384^2 image: RGB2Gray,
   opening by the 13 x 13 disk, distance transform, CCL, area threshold,
   h-dome and regional maxima, each with its time, algorithmic bytes against
-  the HBM peak, and an oracle check.
+  the HBM peak, an oracle check, and the oracle's own time on one core
+  (``cpu_oracle``; the opening's on the windows it checks).
 
 The line also carries ``copy_bandwidth``: what a plain 1 GiB device copy
 reaches, beside the 8 TB/s peak the rooflines use.
@@ -588,7 +589,11 @@ def leg_erode(args, dev) -> dict:
     log(f"erode: {ms:.3f} ms per call")
     if not args.no_verify:
         import oracle
+        t = time.perf_counter()
         want, _ = oracle.recon_erode(marker, mask, conn)
+        secs = time.perf_counter() - t
+        out["cpu_oracle"] = {"s": round(secs, 3), "mpx_s": round(marker.size / secs / 1e6, 2),
+                             "cores": 1, "kind": "oracle"}
         out["bit_exact"] = bool(np.array_equal(copies[K - 1].cpu().numpy(), want))
         log("erode: bit-exact vs oracle:", out["bit_exact"])
     del copies, ws, d_mask, d_src
@@ -873,12 +878,25 @@ def leg_ops(args, dev, mask) -> dict:
         return d
 
     verify = not args.no_verify
+
+    def cpu(fn, px=npx):
+        """Run one oracle computation on one host core: its result and the
+        oracle's rate beside the GPU's (the oracle as it stands, untuned)."""
+        t = time.perf_counter()
+        r = fn()
+        s = time.perf_counter() - t
+        return r, {"s": round(s, 3), "mpx_s": round(px / s / 1e6, 2), "cores": 1,
+                   "kind": "oracle"}
+
     # RGB2Gray: 3 bytes in, 1 out per pixel
     d_rgb = torch.from_numpy(rgb).to(dev)
     gray = torch.empty((S, S), dtype=torch.uint8, device=dev)
     ms, _ = timed(lambda: ops.rgb2gray(d_rgb, out=gray))
-    ok = bool(np.array_equal(gray.cpu().numpy(), oracle.rgb2gray(rgb))) if verify else None
-    out["rgb2gray"] = line(ms, 4 * npx, ok)
+    ok, c = None, None
+    if verify:
+        want, c = cpu(lambda: oracle.rgb2gray(rgb))
+        ok = bool(np.array_equal(gray.cpu().numpy(), want))
+    out["rgb2gray"] = line(ms, 4 * npx, ok, cpu_oracle=c)
     log(f"ops: rgb2gray {ms:.3f} ms, exact {ok}")
     del d_rgb, gray
 
@@ -886,19 +904,24 @@ def leg_ops(args, dev, mask) -> dict:
     o = torch.empty_like(d_mask)
     wso = torch.empty(S * S, dtype=torch.uint8, device=dev)
     ms, _ = timed(lambda: ops.open_disk13(d_mask, out=o, workspace=wso))
-    ok = None
+    ok, c = None, None
     if verify:
         rng = np.random.default_rng(11)
         got = o.cpu().numpy()
-        ok = True
+        ok, secs, px = True, 0.0, 0
         for _ in range(48):
             y, x = (int(v) for v in rng.integers(0, S - 256, 2))
             y0, x0 = max(0, y - 12), max(0, x - 12)
             y1, x1 = min(S, y + 256 + 12), min(S, x + 256 + 12)
-            want = oracle.open_disk13(mask[y0:y1, x0:x1])
+            want, cw = cpu(lambda: oracle.open_disk13(mask[y0:y1, x0:x1]), (y1 - y0) * (x1 - x0))
+            secs += cw["s"]
+            px += (y1 - y0) * (x1 - x0)
             ok &= bool(np.array_equal(got[y:y + 256, x:x + 256],
                                       want[y - y0:y - y0 + 256, x - x0:x - x0 + 256]))
-    out["open_disk13"] = line(ms, 4 * npx, ok, check="48 windows of 256x256 (12-pixel margin)",
+        c = {"s": round(secs, 3), "mpx_s": round(px / max(secs, 1e-9) / 1e6, 2), "cores": 1,
+             "kind": "oracle", "sample": "the 48 checked windows with their margins"}
+    out["open_disk13"] = line(ms, 4 * npx, ok, cpu_oracle=c,
+                              check="48 windows of 256x256 (12-pixel margin)",
                               note="two passes (erosion, dilation); bound by instruction "
                                    "issue rather than HBM")
     log(f"ops: open {ms:.3f} ms, exact {ok}")
@@ -910,9 +933,11 @@ def leg_ops(args, dev, mask) -> dict:
     wsd = torch.empty(ops.lib().mr_distance_transform_workspace_bytes(S, S, 8),
                       dtype=torch.uint8, device=dev)
     ms, _ = timed(lambda: ops.distance_transform(d_bin, 8, out=dist, workspace=wsd))
-    ok = bool(np.array_equal(dist.cpu().numpy(), oracle.distance_transform(binary, 8))) \
-        if verify else None
-    out["distance_transform"] = line(ms, 5 * npx, ok, conn=8)
+    ok, c = None, None
+    if verify:
+        want, c = cpu(lambda: oracle.distance_transform(binary, 8))
+        ok = bool(np.array_equal(dist.cpu().numpy(), want))
+    out["distance_transform"] = line(ms, 5 * npx, ok, conn=8, cpu_oracle=c)
     log(f"ops: distance transform {ms:.3f} ms, exact {ok}")
     del dist, wsd
 
@@ -921,9 +946,11 @@ def leg_ops(args, dev, mask) -> dict:
     lab = torch.empty((S, S), dtype=torch.int32, device=dev)
     wsc = torch.empty(ops.lib().mr_ccl_workspace_bytes(S, S), dtype=torch.uint8, device=dev)
     ms, _ = timed(lambda: ops.ccl(d_bin, 8, out=lab, workspace=wsc))
-    want_lab = oracle.ccl(binary, 8) if verify else None
-    ok = bool(np.array_equal(lab.cpu().numpy(), want_lab)) if verify else None
-    out["ccl"] = line(ms, 5 * npx, ok, conn=8)
+    ok, c, want_lab = None, None, None
+    if verify:
+        want_lab, c = cpu(lambda: oracle.ccl(binary, 8))
+        ok = bool(np.array_equal(lab.cpu().numpy(), want_lab))
+    out["ccl"] = line(ms, 5 * npx, ok, conn=8, cpu_oracle=c)
     log(f"ops: ccl {ms:.3f} ms, exact {ok}")
     del wsc
     lab2 = torch.empty_like(lab)
@@ -932,9 +959,11 @@ def leg_ops(args, dev, mask) -> dict:
     lo, hi = 150, 500
     ms, _ = timed(lambda: ops.area_threshold(lab2, lo, hi, workspace=wsa),
                   prep=lambda: lab2.copy_(lab))
-    ok = bool(np.array_equal(lab2.cpu().numpy(), oracle.area_threshold(want_lab, lo, hi)[0])) \
-        if verify else None
-    out["area_threshold"] = line(ms, 8 * npx, ok, range=[lo, hi])
+    ok, c = None, None
+    if verify:
+        want, c = cpu(lambda: oracle.area_threshold(want_lab, lo, hi)[0])
+        ok = bool(np.array_equal(lab2.cpu().numpy(), want))
+    out["area_threshold"] = line(ms, 8 * npx, ok, range=[lo, hi], cpu_oracle=c)
     log(f"ops: area threshold {ms:.3f} ms, exact {ok}")
     del lab, lab2, wsa
 
@@ -945,14 +974,19 @@ def leg_ops(args, dev, mask) -> dict:
     wsh = torch.empty(ops.hdome_workspace_bytes(S, S, S, torch.uint8, 8), dtype=torch.uint8,
                       device=dev)
     ms, _ = timed(lambda: ops.hdome(hd, h, 8, workspace=wsh), prep=lambda: hd.copy_(d_mask))
-    ok = bool(np.array_equal(hd.cpu().numpy(), oracle.hdome(mask, h, 8))) if verify else None
-    out["hdome"] = line(ms, 3 * npx, ok, h=h)
+    ok, c = None, None
+    if verify:
+        want, c = cpu(lambda: oracle.hdome(mask, h, 8))
+        ok = bool(np.array_equal(hd.cpu().numpy(), want))
+    out["hdome"] = line(ms, 3 * npx, ok, h=h, cpu_oracle=c)
     log(f"ops: h-dome {ms:.3f} ms, exact {ok}")
     rm = torch.empty_like(d_mask)
     ms, _ = timed(lambda: ops.regional_maxima(d_mask, 8, out=rm, workspace=wsh))
-    ok = bool(np.array_equal(rm.cpu().numpy(), oracle.regional_maxima(mask, 8))) \
-        if verify else None
-    out["regional_maxima"] = line(ms, 3 * npx, ok)
+    ok, c = None, None
+    if verify:
+        want, c = cpu(lambda: oracle.regional_maxima(mask, 8))
+        ok = bool(np.array_equal(rm.cpu().numpy(), want))
+    out["regional_maxima"] = line(ms, 3 * npx, ok, cpu_oracle=c)
     log(f"ops: regional maxima {ms:.3f} ms, exact {ok}")
     del hd, rm, wsh, d_mask, d_bin
     return out
