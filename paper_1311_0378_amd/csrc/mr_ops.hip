@@ -295,22 +295,22 @@ __global__ __launch_bounds__(256) void k_rgb2gray1(const uint8_t *__restrict__ r
 
 // The disk of radius 6 as rows: offset dy has half-width HW[|dy|]
 // (dy^2 + dx^2 <= 36: 6, 5, 5, 5, 4, 3, 0).
-// Each workgroup of DK_THREADS lanes produces DK_TH rows x 4 * DK_THREADS
-// columns. The input rows it needs (DK_TH + 12, with 6 columns of halo on
-// each side) are staged in LDS as bytes. Each lane owns 4 adjacent columns:
-// per input row it reads the 16 bytes around them (4 LDS words), forms the
-// horizontal extrema of widths 0, 3, 4, 5 and 6 for its 4 columns, and folds
-// them into 13 running accumulators, one per output row that this input row
-// still contributes to (the accumulator of the output row dy above gets the
-// extremum of width HW[|dy|]). Each output row is complete once its last
-// input row is folded in, and is stored. Pixels outside the image read as
-// the operation's identity (255 for the erosion, 0 for the dilation), which
-// leaves the extrema over the inside offsets.
-constexpr int DK_THREADS = 128;
-constexpr int DK_TW = 4 * DK_THREADS;    // output columns per workgroup
-constexpr int DK_TH = 64;                // output rows per workgroup
-constexpr int DK_ROWS = DK_TH + 12;      // staged input rows
-constexpr int DK_SW = DK_TW + 16;        // staged row bytes: 8 left, 8 right (6 used)
+// One wave per workgroup. A wave's 64 lanes cover a window of 256 adjacent
+// columns, 4 per lane, and it produces the 240 columns of lanes 2..61 for
+// DK_TH rows: an extremum over 13 columns needs 6 columns on each side, and
+// lanes 0, 1, 62 and 63 supply them. Per input row each lane loads the one
+// dword of its 4 columns, forms the horizontal extrema of half-widths 1, 3,
+// 4, 5 and 6 of its own columns, taking the few values it needs of the
+// neighbouring lanes' columns by lane shifts (DPP), and folds them into 13
+// running accumulators, one per output row that this input row still
+// contributes to (the accumulator of the output row dy above gets the
+// extremum of half-width HW[|dy|]). Each output row is complete once its
+// last input row is folded in, and is stored. Pixels outside the image read
+// as the operation's identity (255 for the erosion, 0 for the dilation),
+// which leaves the extrema over the inside offsets.
+constexpr int DK_OUT = 240;          // output columns per wave (lanes 2..61)
+constexpr int DK_TH = 64;           // output rows per wave
+constexpr int DK_ROWS = DK_TH + 12;  // input rows per wave
 
 typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
 
@@ -325,97 +325,110 @@ template <bool MIN> __device__ __forceinline__ uint32_t ext3(uint32_t a, uint32_
         asm("v_max3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
     return r;
 }
+// Lane i gets lane i-1's value; lane i gets lane i+1's value. Lanes 0 and 63
+// get 0 from the missing neighbour; only columns of lanes 0, 1, 62 and 63
+// depend on those values, and they are not stored.
+__device__ __forceinline__ uint32_t from_left(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138 /* wave_shr:1 */, 0xF, 0xF,
+                                                 true);
+}
+__device__ __forceinline__ uint32_t from_right(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130 /* wave_shl:1 */, 0xF, 0xF,
+                                                 true);
+}
 
 template <bool MIN>
-__global__ __launch_bounds__(DK_THREADS) void k_disk13(const uint8_t *__restrict__ in,
-                                                       uint8_t *__restrict__ out, int64_t H,
-                                                       int64_t W, int64_t pitch, int64_t tiles_x) {
-    // the staged rows of one step of 13 (the accumulator ring's period)
-    __shared__ uint32_t st[13 * (DK_SW / 4)];
+__global__ __launch_bounds__(64) void k_disk13(const uint8_t *__restrict__ in,
+                                               uint8_t *__restrict__ out, int64_t H, int64_t W,
+                                               int64_t pitch, int64_t tiles_x) {
     const uint32_t ident = MIN ? 0xFFu : 0u;
     const uint32_t ident4 = MIN ? 0xFFFFFFFFu : 0u;
+    const int lane = threadIdx.x;
     const int64_t tile = blockIdx.x;
     const int64_t ty = tile / tiles_x, tx = tile - ty * tiles_x;
-    const int64_t y0 = ty * DK_TH, x0 = tx * DK_TW;
-    constexpr int WPR = DK_SW / 4; // words per staged row
-    // stage rows y0-6+r0 .. y0-6+r0+12, columns x0-8 .. x0+DK_TW+7, one word
-    // per lane and step; a word is gathered byte by byte at the image edges.
-    // Staging 13 rows at a time (instead of the tile's 76) keeps a
-    // workgroup's LDS at 7 KB, so that LDS no longer limits the waves per
-    // SIMD.
-    auto stage = [&](int r0) {
-        for (int i = threadIdx.x; i < 13 * WPR; i += DK_THREADS) {
-            const int rl = i / WPR, wc = i - rl * WPR;
-            if (r0 + rl >= DK_ROWS) break;
-            const int64_t gy = y0 - 6 + r0 + rl, gx = x0 - 8 + 4 * (int64_t)wc;
-            uint32_t v = ident4;
-            if (gy >= 0 && gy < H) {
-                const uint8_t *row = in + gy * pitch;
-                if (gx >= 0 && gx + 3 < W && (((uintptr_t)(row + gx)) & 3) == 0) {
-                    v = *(const uint32_t *)(row + gx);
-                } else {
-                    v = 0u;
+    const int64_t y0 = ty * DK_TH;
+    const int64_t gx = tx * DK_OUT - 8 + 4 * lane; // this lane's first column
+    const bool whole = gx >= 0 && gx + 3 < W;
+    // input row r of this wave is image row y0 - 6 + r
+    auto load = [&](int r) -> uint32_t {
+        const int64_t gy = y0 - 6 + r;
+        if (gy < 0 || gy >= H) return ident4;
+        const uint8_t *p = in + gy * pitch + gx;
+        if (whole && (((uintptr_t)p) & 3) == 0) return *(const uint32_t *)p;
+        uint32_t v = 0u;
 #pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const int64_t x = gx + b;
-                        const uint32_t byte = (x >= 0 && x < W) ? row[x] : ident;
-                        v |= byte << (8 * b);
-                    }
-                }
-            }
-            st[i] = v;
+        for (int b = 0; b < 4; ++b) {
+            const uint32_t byte = (gx + b >= 0 && gx + b < W) ? p[b] : ident;
+            v |= byte << (8 * b);
         }
+        return v;
     };
 
-    const int lx = threadIdx.x * 4; // first of this lane's columns, tile-relative
-    // 13 accumulators per column in a ring: output row o (tile-relative) lives
-    // in slot o mod 13. Input row r reaches output rows r - 12 .. r (offsets
-    // dy = 6 .. -6), which sit in slots (r + 1 + k) mod 13, k = 0..12; the
-    // rows are walked 13 at a time so that every slot index is a constant.
-    // Two columns per accumulator, one in each 16-bit half (the pixels are
-    // 8-bit), folded with packed 16-bit extrema: half the fold instructions
-    // and accumulator registers.
+    // 13 accumulators per column in a ring: output row o (wave-relative)
+    // lives in slot o mod 13. Input row r reaches output rows r - 12 .. r
+    // (offsets dy = 6 .. -6), which sit in slots (r + 1 + k) mod 13,
+    // k = 0..12; the rows are walked 13 at a time so that every slot index is
+    // a constant. Two columns per accumulator, one in each 16-bit half (the
+    // pixels are 8-bit), folded with packed 16-bit extrema.
     const u16x2 identp = {(uint16_t)ident, (uint16_t)ident};
     u16x2 acc[13][2];
 #pragma unroll
     for (int k = 0; k < 13; ++k) acc[k][0] = acc[k][1] = identp;
     constexpr int HWID[7] = {6, 5, 5, 5, 4, 3, 0}; // half-width of the disk row |dy|
+    const bool stores = lane >= 2 && lane < 62;
 #pragma unroll 1
     for (int r0 = 0; r0 < DK_ROWS; r0 += 13) {
-        __syncthreads(); // the previous step's reads of the stage are done
-        stage(r0);
-        __syncthreads();
+        uint32_t wd[13];
+#pragma unroll
+        for (int rr = 0; rr < 13; ++rr) wd[rr] = r0 + rr < DK_ROWS ? load(r0 + rr) : ident4;
 #pragma unroll
         for (int rr = 0; rr < 13; ++rr) {
             const int r = r0 + rr;
             if (r >= DK_ROWS) break;
-            // staged row r starts 8 columns left of the tile, so column
-            // lx - 6 + j (j = 0..15) is staged byte lx + 2 + j: the 5 words
-            // from staged byte lx hold them
-            const uint32_t *w = st + rr * WPR + (lx >> 2);
-            uint32_t wd[5];
+            // e_w[c]: the extremum over columns c - w .. c + w of this lane's
+            // column c (0..3); index c + 1 of the arrays below, so that the
+            // left neighbour's last column is index 0 and the right
+            // neighbour's first is index 5 where a step needs them
+            uint32_t b[4];
 #pragma unroll
-            for (int k = 0; k < 5; ++k) wd[k] = w[k];
-            uint32_t b[16];
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const int q = j + 2;
-                b[j] = (wd[q >> 2] >> ((q & 3) * 8)) & 0xFFu;
+            for (int c = 0; c < 4; ++c) b[c] = (wd[rr] >> (8 * c)) & 0xFFu;
+            uint32_t e1[4], e3[4], e4[4], e5[4], e6[4];
+            {
+                const uint32_t l = from_left(b[3]), rt = from_right(b[0]);
+                e1[0] = ext3<MIN>(l, b[0], b[1]);
+                e1[1] = ext3<MIN>(b[0], b[1], b[2]);
+                e1[2] = ext3<MIN>(b[1], b[2], b[3]);
+                e1[3] = ext3<MIN>(b[2], b[3], rt);
             }
-            // horizontal extrema over the columns j-w .. j+w (widths 1, 3, 4,
-            // 5, 6) for the positions the next width needs; this lane's
-            // output column c is position c + 6
-            uint32_t e1[16], e3[16], e4[16], e5[16], e6[4];
-#pragma unroll
-            for (int j = 1; j < 15; ++j) e1[j] = ext3<MIN>(b[j - 1], b[j], b[j + 1]);
-#pragma unroll
-            for (int j = 3; j < 13; ++j) e3[j] = ext3<MIN>(e1[j - 2], e1[j], e1[j + 2]);
-#pragma unroll
-            for (int j = 4; j < 12; ++j) e4[j] = ext<MIN>(e3[j - 1], e3[j + 1]);
-#pragma unroll
-            for (int j = 5; j < 11; ++j) e5[j] = ext<MIN>(e4[j - 1], e4[j + 1]);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) e6[c] = ext<MIN>(e5[c + 5], e5[c + 7]);
+            {
+                const uint32_t l2 = from_left(e1[2]), l3 = from_left(e1[3]);
+                const uint32_t r0v = from_right(e1[0]), r1v = from_right(e1[1]);
+                e3[0] = ext3<MIN>(l2, e1[0], e1[2]);
+                e3[1] = ext3<MIN>(l3, e1[1], e1[3]);
+                e3[2] = ext3<MIN>(e1[0], e1[2], r0v);
+                e3[3] = ext3<MIN>(e1[1], e1[3], r1v);
+            }
+            {
+                const uint32_t l = from_left(e3[3]), rt = from_right(e3[0]);
+                e4[0] = ext<MIN>(l, e3[1]);
+                e4[1] = ext<MIN>(e3[0], e3[2]);
+                e4[2] = ext<MIN>(e3[1], e3[3]);
+                e4[3] = ext<MIN>(e3[2], rt);
+            }
+            {
+                const uint32_t l = from_left(e4[3]), rt = from_right(e4[0]);
+                e5[0] = ext<MIN>(l, e4[1]);
+                e5[1] = ext<MIN>(e4[0], e4[2]);
+                e5[2] = ext<MIN>(e4[1], e4[3]);
+                e5[3] = ext<MIN>(e4[2], rt);
+            }
+            {
+                const uint32_t l = from_left(e5[3]), rt = from_right(e5[0]);
+                e6[0] = ext<MIN>(l, e5[1]);
+                e6[1] = ext<MIN>(e5[0], e5[2]);
+                e6[2] = ext<MIN>(e5[1], e5[3]);
+                e6[3] = ext<MIN>(e5[2], rt);
+            }
             // fold into output row r - 12 + k, which lies dy = 6 - k rows above
             // this input row, with the disk row's half-width at |dy|
 #pragma unroll
@@ -426,9 +439,8 @@ __global__ __launch_bounds__(DK_THREADS) void k_disk13(const uint8_t *__restrict
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     auto pick = [&](int c) -> uint32_t {
-                        const int j = c + 6;
-                        return hw == 6 ? e6[c] : hw == 5 ? e5[j] : hw == 4 ? e4[j]
-                             : hw == 3 ? e3[j] : b[j];
+                        return hw == 6 ? e6[c] : hw == 5 ? e5[c] : hw == 4 ? e4[c]
+                             : hw == 3 ? e3[c] : b[c];
                     };
                     const u16x2 v = {(uint16_t)pick(2 * h), (uint16_t)pick(2 * h + 1)};
                     acc[slot][h] = MIN ? __builtin_elementwise_min(acc[slot][h], v)
@@ -439,18 +451,17 @@ __global__ __launch_bounds__(DK_THREADS) void k_disk13(const uint8_t *__restrict
             // start the slot over for output row r + 1
             const int done = (rr + 1) % 13;
             const int64_t oy = y0 + r - 12;
-            if (r >= 12 && oy < H) {
-                const int64_t ox = x0 + lx;
+            if (r >= 12 && oy < H && stores && gx < W) {
                 uint8_t *orow = out + oy * pitch;
                 const uint32_t o4 = (uint32_t)acc[done][0].x | ((uint32_t)acc[done][0].y << 8) |
                                     ((uint32_t)acc[done][1].x << 16) |
                                     ((uint32_t)acc[done][1].y << 24);
-                if (ox + 3 < W && (((uintptr_t)(orow + ox)) & 3) == 0) {
-                    *(uint32_t *)(orow + ox) = o4;
+                if (gx + 3 < W && (((uintptr_t)(orow + gx)) & 3) == 0) {
+                    *(uint32_t *)(orow + gx) = o4;
                 } else {
 #pragma unroll
                     for (int c = 0; c < 4; ++c)
-                        if (ox + c < W) orow[ox + c] = (uint8_t)(o4 >> (8 * c));
+                        if (gx + c < W) orow[gx + c] = (uint8_t)(o4 >> (8 * c));
                 }
             }
             acc[done][0] = acc[done][1] = identp;
@@ -460,15 +471,15 @@ __global__ __launch_bounds__(DK_THREADS) void k_disk13(const uint8_t *__restrict
 
 hipError_t launch_disk13(bool erode, const uint8_t *in, uint8_t *out, int64_t H, int64_t W,
                          int64_t pitch, hipStream_t s) {
-    const int64_t tx = (W + DK_TW - 1) / DK_TW, ty = (H + DK_TH - 1) / DK_TH;
+    const int64_t tx = (W + DK_OUT - 1) / DK_OUT, ty = (H + DK_TH - 1) / DK_TH;
     const int64_t n = tx * ty;
     if (n >= (1ll << 31)) return hipErrorInvalidValue;
     if (erode)
-        hipLaunchKernelGGL(k_disk13<true>, dim3((unsigned)n), dim3(DK_THREADS), 0, s, in, out, H,
-                           W, pitch, tx);
+        hipLaunchKernelGGL(k_disk13<true>, dim3((unsigned)n), dim3(64), 0, s, in, out, H, W, pitch,
+                           tx);
     else
-        hipLaunchKernelGGL(k_disk13<false>, dim3((unsigned)n), dim3(DK_THREADS), 0, s, in, out,
-                           H, W, pitch, tx);
+        hipLaunchKernelGGL(k_disk13<false>, dim3((unsigned)n), dim3(64), 0, s, in, out, H, W,
+                           pitch, tx);
     return hipGetLastError();
 }
 

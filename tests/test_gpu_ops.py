@@ -118,7 +118,8 @@ def test_rgb2gray_shapes_and_pitches(shape, pad):
 # -------------------------------------------------------- 13 x 13 disk
 
 DISK_SHAPES = [(1, 1), (1, 600), (600, 1), (5, 40), (13, 13), (63, 511), (64, 512), (65, 513),
-               (129, 1030), (200, 777)]
+               (129, 1030), (200, 777), (128, 239), (127, 240), (129, 241), (257, 480),
+               (256, 481), (300, 721)]
 
 
 @pytest.mark.parametrize("shape", DISK_SHAPES, ids=lambda s: f"{s[0]}x{s[1]}")
