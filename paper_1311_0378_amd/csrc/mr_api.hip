@@ -847,7 +847,7 @@ int mr_autotune(const mr_tile *tiles, int32_t n, mr_dtype t, int conn, void *ws,
                                   {-1, 16, 8, 1},  {-1, 16, 12, 1}, {-1, 16, 4, 16}, {-1, 16, 6, 16},
                                   {-1, 16, 8, 16}, {-1, 16, 12, 16}, {4, 16, 0, 1},  {8, 16, 0, 1},
                                   {12, 16, 0, 1},  {16, 16, 0, 1},  {24, 16, 0, 1},  {32, 16, 0, 1},
-                                  {48, 16, 0, 1},  {16, 3, 0, 1}};
+                                  {48, 16, 0, 1},  {16, 3, 0, 1},   {-1, 16, 16, 1}, {-1, 16, 20, 1}};
     hipEvent_t a = nullptr, b = nullptr;
     if ((e = hipEventCreate(&a)) != hipSuccess || (e = hipEventCreate(&b)) != hipSuccess) {
         if (a) (void)hipEventDestroy(a);
