@@ -390,8 +390,9 @@ __global__ __launch_bounds__(64) void k_disk13(const uint8_t *__restrict__ in,
             // left neighbour's last column is index 0 and the right
             // neighbour's first is index 5 where a step needs them
             uint32_t b[4];
+            b[0] = wd[rr] & 0xFFu;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) b[c] = (wd[rr] >> (8 * c)) & 0xFFu;
+            for (int c = 1; c < 4; ++c) b[c] = __builtin_amdgcn_ubfe(wd[rr], 8 * c, 8);
             uint32_t e1[4], e3[4], e4[4], e5[4], e6[4];
             {
                 const uint32_t l = from_left(b[3]), rt = from_right(b[0]);
@@ -453,9 +454,10 @@ __global__ __launch_bounds__(64) void k_disk13(const uint8_t *__restrict__ in,
             const int64_t oy = y0 + r - 12;
             if (r >= 12 && oy < H && stores && gx < W) {
                 uint8_t *orow = out + oy * pitch;
-                const uint32_t o4 = (uint32_t)acc[done][0].x | ((uint32_t)acc[done][0].y << 8) |
-                                    ((uint32_t)acc[done][1].x << 16) |
-                                    ((uint32_t)acc[done][1].y << 24);
+                // the low bytes of the four 16-bit halves, in column order
+                const uint32_t o4 = __builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, acc[done][1]),
+                                                          __builtin_bit_cast(uint32_t, acc[done][0]),
+                                                          0x06040200u);
                 if (gx + 3 < W && (((uintptr_t)(orow + gx)) & 3) == 0) {
                     *(uint32_t *)(orow + gx) = o4;
                 } else {
