@@ -349,6 +349,16 @@ __global__ __launch_bounds__(64) void k_disk13(const uint8_t *__restrict__ in,
     const int64_t y0 = ty * DK_TH;
     const int64_t gx = tx * DK_OUT - 8 + 4 * lane; // this lane's first column
     const bool whole = gx >= 0 && gx + 3 < W;
+    // A strip whose 256 columns all lie inside the image, with dword-aligned
+    // rows, takes the fast path: a row is one plain dword load per lane from
+    // the row's uniform base plus a 32-bit lane offset, with no per-lane
+    // branch, so the 13 loads of a step are in flight together. Strips at the
+    // image's left and right edges (and unaligned planes) take the general
+    // path below.
+    const bool fast =
+        ((((uintptr_t)in) | ((uintptr_t)out) | (uintptr_t)pitch) & 3) == 0 &&
+        W < (1ll << 31) && __ballot(whole) == ~0ull;
+    const uint32_t lx4 = (uint32_t)(fast ? gx : 0);
     // input row r of this wave is image row y0 - 6 + r
     auto load = [&](int r) -> uint32_t {
         const int64_t gy = y0 - 6 + r;
@@ -379,8 +389,20 @@ __global__ __launch_bounds__(64) void k_disk13(const uint8_t *__restrict__ in,
 #pragma unroll 1
     for (int r0 = 0; r0 < DK_ROWS; r0 += 13) {
         uint32_t wd[13];
+        if (fast) {
 #pragma unroll
-        for (int rr = 0; rr < 13; ++rr) wd[rr] = r0 + rr < DK_ROWS ? load(r0 + rr) : ident4;
+            for (int rr = 0; rr < 13; ++rr) {
+                // rows outside the image (and past the strip's last input
+                // row) load a clamped row and take the identity instead
+                const int64_t gy = y0 - 6 + r0 + rr;
+                const int64_t cy = gy < 0 ? 0 : (gy >= H ? H - 1 : gy);
+                const uint32_t v = *(const uint32_t *)(in + cy * pitch + lx4);
+                wd[rr] = (gy >= 0 && gy < H && r0 + rr < DK_ROWS) ? v : ident4;
+            }
+        } else {
+#pragma unroll
+            for (int rr = 0; rr < 13; ++rr) wd[rr] = r0 + rr < DK_ROWS ? load(r0 + rr) : ident4;
+        }
 #pragma unroll
         for (int rr = 0; rr < 13; ++rr) {
             const int r = r0 + rr;
@@ -452,7 +474,12 @@ __global__ __launch_bounds__(64) void k_disk13(const uint8_t *__restrict__ in,
             // start the slot over for output row r + 1
             const int done = (rr + 1) % 13;
             const int64_t oy = y0 + r - 12;
-            if (r >= 12 && oy < H && stores && gx < W) {
+            if (fast && r >= 12 && oy < H) {
+                if (stores)
+                    *(uint32_t *)(out + oy * pitch + lx4) = __builtin_amdgcn_perm(
+                        __builtin_bit_cast(uint32_t, acc[done][1]),
+                        __builtin_bit_cast(uint32_t, acc[done][0]), 0x06040200u);
+            } else if (r >= 12 && oy < H && stores && gx < W) {
                 uint8_t *orow = out + oy * pitch;
                 // the low bytes of the four 16-bit halves, in column order
                 const uint32_t o4 = __builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, acc[done][1]),
