@@ -164,6 +164,9 @@ __global__ __launch_bounds__(CT_THREADS) void k_ccl_local(const uint8_t *__restr
     }
     __syncthreads();
     // each pixel points at its tile-local root, as a global linear index
+    // (H * W < 2^31, so linear indices are 32-bit)
+    const uint32_t W32 = (uint32_t)W;
+    const uint32_t tile0 = (uint32_t)(y0 * W + x0); // the tile's first pixel
 #pragma unroll
     for (int k = 0; k < CT_H / RSTEP; ++k) {
         const int ly = ly0 + k * RSTEP;
@@ -172,9 +175,9 @@ __global__ __launch_bounds__(CT_THREADS) void k_ccl_local(const uint8_t *__restr
         uint32_t v = 0;
         if (fg[k]) {
             const uint32_t r = P[P[ly * CT_W + lx]];
-            v = (uint32_t)((y0 + r / CT_W) * W + x0 + r % CT_W) + 1u;
+            v = tile0 + (r / CT_W) * W32 + r % CT_W + 1u;
         }
-        forest[y * W + x] = v;
+        forest[tile0 + (uint32_t)ly * W32 + (uint32_t)lx] = v;
     }
 }
 
