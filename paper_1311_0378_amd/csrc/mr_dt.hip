@@ -94,15 +94,17 @@ __device__ __forceinline__ void transpose(uint32_t (&A)[DS], uint32_t (*tb)[DS +
     dt_wave_sync();
 }
 
+// One visit of tile t by the calling wave (every lane, uniform t). A tile
+// raised past `round` before its visit is left to the later round it is
+// listed for. `tb` is the wave's transpose buffer.
 template <int CONN, bool FIRST>
-__global__ __launch_bounds__(64) void k_dt_round(const uint8_t *__restrict__ img, int64_t ipitch,
-                                                 int32_t *__restrict__ dist, int64_t dpitch,
-                                                 int64_t H, int64_t W, int32_t ntx, int32_t nty,
-                                                 uint32_t *__restrict__ flags, uint32_t round,
-                                                 DtCtrl *__restrict__ ctrl) {
-    __shared__ uint32_t tb[DS][DS + 1];
+__device__ __forceinline__ void dt_visit(const uint8_t *__restrict__ img, int64_t ipitch,
+                                         int32_t *__restrict__ dist, int64_t dpitch, int64_t H,
+                                         int64_t W, int32_t ntx, int32_t nty,
+                                         uint32_t *__restrict__ flags, uint32_t round,
+                                         DtCtrl *__restrict__ ctrl, uint32_t *__restrict__ lists,
+                                         int64_t t, uint32_t (*tb)[DS + 1]) {
     const int lane = threadIdx.x;
-    const int64_t t = blockIdx.x;
     if (!FIRST && flags[t] != round) return;
     const int ty = (int)(t / ntx), tx = (int)(t - (int64_t)ty * ntx);
     const int64_t gy0 = (int64_t)ty * DI - 1, gx = (int64_t)tx * DI - 1 + lane;
@@ -294,8 +296,38 @@ __global__ __launch_bounds__(64) void k_dt_round(const uint8_t *__restrict__ img
     const int ny = ty + dy, nx = tx + dx;
     if (want && ny >= 0 && ny < nty && nx >= 0 && nx < ntx) {
         const int64_t nb = (int64_t)ny * ntx + nx;
-        if (atomicMax(flags + nb, nxt) < nxt) atomicAdd(&ctrl->marked[nxt & 1], 1u);
+        // the first mark of a tile for round nxt lists it for that round
+        if (atomicMax(flags + nb, nxt) < nxt) {
+            const int64_t n = (int64_t)ntx * nty;
+            const uint32_t slot = atomicAdd(&ctrl->marked[nxt & 1], 1u);
+            if ((int64_t)slot < n) lists[(int64_t)(nxt & 1) * n + slot] = (uint32_t)nb;
+        }
     }
+}
+
+// Round 1 visits every tile, one wave per tile. A later round visits the
+// tiles listed for it (each at most once: a tile is listed when its flag
+// first reaches the round), a fixed grid of waves walking the list, so that
+// a round with few marked tiles does not launch a wave per tile.
+template <int CONN, bool FIRST>
+__global__ __launch_bounds__(64) void k_dt_round(const uint8_t *__restrict__ img, int64_t ipitch,
+                                                 int32_t *__restrict__ dist, int64_t dpitch,
+                                                 int64_t H, int64_t W, int32_t ntx, int32_t nty,
+                                                 uint32_t *__restrict__ flags, uint32_t round,
+                                                 DtCtrl *__restrict__ ctrl,
+                                                 uint32_t *__restrict__ lists) {
+    __shared__ uint32_t tb[DS][DS + 1];
+    if (FIRST) {
+        dt_visit<CONN, true>(img, ipitch, dist, dpitch, H, W, ntx, nty, flags, round, ctrl, lists,
+                             (int64_t)blockIdx.x, tb);
+        return;
+    }
+    const int64_t n = (int64_t)ntx * nty;
+    const int64_t cnt = std::min<int64_t>(ctrl->marked[round & 1], n);
+    const uint32_t *list = lists + (int64_t)(round & 1) * n;
+    for (int64_t i = blockIdx.x; i < cnt; i += gridDim.x)
+        dt_visit<CONN, false>(img, ipitch, dist, dpitch, H, W, ntx, nty, flags, round, ctrl,
+                              lists, (int64_t)list[i], tb);
 }
 
 __global__ void k_dt_clear(DtCtrl *c, uint32_t *flags, int64_t n) {
@@ -319,7 +351,7 @@ __global__ void k_dt_fill(int32_t *dist, int64_t dpitch, int64_t H, int64_t W, i
 }
 
 struct DtLayout {
-    size_t ctrl = 0, flags = 0, total = 0;
+    size_t ctrl = 0, flags = 0, lists = 0, total = 0;
     int64_t ntx = 0, nty = 0;
 };
 
@@ -329,29 +361,33 @@ DtLayout dt_layout(int64_t H, int64_t W) {
     L.nty = (H + DI - 1) / DI;
     L.ctrl = 0;
     L.flags = up256(sizeof(DtCtrl));
-    L.total = L.flags + up256((size_t)(L.ntx * L.nty) * 4);
+    L.lists = L.flags + up256((size_t)(L.ntx * L.nty) * 4);
+    L.total = L.lists + up256((size_t)(L.ntx * L.nty) * 8); // one list per round parity
     return L;
 }
 
 hipError_t dt_round(int conn, bool first, const uint8_t *img, int64_t ipitch, int32_t *dist,
                     int64_t dpitch, int64_t H, int64_t W, const DtLayout &L, uint32_t *flags,
-                    uint32_t round, DtCtrl *ctrl, hipStream_t s) {
+                    uint32_t *lists, uint32_t round, DtCtrl *ctrl, hipStream_t s) {
     const unsigned n = (unsigned)(L.ntx * L.nty);
+    // later rounds: a fixed grid walks the round's list (the count is on the
+    // device); 4096 waves cover the lists of the late rounds in one pass
+    const unsigned g = first ? n : std::min(n, 4096u);
     const int32_t ntx = (int32_t)L.ntx, nty = (int32_t)L.nty;
     if (conn == 8) {
         if (first)
-            hipLaunchKernelGGL((k_dt_round<8, true>), dim3(n), dim3(64), 0, s, img, ipitch, dist,
-                               dpitch, H, W, ntx, nty, flags, round, ctrl);
+            hipLaunchKernelGGL((k_dt_round<8, true>), dim3(g), dim3(64), 0, s, img, ipitch, dist,
+                               dpitch, H, W, ntx, nty, flags, round, ctrl, lists);
         else
-            hipLaunchKernelGGL((k_dt_round<8, false>), dim3(n), dim3(64), 0, s, img, ipitch, dist,
-                               dpitch, H, W, ntx, nty, flags, round, ctrl);
+            hipLaunchKernelGGL((k_dt_round<8, false>), dim3(g), dim3(64), 0, s, img, ipitch, dist,
+                               dpitch, H, W, ntx, nty, flags, round, ctrl, lists);
     } else {
         if (first)
-            hipLaunchKernelGGL((k_dt_round<4, true>), dim3(n), dim3(64), 0, s, img, ipitch, dist,
-                               dpitch, H, W, ntx, nty, flags, round, ctrl);
+            hipLaunchKernelGGL((k_dt_round<4, true>), dim3(g), dim3(64), 0, s, img, ipitch, dist,
+                               dpitch, H, W, ntx, nty, flags, round, ctrl, lists);
         else
-            hipLaunchKernelGGL((k_dt_round<4, false>), dim3(n), dim3(64), 0, s, img, ipitch, dist,
-                               dpitch, H, W, ntx, nty, flags, round, ctrl);
+            hipLaunchKernelGGL((k_dt_round<4, false>), dim3(g), dim3(64), 0, s, img, ipitch, dist,
+                               dpitch, H, W, ntx, nty, flags, round, ctrl, lists);
     }
     return hipGetLastError();
 }
@@ -389,6 +425,7 @@ int mr_distance_transform(const void *img, void *dist, int64_t H, int64_t W, int
     hipStream_t s = (hipStream_t)stream;
     DtCtrl *ctrl = (DtCtrl *)((char *)ws + L.ctrl);
     uint32_t *flags = (uint32_t *)((char *)ws + L.flags);
+    uint32_t *lists = (uint32_t *)((char *)ws + L.lists);
     const uint8_t *im = (const uint8_t *)img;
     int32_t *d = (int32_t *)dist;
     const int64_t n = L.ntx * L.nty;
@@ -399,7 +436,7 @@ int mr_distance_transform(const void *img, void *dist, int64_t H, int64_t W, int
     // round 1 builds every tile from the image; later rounds visit the tiles
     // marked for them, DT_BATCH rounds per host poll of the marks
     uint32_t round = 1;
-    if ((e = dt_round(conn, true, im, pitch, d, dist_pitch, H, W, L, flags, round, ctrl, s)) !=
+    if ((e = dt_round(conn, true, im, pitch, d, dist_pitch, H, W, L, flags, lists, round, ctrl, s)) !=
         hipSuccess)
         return dhip(e, "round");
     uint32_t h_marked = 0, h_has_bg = 0;
@@ -421,8 +458,8 @@ int mr_distance_transform(const void *img, void *dist, int64_t H, int64_t W, int
             ++round;
             // the slot that will count this round's marks held round - 1's
             hipLaunchKernelGGL(k_dt_reset_mark, dim3(1), dim3(1), 0, s, ctrl, (round + 1) & 1);
-            if ((e = dt_round(conn, false, im, pitch, d, dist_pitch, H, W, L, flags, round, ctrl,
-                              s)) != hipSuccess)
+            if ((e = dt_round(conn, false, im, pitch, d, dist_pitch, H, W, L, flags, lists, round,
+                              ctrl, s)) != hipSuccess)
                 return dhip(e, "round");
         }
     }
