@@ -371,8 +371,8 @@ hipError_t dt_round(int conn, bool first, const uint8_t *img, int64_t ipitch, in
                     uint32_t *lists, uint32_t round, DtCtrl *ctrl, hipStream_t s) {
     const unsigned n = (unsigned)(L.ntx * L.nty);
     // later rounds: a fixed grid walks the round's list (the count is on the
-    // device); 4096 waves cover the lists of the late rounds in one pass
-    const unsigned g = first ? n : std::min(n, 4096u);
+    // device); 8192 waves (measured against 2048 to 32768)
+    const unsigned g = first ? n : std::min(n, 8192u);
     const int32_t ntx = (int32_t)L.ntx, nty = (int32_t)L.nty;
     if (conn == 8) {
         if (first)
